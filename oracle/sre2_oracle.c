@@ -1,0 +1,306 @@
+/*
+ * sre2_oracle.c - plain FP64 CPU oracle for the second-order stabilizer
+ * Renyi entropy M2 (Huang, Li, Lee, Zhong, arXiv:2512.24685).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the GPU library, and the GPU library never calls it.
+ *
+ * Everything is computed in IEEE double precision with plain scalar loops,
+ * no blocking, no fusion and no reordering beyond what each definition says.
+ * Build with plain -O2 (no -ffast-math).
+ *
+ * Quantities (qubit j = bit j of the basis index, LSB = qubit 0):
+ *   Pauli string      P = X^x Z^z, x,z in Z_2^N           (main text, bit-string
+ *                                                           encoding of Paulis)
+ *   expectation       <psi|X^x Z^z|psi>
+ *                       = sum_t (-1)^{z.t} conj(psi[t^x]) psi[t]   (Eq. Pauli_expect)
+ *   SRE, alpha = 2    M2 = -log2( (1/d) sum_{x,z} |<X^x Z^z>|^4 ), d = 2^N  (Eq. 1)
+ *   XOR-FWHT form     sum_{x,z} |<X^x Z^z>|^4 = sum_x sum_z |FWHT_k(G_x)(z)|^4,
+ *                     G_x[k] = conj(psi[k^x]) psi[k]        (Eq. final1, Algorithm 1)
+ *   FWHT              unnormalised Walsh-Hadamard transform, N butterfly
+ *                     stages (a,b) -> (a+b, a-b)            (SI, fast WHT section)
+ *
+ * Reading adopted for unnormalised input: with n = sum_t |psi[t]|^2 the
+ * oracle returns M2 = -log2( S / (2^N n^4) ), which is the paper's value when
+ * n = 1 and is invariant under psi -> c psi.
+ *
+ * Arrays are interleaved (re, im) doubles of length 2 * 2^N.  Every function
+ * returns 0 on success and a negative value on a bad argument.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_MAX_N 30
+
+static int popcount_parity(uint64_t v)
+{
+    /* parity of the binary inner product z.t = sum_j z_j t_j mod 2 */
+    int p = 0;
+    while (v) {
+        p ^= (int)(v & 1u);
+        v >>= 1;
+    }
+    return p;
+}
+
+/* Neumaier-compensated running sum, ascending index order. */
+static double compensated_sum(const double *v, int64_t n)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = s + v[i];
+        if (fabs(s) >= fabs(v[i]))
+            c += (s - t) + v[i];
+        else
+            c += (v[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int sre2o_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* <psi| X^x Z^z |psi> by the direct sum over t (Eq. Pauli_expect). */
+int sre2o_pauli_expect(const double *psi, int N, uint64_t x, uint64_t z,
+                       double *out_re, double *out_im)
+{
+    if (!psi || !out_re || !out_im || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const uint64_t d = (uint64_t)1 << N;
+    if (x >= d || z >= d)
+        return -1;
+    double re = 0.0, im = 0.0;
+    for (uint64_t t = 0; t < d; ++t) {
+        const uint64_t u = t ^ x;
+        /* conj(psi[u]) * psi[t] */
+        const double ar = psi[2 * u], ai = -psi[2 * u + 1];
+        const double br = psi[2 * t], bi = psi[2 * t + 1];
+        const double pr = ar * br - ai * bi;
+        const double pi = ar * bi + ai * br;
+        if (popcount_parity(z & t)) {
+            re -= pr;
+            im -= pi;
+        } else {
+            re += pr;
+            im += pi;
+        }
+    }
+    *out_re = re;
+    *out_im = im;
+    return 0;
+}
+
+/* Brute force: sum over all 4^N Pauli strings of |<P>|^4, O(8^N).
+ * Per-shift sums are kept and added in ascending shift order. */
+int sre2o_brute_sum(const double *psi, int N, int nthreads, double *out_sum)
+{
+    if (!psi || !out_sum || N < 0 || N > 12)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *per_x = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!per_x)
+        return -2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t x = 0; x < d; ++x) {
+        double *q = (double *)malloc(sizeof(double) * (size_t)d);
+        for (int64_t z = 0; z < d; ++z) {
+            double re, im;
+            sre2o_pauli_expect(psi, N, (uint64_t)x, (uint64_t)z, &re, &im);
+            const double m = re * re + im * im;
+            q[z] = m * m;
+        }
+        per_x[x] = compensated_sum(q, d);
+        free(q);
+    }
+    *out_sum = compensated_sum(per_x, d);
+    free(per_x);
+    return 0;
+}
+
+/* In-place unnormalised FWHT of an interleaved complex array of length 2^N.
+ * Stage h = 1, 2, 4, ...: within each block of 2h, (u, v) -> (u + v, u - v)
+ * (SI, fast WHT section: H_{2^N} = [[H, H], [H, -H]]). */
+int sre2o_fwht(double *a, int N)
+{
+    if (!a || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    for (int64_t h = 1; h < d; h *= 2) {
+        for (int64_t i = 0; i < d; i += 2 * h) {
+            for (int64_t j = i; j < i + h; ++j) {
+                const double ur = a[2 * j], ui = a[2 * j + 1];
+                const double vr = a[2 * (j + h)], vi = a[2 * (j + h) + 1];
+                a[2 * j] = ur + vr;
+                a[2 * j + 1] = ui + vi;
+                a[2 * (j + h)] = ur - vr;
+                a[2 * (j + h) + 1] = ui - vi;
+            }
+        }
+    }
+    return 0;
+}
+
+/* W_x = FWHT_k( conj(psi[k^x]) psi[k] ), one shift (Algorithm 1, loop body). */
+int sre2o_shift_transform(const double *psi, int N, uint64_t x, double *W)
+{
+    if (!psi || !W || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const uint64_t d = (uint64_t)1 << N;
+    if (x >= d)
+        return -1;
+    for (uint64_t k = 0; k < d; ++k) {
+        const uint64_t u = k ^ x;
+        const double ar = psi[2 * u], ai = -psi[2 * u + 1];
+        const double br = psi[2 * k], bi = psi[2 * k + 1];
+        W[2 * k] = ar * br - ai * bi;
+        W[2 * k + 1] = ar * bi + ai * br;
+    }
+    return sre2o_fwht(W, N);
+}
+
+static double shift_partial(const double *psi, int N, uint64_t x, double *W, double *q)
+{
+    const int64_t d = (int64_t)1 << N;
+    sre2o_shift_transform(psi, N, x, W);
+    for (int64_t z = 0; z < d; ++z) {
+        const double m = W[2 * z] * W[2 * z] + W[2 * z + 1] * W[2 * z + 1];
+        q[z] = m * m;
+    }
+    return compensated_sum(q, d);
+}
+
+/* S_x = sum_z |W_x(z)|^4 for each shift in xs[0..nx). */
+int sre2o_shift_partials(const double *psi, int N, const int64_t *xs, int64_t nx,
+                         int nthreads, double *S)
+{
+    if (!psi || !S || (!xs && nx > 0) || nx < 0 || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    for (int64_t i = 0; i < nx; ++i)
+        if (xs[i] < 0 || xs[i] >= d)
+            return -1;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel
+    {
+        double *W = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        double *q = (double *)malloc(sizeof(double) * (size_t)d);
+        if (!W || !q) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t i = 0; i < nx; ++i)
+                S[i] = shift_partial(psi, N, (uint64_t)xs[i], W, q);
+        }
+        free(W);
+        free(q);
+    }
+    return err;
+}
+
+/* S_x for every shift x = 0 .. 2^N - 1. */
+int sre2o_all_partials(const double *psi, int N, int nthreads, double *S)
+{
+    if (!psi || !S || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel
+    {
+        double *W = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        double *q = (double *)malloc(sizeof(double) * (size_t)d);
+        if (!W || !q) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t x = 0; x < d; ++x)
+                S[x] = shift_partial(psi, N, (uint64_t)x, W, q);
+        }
+        free(W);
+        free(q);
+    }
+    return err;
+}
+
+int sre2o_sum_ascending(const double *v, int64_t n, double *out)
+{
+    if ((!v && n > 0) || !out || n < 0)
+        return -1;
+    *out = compensated_sum(v, n);
+    return 0;
+}
+
+/* n = sum_t |psi[t]|^2 (ascending t, compensated). */
+int sre2o_norm2(const double *psi, int N, double *out)
+{
+    if (!psi || !out || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *q = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!q)
+        return -2;
+    for (int64_t t = 0; t < d; ++t)
+        q[t] = psi[2 * t] * psi[2 * t] + psi[2 * t + 1] * psi[2 * t + 1];
+    *out = compensated_sum(q, d);
+    free(q);
+    return 0;
+}
+
+/* M2 by Algorithm 1: all shifts, FWHT per shift, ascending compensated sum,
+ * then M2 = -log2( S / (2^N n^4) ).  Optionally returns S and n. */
+int sre2o_m2(const double *psi, int N, int nthreads, double *m2, double *total,
+             double *norm2)
+{
+    if (!psi || !m2 || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *S = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!S)
+        return -2;
+    int rc = sre2o_all_partials(psi, N, nthreads, S);
+    if (rc) {
+        free(S);
+        return rc;
+    }
+    double s = compensated_sum(S, d);
+    free(S);
+    double n;
+    rc = sre2o_norm2(psi, N, &n);
+    if (rc)
+        return rc;
+    if (!(n > 0.0) || !isfinite(n))
+        return -3;
+    *m2 = -log2(s / (ldexp(1.0, N) * n * n * n * n));
+    if (total)
+        *total = s;
+    if (norm2)
+        *norm2 = n;
+    return 0;
+}

@@ -1,0 +1,208 @@
+"""Pins of the FP64 CPU oracle against things fixed by the paper and by the
+mathematics, not by the oracle itself (CPU only).
+
+* Textbook Pauli matrices: W_x(z) equals <psi| (X^x1 Z^z1) (x) ... |psi> built
+  from dense 2x2 matrices and Kronecker products (N <= 5), element by element.
+* Brute force over all Pauli strings (the definition, Eq. 1) equals the
+  XOR-FWHT result (Eq. final1), N <= 7.
+* FWHT equals the Sylvester Hadamard matrix of scipy; WHT identities of the
+  SI (involution, XOR-convolution theorem, conjugation, Parseval).
+* Closed forms: stabilizer states give 0 (faithfulness), |T>^N gives
+  N log2(4/3) (Eq. 1 on one qubit + additivity), graph+T on m qubits gives
+  m log2(4/3) (Clifford invariance), Ising snapshots vanish at Clifford angles
+  and obey their period / reflection symmetries.
+* Invariants: additivity, Clifford invariance, scale invariance, purity,
+  per-shift Parseval, bounds, the real / imaginary pattern of W, Haar average.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as W
+
+LOG43 = np.log2(4.0 / 3.0)
+
+_I = np.eye(2, dtype=np.complex128)
+_X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def _pauli_matrix(N, x, z):
+    """X^x Z^z as a dense matrix; qubit j = bit j, so qubit N-1 is the
+    leftmost Kronecker factor."""
+    M = np.ones((1, 1), dtype=np.complex128)
+    for j in reversed(range(N)):
+        f = _I
+        if (x >> j) & 1:
+            f = f @ _X
+        if (z >> j) & 1:
+            f = f @ _Z
+        M = np.kron(M, f)
+    return M
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_transform_equals_textbook_pauli_expectations(oracle_mod, N):
+    psi = W.haar(N, 100 + N)
+    d = 1 << N
+    for x in range(d):
+        Wx = oracle_mod.shift_transform(psi, x)
+        for z in range(d):
+            ref = np.vdot(psi, _pauli_matrix(N, x, z) @ psi)
+            assert abs(Wx[z] - ref) < 1e-13, (x, z)
+    # the direct-sum expectation agrees as well
+    for x, z in [(0, 0), (1, d - 1), (d - 1, 1), (d // 2, d // 2 + 1 if d > 2 else 0)]:
+        ref = np.vdot(psi, _pauli_matrix(N, x, z) @ psi)
+        assert abs(oracle_mod.pauli_expect(psi, x, z) - ref) < 1e-13
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_brute_force_equals_xor_fwht(oracle_mod, N):
+    psi = W.haar(N, 200 + N)
+    S_fwht, n = oracle_mod.total(psi)
+    S_brute = oracle_mod.brute_sum(psi)
+    assert abs(S_fwht - S_brute) <= 1e-13 * S_brute
+    assert abs(oracle_mod.m2(psi) - oracle_mod.brute_m2(psi)) < 1e-12
+
+
+def test_brute_force_matches_dense_definition(oracle_mod):
+    """Eq. 1 with alpha=2 over all 4^N Pauli matrices, N=3."""
+    N = 3
+    psi = W.haar(N, 5)
+    s = 0.0
+    for x, z in itertools.product(range(8), range(8)):
+        s += abs(np.vdot(psi, _pauli_matrix(N, x, z) @ psi)) ** 4
+    assert abs(oracle_mod.brute_sum(psi) - s) < 1e-13 * s
+
+
+@pytest.mark.parametrize("N", [0, 1, 3, 6, 10])
+def test_fwht_equals_sylvester_hadamard(oracle_mod, N):
+    rng = np.random.default_rng(N)
+    a = rng.standard_normal(1 << N) + 1j * rng.standard_normal(1 << N)
+    H = scipy.linalg.hadamard(1 << N).astype(np.float64)
+    assert np.allclose(oracle_mod.fwht(a), H @ a, atol=1e-11, rtol=0)
+
+
+@pytest.mark.parametrize("N", [2, 5, 9])
+def test_wht_identities(oracle_mod, N):
+    rng = np.random.default_rng(10 + N)
+    d = 1 << N
+    f = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    g = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    Ff, Fg = oracle_mod.fwht(f), oracle_mod.fwht(g)
+    # involution: FWHT(FWHT f) = 2^N f
+    assert np.allclose(oracle_mod.fwht(Ff), d * f, atol=1e-10)
+    # XOR convolution theorem (unnormalised form): FWHT(f *xor g) = FWHT f . FWHT g
+    idx = np.arange(d)
+    conv = np.array([np.sum(f * g[x ^ idx]) for x in range(d)])
+    assert np.allclose(oracle_mod.fwht(conv), Ff * Fg, atol=1e-9)
+    # conjugation
+    assert np.allclose(oracle_mod.fwht(np.conj(f)), np.conj(Ff), atol=1e-12)
+    # Parseval (unnormalised): sum |FWHT f|^2 = 2^N sum |f|^2
+    assert abs(np.sum(abs(Ff) ** 2) - d * np.sum(abs(f) ** 2)) < 1e-10 * d * np.sum(abs(f) ** 2)
+
+
+def test_single_qubit_t_state_pauli_values(oracle_mod):
+    """|T>: <I>=1, <X>=<Y>=1/sqrt2, <Z>=0, so sum |<P>|^4 = 3/2."""
+    psi = W.t_product(1)
+    vals = {(x, z): oracle_mod.pauli_expect(psi, x, z) for x in (0, 1) for z in (0, 1)}
+    assert abs(vals[(0, 0)] - 1) < 1e-15
+    assert abs(abs(vals[(1, 0)]) - 2 ** -0.5) < 1e-15
+    assert abs(abs(vals[(1, 1)]) - 2 ** -0.5) < 1e-15
+    assert abs(vals[(0, 1)]) < 1e-15
+    assert abs(oracle_mod.brute_sum(psi) - 1.5) < 1e-14
+
+
+@pytest.mark.parametrize("N", list(range(1, 11)))
+def test_t_product_closed_form(oracle_mod, N):
+    assert abs(oracle_mod.m2(W.t_product(N)) - N * LOG43) < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 9, 10, 12])
+def test_stabilizer_states_vanish(oracle_mod, N):
+    for psi in (W.computational_basis(N, (1 << N) - 1), W.plus_state(N),
+                W.graph(N, 300 + N)):
+        assert abs(oracle_mod.m2(psi)) < 1e-12
+
+
+@pytest.mark.parametrize("N,m", [(7, 0), (7, 1), (7, 3), (7, 6), (9, 9), (10, 4)])
+def test_graph_t_closed_form(oracle_mod, N, m):
+    psi, _ = W.graph_t(N, m, 400 + 10 * N + m)
+    assert abs(oracle_mod.m2(psi) - m * LOG43) < 1e-12
+
+
+def test_ising_snapshot_clifford_points_and_symmetries(oracle_mod):
+    N = 7
+    J = W.ising_couplings(N, 17)
+    h = W.ising_energy(N, J)
+    m = {t: oracle_mod.m2(W.ising_snapshot(N, t, J, energy=h)) for t in range(0, 64)}
+    for t in (0, 16, 32, 48):
+        assert abs(m[t]) < 1e-12
+    for t in range(1, 32):
+        assert abs(m[t] - m[t + 32]) < 1e-11
+        assert abs(m[t] - m[32 - t]) < 1e-11
+    assert max(m.values()) > 0.5  # non-trivial away from Clifford angles
+
+
+def test_additivity(oracle_mod):
+    a, b = W.haar(3, 1), W.haar(4, 2)
+    ab = np.kron(a, b)
+    assert abs(oracle_mod.m2(ab) - oracle_mod.m2(a) - oracle_mod.m2(b)) < 1e-12
+
+
+def test_clifford_invariance(oracle_mod):
+    psi = W.haar(6, 3)
+    phi = W.apply_random_clifford(psi, seed=4, layers=5)
+    assert abs(np.linalg.norm(phi) - 1) < 1e-12
+    assert abs(oracle_mod.m2(phi) - oracle_mod.m2(psi)) < 1e-12
+
+
+def test_scale_invariance(oracle_mod):
+    psi = W.haar(8, 9)
+    assert abs(oracle_mod.m2(psi * (0.37 - 1.1j)) - oracle_mod.m2(psi)) < 1e-12
+
+
+def test_purity_parseval_hermiticity_bounds(oracle_mod):
+    N = 6
+    d = 1 << N
+    psi = W.haar(N, 11) * 1.7  # unnormalised on purpose
+    n = np.sum(abs(psi) ** 2)
+    total2 = 0.0
+    for x in range(d):
+        Wx = oracle_mod.shift_transform(psi, x)
+        f = np.conj(psi[np.arange(d) ^ x]) * psi
+        # per-shift Parseval
+        assert abs(np.sum(abs(Wx) ** 2) - d * np.sum(abs(f) ** 2)) < 1e-11 * d
+        total2 += np.sum(abs(Wx) ** 2)
+        # W is real for even popcount(x & z), imaginary for odd
+        par = np.array([bin(x & z).count("1") & 1 for z in range(d)])
+        assert np.all(abs(Wx.imag[par == 0]) < 1e-13)
+        assert np.all(abs(Wx.real[par == 1]) < 1e-13)
+        assert np.all(abs(Wx) <= n * (1 + 1e-13))
+        if x == 0:
+            assert abs(Wx[0] - n) < 1e-13
+    # purity: sum_{x,z} |W|^2 = 2^N n^2
+    assert abs(total2 - d * n * n) < 1e-11 * d * n * n
+    m = oracle_mod.m2(psi)
+    assert 0.0 <= m <= N
+
+
+def test_haar_average_law(oracle_mod):
+    """Fig. 1(b): Haar average close to log2(2^N + 3) - 2 (statistical)."""
+    N = 10
+    vals = [oracle_mod.m2(W.haar(N, 500 + i)) for i in range(4)]
+    assert abs(np.mean(vals) - (np.log2(2 ** N + 3) - 2)) < 0.02
+
+
+def test_partials_match_full_and_sum(oracle_mod):
+    psi = W.haar(9, 12)
+    S_all = oracle_mod.partials(psi)
+    xs = [0, 5, 511, 256]
+    assert np.array_equal(oracle_mod.partials(psi, xs), S_all[xs])
+    S, n = oracle_mod.total(psi)
+    assert abs(oracle_mod.sum_ascending(S_all) - S) <= 1e-15 * S
+    # S_0 = sum_z |FWHT(|psi|^2)(z)|^4
+    F = oracle_mod.fwht(abs(psi) ** 2)
+    assert abs(S_all[0] - np.sum(abs(F) ** 4)) < 1e-13 * S_all[0]

@@ -1,0 +1,27 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This package holds no part of the method's arithmetic: it only builds state
+vectors (and request streams) of the shapes the paper and its benchmark
+configurations use.  Both the CPU oracle and the GPU path consume its output;
+neither is imported from here.
+"""
+from .states import (  # noqa: F401
+    BASE_SEED,
+    config_seed,
+    haar,
+    t_product,
+    graph,
+    graph_t,
+    ising_couplings,
+    ising_snapshot,
+    computational_basis,
+    plus_state,
+    apply_random_clifford,
+    to_dtype,
+    config_inputs,
+    serving_requests,
+    build_request,
+    ising_energy,
+    snapshot_couplings,
+    random_adjacency,
+)

@@ -1,0 +1,255 @@
+"""Seeded state-vector generators.
+
+Conventions
+-----------
+* A state on N qubits is a length-2^N complex vector indexed by the integer
+  encoding of the computational bit string; qubit j is bit j of the index
+  (least significant bit = qubit 0).  The paper leaves the endianness open;
+  M2 does not depend on it, since permuting qubits is a Clifford operation.
+* Every generator builds the state in float64 / complex128, normalises it in
+  float64, and only then casts (``to_dtype``).  The oracle receives exactly the
+  cast bytes, upcast to complex128.
+* Random draws use ``numpy.random.default_rng`` (PCG64) with explicit seeds.
+  ``config_seed(i)`` = 2512_24685 + i is the seed of benchmark configuration i.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 2512_24685
+
+
+def config_seed(index: int) -> int:
+    return BASE_SEED + int(index)
+
+
+def _indices(N: int) -> np.ndarray:
+    return np.arange(1 << N, dtype=np.uint64)
+
+
+def _bit(k: np.ndarray, j: int) -> np.ndarray:
+    return ((k >> np.uint64(j)) & np.uint64(1)).astype(np.int64)
+
+
+def to_dtype(psi: np.ndarray, dtype) -> np.ndarray:
+    """Cast a complex128 state to complex64 or complex128 (contiguous)."""
+    return np.ascontiguousarray(psi.astype(np.dtype(dtype)))
+
+
+def haar(N: int, seed: int, dtype=np.complex128) -> np.ndarray:
+    """Haar-random pure state: i.i.d. standard complex Gaussian amplitudes,
+    normalised (the paper's benchmark workload)."""
+    rng = np.random.default_rng(seed)
+    d = 1 << N
+    psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    psi /= np.sqrt(np.sum(np.abs(psi) ** 2))
+    return to_dtype(psi, dtype)
+
+
+def computational_basis(N: int, index: int = 0, dtype=np.complex128) -> np.ndarray:
+    psi = np.zeros(1 << N, dtype=np.complex128)
+    psi[index] = 1.0
+    return to_dtype(psi, dtype)
+
+
+def plus_state(N: int, dtype=np.complex128) -> np.ndarray:
+    psi = np.full(1 << N, 2.0 ** (-N / 2), dtype=np.complex128)
+    return to_dtype(psi, dtype)
+
+
+def t_product(N: int, dtype=np.complex128) -> np.ndarray:
+    """|T>^{(x)N} with |T> = (|0> + e^{i pi/4}|1>)/sqrt(2):
+    psi(k) = 2^{-N/2} exp(i pi/4 * popcount(k))."""
+    k = _indices(N)
+    pc = np.bitwise_count(k).astype(np.float64)
+    psi = np.exp(1j * np.pi / 4 * pc) * 2.0 ** (-N / 2)
+    return to_dtype(psi, dtype)
+
+
+def _graph_parity(N: int, adj: np.ndarray) -> np.ndarray:
+    """sum_{i<j} A_ij k_i k_j mod 2 for every k (A strictly upper triangular)."""
+    k = _indices(N)
+    par = np.zeros(1 << N, dtype=np.int64)
+    for i in range(N):
+        mask = 0
+        for j in range(i + 1, N):
+            if adj[i, j]:
+                mask |= 1 << j
+        if mask == 0:
+            continue
+        cnt = np.bitwise_count(k & np.uint64(mask)).astype(np.int64)
+        par ^= _bit(k, i) & (cnt & 1)
+    return par
+
+
+def random_adjacency(N: int, rng: np.random.Generator, p: float = 0.5) -> np.ndarray:
+    """Erdos-Renyi adjacency: A_ij ~ Bernoulli(p) for i<j, drawn row-major."""
+    adj = np.zeros((N, N), dtype=bool)
+    for i in range(N):
+        for j in range(i + 1, N):
+            adj[i, j] = rng.random() < p
+    return adj
+
+
+def graph(N: int, seed: int, p: float = 0.5, dtype=np.complex128) -> np.ndarray:
+    """Random graph state psi(k) = (-1)^{sum_{i<j} A_ij k_i k_j} / 2^{N/2}."""
+    rng = np.random.default_rng(seed)
+    adj = random_adjacency(N, rng, p)
+    par = _graph_parity(N, adj)
+    psi = (1.0 - 2.0 * par) * 2.0 ** (-N / 2)
+    return to_dtype(psi.astype(np.complex128), dtype)
+
+
+def graph_t(N: int, m: int, seed: int, p: float = 0.5, dtype=np.complex128):
+    """Graph state with a diagonal T phase exp(i pi/4 k_j) on m random qubits:
+    the CZ network applied to |T>^{(x)m} (x) |+>^{(x)(N-m)} (up to a qubit
+    relabelling).  Returns (psi, subset)."""
+    rng = np.random.default_rng(seed)
+    adj = random_adjacency(N, rng, p)
+    subset = np.sort(rng.choice(N, size=m, replace=False)) if m > 0 else np.zeros(0, int)
+    par = _graph_parity(N, adj)
+    k = _indices(N)
+    tcount = np.zeros(1 << N, dtype=np.float64)
+    for j in subset:
+        tcount += _bit(k, int(j))
+    psi = (1.0 - 2.0 * par) * np.exp(1j * np.pi / 4 * tcount) * 2.0 ** (-N / 2)
+    return to_dtype(psi, dtype), subset
+
+
+def ising_couplings(N: int, seed: int) -> np.ndarray:
+    """All-to-all couplings J_ij uniform on {-1, +1} for i<j (row-major draws)."""
+    rng = np.random.default_rng(seed)
+    J = np.zeros((N, N), dtype=np.int64)
+    for i in range(N):
+        for j in range(i + 1, N):
+            J[i, j] = 1 if rng.random() < 0.5 else -1
+    return J
+
+
+def _ising_energy(N: int, J: np.ndarray) -> np.ndarray:
+    """h(k) = sum_{i<j} J_ij s_i s_j with s_i = 1 - 2 k_i (exact integers)."""
+    k = _indices(N)
+    h = np.zeros(1 << N, dtype=np.int64)
+    bits = [_bit(k, i) for i in range(N)]
+    for i in range(N):
+        for j in range(i + 1, N):
+            if J[i, j]:
+                h += J[i, j] * (1 - 2 * (bits[i] ^ bits[j]))
+    return h
+
+
+def ising_snapshot(N: int, t: int, J: np.ndarray, steps: int = 64,
+                   dtype=np.complex128, energy: np.ndarray | None = None) -> np.ndarray:
+    """psi_t = diag(exp(i theta_t h(k))) H^{(x)N}|0>, theta_t = pi t / steps."""
+    h = _ising_energy(N, J) if energy is None else energy
+    theta = np.pi * t / steps
+    psi = np.exp(1j * theta * h.astype(np.float64)) * 2.0 ** (-N / 2)
+    return to_dtype(psi, dtype)
+
+
+def ising_energy(N: int, J: np.ndarray) -> np.ndarray:
+    return _ising_energy(N, J)
+
+
+# ---------------------------------------------------------------------------
+# Clifford gates on state vectors (for invariance checks of the inputs).
+# ---------------------------------------------------------------------------
+
+def _apply_1q(psi: np.ndarray, q: int, U: np.ndarray) -> np.ndarray:
+    N = int(np.log2(psi.size))
+    t = psi.reshape((2,) * N)            # axis 0 = most significant qubit
+    ax = N - 1 - q
+    t = np.moveaxis(np.tensordot(U, t, axes=([1], [ax])), 0, ax)
+    return np.ascontiguousarray(t.reshape(-1))
+
+
+def _apply_cz(psi: np.ndarray, a: int, b: int) -> np.ndarray:
+    N = int(np.log2(psi.size))
+    k = _indices(N)
+    sign = 1 - 2 * (_bit(k, a) & _bit(k, b))
+    return psi * sign
+
+
+_H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+_S = np.array([[1, 0], [0, 1j]], dtype=np.complex128)
+
+
+def apply_random_clifford(psi: np.ndarray, seed: int, layers: int = 4) -> np.ndarray:
+    """Apply `layers` random layers of H, S and CZ gates (complex128)."""
+    rng = np.random.default_rng(seed)
+    psi = np.asarray(psi, dtype=np.complex128).copy()
+    N = int(np.log2(psi.size))
+    for _ in range(layers):
+        for q in range(N):
+            r = rng.integers(3)
+            if r == 0:
+                psi = _apply_1q(psi, q, _H)
+            elif r == 1:
+                psi = _apply_1q(psi, q, _S)
+        perm = rng.permutation(N)
+        for i in range(0, N - 1, 2):
+            psi = _apply_cz(psi, int(perm[i]), int(perm[i + 1]))
+    return psi
+
+
+# ---------------------------------------------------------------------------
+# Benchmark configurations as concrete inputs.
+# ---------------------------------------------------------------------------
+
+def config_inputs(index: int):
+    """Inputs of benchmark configuration `index` (1-based) as a list of
+    (name, psi, expected_closed_form_or_None).  Configuration 4 (serving) is
+    produced by `serving_requests`."""
+    seed = config_seed(index)
+    out = []
+    if index == 1:
+        out.append(("haar10", haar(10, seed), None))
+        out.append(("t10", t_product(10), 10 * np.log2(4.0 / 3.0)))
+        out.append(("graph10", graph(10, seed + 100), 0.0))
+    elif index == 2:
+        rng = np.random.default_rng(seed)
+        for i in range(32):
+            out.append((f"haar16_{i}", haar(16, seed * 1000 + i, np.complex64), None))
+        for i in range(8):
+            m = int(rng.integers(1, 9))
+            psi, _ = graph_t(16, m, seed * 1000 + 500 + i, dtype=np.complex64)
+            out.append((f"graphT16_{i}_m{m}", psi, m * np.log2(4.0 / 3.0)))
+    elif index == 3:
+        out.append(("haar20", haar(20, seed, np.complex64), None))
+        psi, _ = graph_t(20, 10, seed + 1, dtype=np.complex64)
+        out.append(("graphT20_m10", psi, 10 * np.log2(4.0 / 3.0)))
+    elif index == 5:
+        out.append(("haar22", haar(22, seed, np.complex64), None))
+        out.append(("haar24", haar(24, seed + 1, np.complex64), None))
+    else:
+        raise ValueError(f"no static inputs for configuration {index}")
+    return out
+
+
+def serving_requests(count: int = 4096, seed: int | None = None,
+                     n_min: int = 8, n_max: int = 18):
+    """Serving stream: N ~ U{n_min..n_max}; kind 50/50 Haar or graph+T with
+    m ~ U{1..8}; complex64.  Returns a list of dicts with the request's N,
+    kind, seed and m (states are built lazily with `build_request`)."""
+    rng = np.random.default_rng(config_seed(4) if seed is None else seed)
+    reqs = []
+    for i in range(count):
+        N = int(rng.integers(n_min, n_max + 1))
+        kind = "haar" if rng.random() < 0.5 else "graphT"
+        m = int(rng.integers(1, 9)) if kind == "graphT" else 0
+        m = min(m, N)
+        reqs.append({"id": i, "N": N, "kind": kind, "m": m,
+                     "seed": int(rng.integers(0, 2**62))})
+    return reqs
+
+
+def build_request(req) -> np.ndarray:
+    if req["kind"] == "haar":
+        return haar(req["N"], req["seed"], np.complex64)
+    psi, _ = graph_t(req["N"], req["m"], req["seed"], dtype=np.complex64)
+    return psi
+
+
+def snapshot_couplings(N: int = 20) -> np.ndarray:
+    """Couplings of the 64-snapshot Ising sequence (benchmark configuration 5)."""
+    return ising_couplings(N, config_seed(5) + 2)
