@@ -1,0 +1,160 @@
+/*
+ * sre2.h - C ABI of libsre2: exact second-order stabilizer Renyi entropy M2 of
+ * an N-qubit state vector on an AMD Instinct MI355X (gfx950), by the XOR-FWHT
+ * algorithm of Huang, Li, Lee and Zhong (arXiv:2512.24685).
+ *
+ * What is computed (paper, Eq. 1 with alpha = 2, Eq. Pauli_expect, Eq. final1,
+ * Algorithm 1):
+ *
+ *   W_x(z) = sum_k (-1)^{popcount(z & k)} conj(psi[k ^ x]) psi[k]
+ *          = <psi| X^x Z^z |psi>                 (every Pauli string, up to phase)
+ *   S_x    = sum_z |W_x(z)|^4                     (one Walsh-Hadamard transform)
+ *   S      = sum_x S_x                            (all 4^N Pauli strings)
+ *   n      = sum_k |psi[k]|^2
+ *   M2     = -log2( S / (2^N n^4) )
+ *
+ * For a normalised state (n = 1) M2 is the paper's -log2(S / d), d = 2^N.  The
+ * division by n^4 makes the result invariant under psi -> c psi.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - psi is a caller-owned DEVICE buffer of 2^N complex amplitudes, interleaved
+ *    (re, im): SRE2_C64 = 2 x float32 per amplitude, SRE2_C128 = 2 x float64.
+ *    Index k is the integer encoding of the computational basis bit string
+ *    (qubit j = bit j).  M2 does not depend on the qubit order.
+ *  - Output buffers are caller-owned DEVICE memory.  The library never frees
+ *    caller memory.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is stream-ordered like any HIP call: inputs must stay valid and outputs
+ *    must not be read until the stream work completes.
+ *  - Argument errors are detected on the host and returned before any work is
+ *    enqueued.  Errors raised by the HIP runtime while enqueuing are returned as
+ *    SRE2_EHIP.  Properties of the input VALUES (zero norm, NaN, Inf) are only
+ *    known on the device: they are reported through the status slot of the
+ *    output (see sre2_m2), never by the return code.
+ *  - A context owns lazily grown device workspace and is NOT safe for
+ *    concurrent use: calls that share a context must be ordered on one stream
+ *    (or one host thread).  Use one context per stream.
+ *  - All sums are fixed-shape FP64 reductions: for a given (psi bytes, N,
+ *    dtype, form) the results are bitwise reproducible run to run.
+ */
+#ifndef SRE2_H
+#define SRE2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (every function returns one; 0 = success) ------------- */
+#define SRE2_OK 0
+#define SRE2_EINVAL (-1)     /* null pointer, N outside [1, SRE2_MAX_N], bad count/range */
+#define SRE2_EDTYPE (-2)     /* dtype not SRE2_C64 / SRE2_C128 */
+#define SRE2_EFORM (-3)      /* unknown or unsupported form for this N */
+#define SRE2_ENORM (-4)      /* reserved for host-side input checks (serving) */
+#define SRE2_ENOMEM (-5)     /* device workspace could not be allocated */
+#define SRE2_EHIP (-6)       /* HIP runtime / launch error (no GPU, bad stream...) */
+#define SRE2_EBUSY (-7)      /* serving: no free slot or HBM budget right now */
+#define SRE2_ECANCELLED (-8) /* serving: request was cancelled */
+#define SRE2_ENOTFOUND (-9)  /* serving: unknown ticket */
+
+/* ---- element types ----------------------------------------------------- */
+#define SRE2_C64 0  /* complex64: float32 (re, im) */
+#define SRE2_C128 1 /* complex128: float64 (re, im) */
+
+/* ---- arithmetic forms -------------------------------------------------- */
+/* FP32: f_x and every butterfly in float32; |W|^2 in float32, squared and
+ * accumulated in float64 (complex128 input is rounded to complex64 first). */
+#define SRE2_FORM_FP32 0
+/* FP64: everything in float64 (complex64 input is widened exactly). */
+#define SRE2_FORM_FP64 3
+
+#define SRE2_MAX_N 26
+
+/* Layout of the 4-double result written by sre2_m2 / sre2_m2_batched. */
+#define SRE2_OUT_M2 0     /* M2 (NaN when status != 0)                        */
+#define SRE2_OUT_S 1      /* S = sum over all 4^N Pauli strings of |<P>|^4      */
+#define SRE2_OUT_NORM 2   /* n = sum_k |psi[k]|^2 of the arithmetic's input     */
+#define SRE2_OUT_STATUS 3 /* 0 = ok; 1 = n == 0 or a non-finite amplitude       */
+#define SRE2_OUT_LEN 4
+
+typedef struct sre2_ctx sre2_ctx;
+
+/* Library version, e.g. 100 for 0.1.0. */
+int sre2_version(void);
+
+/* Static, never NULL, description of a status code. */
+const char* sre2_strerror(int status);
+
+/* Create a context bound to HIP device `hip_device`.  No device work happens
+ * here; the device is first touched by the first compute call.
+ * Errors: SRE2_EINVAL (out == NULL or hip_device < 0), SRE2_ENOMEM (host). */
+int sre2_create(sre2_ctx** out, int hip_device);
+
+/* Free the context and its device workspace (waits for the device).  NULL is
+ * accepted. */
+int sre2_destroy(sre2_ctx* ctx);
+
+/* Upper bound for the two-pass scratch slab (N >= 15 in FP32, N >= 14 in
+ * FP64); shifts are processed in chunks that fit it.  Default 4 GiB; values
+ * below one shift's slab are raised to one slab. */
+int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes);
+
+/* Device workspace (bytes) a call with these arguments grows the context to,
+ * with the current default scratch limit.  0 for invalid arguments. */
+size_t sre2_workspace_bytes(int N, int dtype, int form);
+
+/* M2 of one state (Algorithm 1 over all 2^N shifts).
+ *   psi       device, 2^N amplitudes of `dtype`
+ *   out       device, SRE2_OUT_LEN doubles: M2, S, n, status
+ *   partials  device, NULL or 2^N doubles: partials[x] = S_x (natural x order)
+ * Errors: SRE2_EINVAL, SRE2_EDTYPE, SRE2_EFORM, SRE2_ENOMEM, SRE2_EHIP. */
+int sre2_m2(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, void* stream,
+            double* out, double* partials);
+
+/* Per-shift sums S_x for x in [x_begin, x_begin + x_count) only - the unit a
+ * multi-GPU shard computes (shifts are independent; each GPU takes a range and
+ * the totals add).  partials (device, x_count doubles) receives S_x in order.
+ * Errors: as sre2_m2, plus SRE2_EINVAL for a range outside [0, 2^N). */
+int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
+                  int64_t x_count, void* stream, double* partials);
+
+/* M2 of `count` states, each with its own N (mixed N allowed).
+ *   psi_list  HOST array of `count` device pointers
+ *   N_list    HOST array of `count` qubit counts
+ *   out       device, SRE2_OUT_LEN * count doubles (state i at out + 4 i)
+ * Each state's result is bitwise identical to a single sre2_m2 call. */
+int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,
+                    int dtype, int form, void* stream, double* out);
+
+/* ---- measurement ------------------------------------------------------- */
+/* Kernel classes for per-launch timing. */
+#define SRE2_KIND_SHIFT 0 /* k_tiny / k_fused: whole transforms, N <= 14 (FP32), 13 (FP64) */
+#define SRE2_KIND_PASS1 1 /* two-pass row transform (writes the scratch slab)          */
+#define SRE2_KIND_PASS2 2 /* two-pass column transform + |W|^4 (reads the slab)        */
+#define SRE2_KIND_AUX 3   /* conversion, norm, reductions, logarithm                    */
+#define SRE2_KIND_COUNT 4
+
+/* Enable (1) or disable (0) per-launch timing on this context: every later
+ * launch is bracketed by a pair of HIP events recorded on the caller's stream.
+ * Clears previously recorded pairs.  Errors: SRE2_EINVAL (ctx == NULL). */
+int sre2_set_timing(sre2_ctx* ctx, int enable);
+
+/* Wait for the recorded launches, then return per kernel class the summed
+ * elapsed milliseconds ms[SRE2_KIND_COUNT] and launch counts
+ * launches[SRE2_KIND_COUNT] (host arrays) since the last read; clears them.
+ * Errors: SRE2_EINVAL, SRE2_EHIP. */
+int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches);
+
+/* Two-pass geometry of a full evaluation with this context's scratch limit:
+ * shifts per chunk (0 when N uses the fused kernel) and column groups per
+ * shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
+int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRE2_H */

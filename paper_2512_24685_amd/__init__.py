@@ -1,0 +1,258 @@
+"""MI355X-native XOR-FWHT evaluation of the second-order stabilizer Renyi
+entropy M2 (arXiv:2512.24685).
+
+This module is the Python binding of libsre2 (C ABI in include/sre2.h).  It
+only marshals arguments: device memory and streams come from PyTorch, every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is not built, loading fails with an error.
+
+    import torch, paper_2512_24685_amd as sre2
+    psi = torch.randn(1 << 16, dtype=torch.complex64, device="cuda")
+    r = sre2.m2(psi)            # r.m2, r.S, r.n
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsre2.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sre2.h")
+
+OK, EINVAL, EDTYPE, EFORM, ENORM, ENOMEM, EHIP, EBUSY, ECANCELLED, ENOTFOUND = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+C64, C128 = 0, 1
+FORMS = {"fp32": 0, "fp64": 3}
+MAX_N = 26
+OUT_LEN = 4
+KINDS = ("shift", "pass1", "pass2", "aux")
+KIND_COUNT = 4
+
+_lib = None
+
+
+class SRE2Error(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().sre2_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (status {code})")
+
+
+def lib():
+    """Load libsre2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2512_24685_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    c_int, i64, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    sigs = {
+        "sre2_version": ([], c_int),
+        "sre2_strerror": ([c_int], ctypes.c_char_p),
+        "sre2_create": ([ctypes.POINTER(vp), c_int], c_int),
+        "sre2_destroy": ([vp], c_int),
+        "sre2_set_scratch_limit": ([vp, sz], c_int),
+        "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
+        "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
+        "sre2_partials": ([vp, vp, c_int, c_int, c_int, i64, i64, vp, vp], c_int),
+        "sre2_m2_batched": ([vp, ctypes.POINTER(vp), ctypes.POINTER(c_int), c_int, c_int, c_int,
+                             vp, vp], c_int),
+        "sre2_set_timing": ([vp, c_int], c_int),
+        "sre2_timing_read": ([vp, dp, ctypes.POINTER(i64)], c_int),
+        "sre2_chunking": ([vp, c_int, c_int, ctypes.POINTER(i64), ctypes.POINTER(c_int)], c_int),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/sre2.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sre2_[a-z0-9_]+)\s*\(", text)))
+
+
+def strerror(code: int) -> str:
+    return lib().sre2_strerror(code).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise SRE2Error(rc, where)
+
+
+class Context:
+    """Owns a libsre2 context (device workspace) bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._p = ctypes.c_void_p()
+        _check(lib().sre2_create(ctypes.byref(self._p), int(device)), "sre2_create")
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._p
+
+    def set_scratch_limit(self, nbytes: int):
+        _check(lib().sre2_set_scratch_limit(self._p, int(nbytes)), "sre2_set_scratch_limit")
+
+    def set_timing(self, enable: bool):
+        _check(lib().sre2_set_timing(self._p, int(bool(enable))), "sre2_set_timing")
+
+    def timing_read(self) -> dict:
+        """Per kernel class: (summed ms, launches) since the last read."""
+        ms = (ctypes.c_double * KIND_COUNT)()
+        cnt = (ctypes.c_int64 * KIND_COUNT)()
+        _check(lib().sre2_timing_read(self._p, ms, cnt), "sre2_timing_read")
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(KINDS)}
+
+    def chunking(self, N: int, form: str = "fp32") -> tuple[int, int]:
+        cs, P = ctypes.c_int64(), ctypes.c_int()
+        _check(lib().sre2_chunking(self._p, N, FORMS[form], ctypes.byref(cs), ctypes.byref(P)),
+               "sre2_chunking")
+        return cs.value, P.value
+
+    def close(self):
+        if self._p:
+            lib().sre2_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+@dataclass
+class Result:
+    m2: float
+    S: float
+    n: float
+    status: int
+    partials: object = None  # torch tensor of S_x when requested
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
+
+
+def _nqubits(t) -> int:
+    d = t.numel()
+    N = d.bit_length() - 1
+    if d < 2 or (1 << N) != d:
+        raise ValueError("state length must be 2^N with N >= 1")
+    return N
+
+
+def _stream_ptr(t, stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return int(s.cuda_stream)
+
+
+def _prep(psi):
+    torch = _torch()
+    if not isinstance(psi, torch.Tensor) or not psi.is_cuda:
+        raise TypeError("psi must be a torch tensor on a GPU device")
+    return psi.contiguous().reshape(-1)
+
+
+def m2_async(psi, form: str = "fp32", partials: bool = False, ctx: Context | None = None,
+             stream=None):
+    """Enqueue one evaluation; returns (out tensor [4], partials tensor or None)."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    ctx = ctx or context(psi.device.index or 0)
+    out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
+    part = torch.empty(1 << N, dtype=torch.float64, device=psi.device) if partials else None
+    rc = lib().sre2_m2(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
+                       FORMS[form], ctypes.c_void_p(_stream_ptr(psi, stream)),
+                       ctypes.c_void_p(out.data_ptr()),
+                       ctypes.c_void_p(part.data_ptr()) if part is not None else None)
+    _check(rc, "sre2_m2")
+    return out, part
+
+
+def _result(out_row, part=None) -> Result:
+    v = out_row.tolist()
+    return Result(m2=v[0], S=v[1], n=v[2], status=int(v[3]), partials=part)
+
+
+def m2(psi, form: str = "fp32", partials: bool = False, ctx: Context | None = None,
+       stream=None) -> Result:
+    """M2 of one device-resident state (synchronises to read the result)."""
+    out, part = m2_async(psi, form, partials, ctx, stream)
+    return _result(out.cpu(), part)
+
+
+def shift_partials(psi, x_begin: int = 0, x_count: int | None = None, form: str = "fp32",
+                   ctx: Context | None = None, stream=None):
+    """S_x for x in [x_begin, x_begin + x_count) as a float64 device tensor."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    if x_count is None:
+        x_count = (1 << N) - x_begin
+    ctx = ctx or context(psi.device.index or 0)
+    out = torch.empty(max(int(x_count), 1), dtype=torch.float64, device=psi.device)
+    rc = lib().sre2_partials(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
+                             FORMS[form], int(x_begin), int(x_count),
+                             ctypes.c_void_p(_stream_ptr(psi, stream)),
+                             ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_partials")
+    return out
+
+
+def m2_batched(psis, form: str = "fp32", ctx: Context | None = None, stream=None) -> list[Result]:
+    """M2 of several device states of one dtype (mixed N allowed)."""
+    torch = _torch()
+    psis = [_prep(p) for p in psis]
+    if not psis:
+        return []
+    dt = _dtype_code(psis[0])
+    for p in psis:
+        if _dtype_code(p) != dt:
+            raise TypeError("all states of a batch must share one dtype")
+    dev = psis[0].device
+    ctx = ctx or context(dev.index or 0)
+    cnt = len(psis)
+    ptrs = (ctypes.c_void_p * cnt)(*[p.data_ptr() for p in psis])
+    Ns = (ctypes.c_int * cnt)(*[_nqubits(p) for p in psis])
+    out = torch.empty(cnt * OUT_LEN, dtype=torch.float64, device=dev)
+    rc = lib().sre2_m2_batched(ctx.handle, ptrs, Ns, cnt, dt, FORMS[form],
+                               ctypes.c_void_p(_stream_ptr(psis[0], stream)),
+                               ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_m2_batched")
+    o = out.cpu().reshape(cnt, OUT_LEN)
+    return [_result(o[i]) for i in range(cnt)]

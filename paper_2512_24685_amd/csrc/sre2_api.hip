@@ -1,0 +1,397 @@
+// sre2_api.hip - C ABI of libsre2 (declared in include/sre2.h): argument
+// validation, workspace management and the launch sequence of one M2
+// evaluation.  All arithmetic runs in the kernels of sre2_kernels.hip.
+//
+// Launch sequence of sre2_m2 on the caller's stream:
+//   [k_convert]        input -> working precision copy (only if dtype != form's)
+//   k_norm_part        FP64 partial norms + non-finite flags
+//   shift sums         k_tiny | k_fused | per chunk: k_pass1, k_pass2, k_group_sum
+//   k_sum_part         fixed-range FP64 partial sums of S_x
+//   k_final            S, n, M2 = -log2(S / (2^N n^4)), status
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/sre2.h"
+#include "sre2_internal.h"
+#include "sre2_plan.h"
+
+using namespace sre2;
+
+struct sre2_ctx {
+    int device = 0;
+    size_t scratch_limit = size_t(4) << 30;
+    void* psi_work = nullptr;
+    size_t psi_work_bytes = 0;
+    double* sx = nullptr;  // S_x when the caller passes no partials buffer
+    size_t sx_bytes = 0;
+    void* scratch = nullptr;  // two-pass slab
+    size_t scratch_bytes = 0;
+    double* part = nullptr;  // two-pass column-group partials of one chunk
+    size_t part_bytes = 0;
+    double* red = nullptr;  // norm partials, flags, S partials
+    size_t red_bytes = 0;
+    // optional per-launch timing (sre2_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;       // pool, reused between reads
+    std::vector<int> pending;             // kind of each recorded (start, stop) pair
+};
+
+namespace {
+
+constexpr int kMaxRed = 1024;  // upper bound of reduction blocks
+
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int fault_injected(const char* what) {
+    const char* f = getenv("SRE2_FAULT");
+    return f && strcmp(f, what) == 0;
+}
+
+int ensure(void** buf, size_t* have, size_t need) {
+    if (*have >= need && *buf) return SRE2_OK;
+    if (fault_injected("alloc")) return SRE2_ENOMEM;
+    if (*buf) {
+        if (hipFree(*buf) != hipSuccess) return SRE2_EHIP;
+        *buf = nullptr;
+        *have = 0;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, need);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return SRE2_ENOMEM;
+    }
+    if (e != hipSuccess) return SRE2_EHIP;
+    *buf = p;
+    *have = need;
+    return SRE2_OK;
+}
+
+bool form_ok(int form) { return form == SRE2_FORM_FP32 || form == SRE2_FORM_FP64; }
+bool dtype_ok(int dtype) { return dtype == SRE2_C64 || dtype == SRE2_C128; }
+
+int elem_bytes(int dtype) { return dtype == SRE2_C64 ? 8 : 16; }
+int work_dtype(int form) { return form == SRE2_FORM_FP64 ? kC128 : kC64; }
+
+int tile_bits(int form) { return form == SRE2_FORM_FP64 ? Geo<double>::TB : Geo<float>::TB; }
+
+// Two-pass chunking: shifts per chunk (power of two) and column groups per shift.
+struct Chunking {
+    int64_t cs = 0;
+    int P = 1;
+};
+
+Chunking chunking(int N, int form, int64_t x_count, size_t limit) {
+    Chunking c;
+    const int TB = tile_bits(form);
+    if (N <= TB) return c;
+    const size_t slab = (size_t(1) << N) * (size_t)elem_bytes(work_dtype(form));
+    int64_t cs = 1;
+    while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << 14))
+        cs *= 2;
+    c.cs = cs;
+    const int H = N - TB;
+    int P = 1;
+    while (cs * P < 2048 && P * 2 <= (1 << H)) P *= 2;
+    c.P = P;
+    return c;
+}
+
+int red_blocks(int64_t n) {
+    int64_t b = n >> 14;
+    if (b < 1) b = 1;
+    if (b > kMaxRed) b = kMaxRed;
+    return (int)b;
+}
+
+// Bracket one launch with a pair of pooled events when timing is enabled.
+struct Timed {
+    sre2_ctx* ctx;
+    hipStream_t st;
+    int kind;
+    size_t slot = 0;
+    bool on = false;
+    Timed(sre2_ctx* c, hipStream_t s, int k) : ctx(c), st(s), kind(k) {
+        if (!ctx->timing) return;
+        slot = ctx->pending.size() * 2;
+        while (ctx->events.size() < slot + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ctx->events.push_back(e);
+        }
+        on = hipEventRecord(ctx->events[slot], st) == hipSuccess;
+    }
+    ~Timed() {
+        if (on && hipEventRecord(ctx->events[slot + 1], st) == hipSuccess)
+            ctx->pending.push_back(kind);
+    }
+};
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SRE2_OK : SRE2_EHIP; }
+
+int validate(const sre2_ctx* ctx, const void* psi, int N, int dtype, int form) {
+    if (!ctx || !psi) return SRE2_EINVAL;
+    if (N < 1 || N > SRE2_MAX_N) return SRE2_EINVAL;
+    if (!dtype_ok(dtype)) return SRE2_EDTYPE;
+    if (!form_ok(form)) return SRE2_EFORM;
+    return SRE2_OK;
+}
+
+// Stage the input in the form's working precision; returns the pointer the
+// kernels read.
+int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
+                const void** work) {
+    const int wd = work_dtype(form);
+    if (wd == dtype) {
+        *work = psi;
+        return SRE2_OK;
+    }
+    const int64_t n = int64_t(1) << N;
+    int rc = ensure(&ctx->psi_work, &ctx->psi_work_bytes, (size_t)n * elem_bytes(wd));
+    if (rc) return rc;
+    {
+        Timed tm(ctx, st, SRE2_KIND_AUX);
+        rc = hip_status(launch_convert(psi, dtype, ctx->psi_work, wd, n, st));
+    }
+    *work = ctx->psi_work;
+    return rc;
+}
+
+// S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).
+int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
+               double* Sx, hipStream_t st) {
+    const int TB = tile_bits(form);
+    const bool f64 = form == SRE2_FORM_FP64;
+    if (N <= TB) {
+        Timed tm(ctx, st, SRE2_KIND_SHIFT);
+        return hip_status(f64 ? launch_shift_kernel<double>(work, N, x0, xc, Sx, st)
+                              : launch_shift_kernel<float>(work, N, x0, xc, Sx, st));
+    }
+    const Chunking ch = chunking(N, form, xc, ctx->scratch_limit);
+    const size_t slab = (size_t(1) << N) * (size_t)elem_bytes(work_dtype(form));
+    int rc = ensure(&ctx->scratch, &ctx->scratch_bytes, (size_t)ch.cs * slab);
+    if (rc) return rc;
+    rc = ensure((void**)&ctx->part, &ctx->part_bytes, (size_t)ch.cs * ch.P * sizeof(double));
+    if (rc) return rc;
+    for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
+        // a short last chunk keeps the same column grouping
+        const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
+        hipError_t e;
+        {
+            Timed tm(ctx, st, SRE2_KIND_PASS1);
+            e = f64 ? launch_pass1<double>(work, N, x0 + c0, cs, ctx->scratch, st)
+                    : launch_pass1<float>(work, N, x0 + c0, cs, ctx->scratch, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+        {
+            Timed tm(ctx, st, SRE2_KIND_PASS2);
+            e = f64 ? launch_pass2<double>(ctx->scratch, N, cs, ch.P, ctx->part, st)
+                    : launch_pass2<float>(ctx->scratch, N, cs, ch.P, ctx->part, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+        {
+            Timed tm(ctx, st, SRE2_KIND_AUX);
+            e = launch_group_sum(ctx->part, cs, ch.P, Sx + c0, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+    }
+    return SRE2_OK;
+}
+
+int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st, double* out,
+           double* partials) {
+    const void* work = nullptr;
+    int rc = stage_input(ctx, psi, N, dtype, form, st, &work);
+    if (rc) return rc;
+    const int64_t n = int64_t(1) << N;
+    rc = ensure((void**)&ctx->red, &ctx->red_bytes, 3 * kMaxRed * sizeof(double));
+    if (rc) return rc;
+    double* npart = ctx->red;
+    double* nflag = ctx->red + kMaxRed;
+    double* spart = ctx->red + 2 * kMaxRed;
+    const int nb = red_blocks(n);
+    {
+        Timed tm(ctx, st, SRE2_KIND_AUX);
+        rc = hip_status(launch_norm(work, work_dtype(form), n, nb, npart, nflag, st));
+    }
+    if (rc) return rc;
+    double* Sx = partials;
+    if (!Sx) {
+        rc = ensure((void**)&ctx->sx, &ctx->sx_bytes, (size_t)n * sizeof(double));
+        if (rc) return rc;
+        Sx = ctx->sx;
+    }
+    rc = shift_sums(ctx, work, N, form, 0, n, Sx, st);
+    if (rc) return rc;
+    {
+        Timed tm(ctx, st, SRE2_KIND_AUX);
+        rc = hip_status(launch_sum(Sx, n, 1, nb, spart, nullptr, st));
+    }
+    if (rc) return rc;
+    Timed tm(ctx, st, SRE2_KIND_AUX);
+    return hip_status(launch_final(spart, nb, npart, nflag, nb, N, out, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sre2_version(void) { return 100; }
+
+const char* sre2_strerror(int status) {
+    switch (status) {
+        case SRE2_OK: return "success";
+        case SRE2_EINVAL: return "invalid argument (null pointer, N out of range, bad count or range)";
+        case SRE2_EDTYPE: return "unsupported dtype (expected SRE2_C64 or SRE2_C128)";
+        case SRE2_EFORM: return "unsupported arithmetic form";
+        case SRE2_ENORM: return "input state has zero norm or non-finite amplitudes";
+        case SRE2_ENOMEM: return "device workspace allocation failed";
+        case SRE2_EHIP: return "HIP runtime or kernel launch error";
+        case SRE2_EBUSY: return "no free slot or memory budget";
+        case SRE2_ECANCELLED: return "request cancelled";
+        case SRE2_ENOTFOUND: return "unknown ticket";
+        default: return "unknown status code";
+    }
+}
+
+int sre2_create(sre2_ctx** out, int hip_device) {
+    if (!out || hip_device < 0) return SRE2_EINVAL;
+    sre2_ctx* c = new (std::nothrow) sre2_ctx();
+    if (!c) return SRE2_ENOMEM;
+    c->device = hip_device;
+    *out = c;
+    return SRE2_OK;
+}
+
+int sre2_destroy(sre2_ctx* ctx) {
+    if (!ctx) return SRE2_OK;
+    int rc = SRE2_OK;
+    if (ctx->psi_work || ctx->sx || ctx->scratch || ctx->part || ctx->red) {
+        DeviceGuard g(ctx->device);
+        if (g.err != hipSuccess) rc = SRE2_EHIP;
+        (void)hipDeviceSynchronize();
+        void* bufs[] = {ctx->psi_work, ctx->sx, ctx->scratch, ctx->part, ctx->red};
+        for (void* b : bufs)
+            if (b && hipFree(b) != hipSuccess) rc = SRE2_EHIP;
+    }
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    delete ctx;
+    return rc;
+}
+
+int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes) {
+    if (!ctx) return SRE2_EINVAL;
+    ctx->scratch_limit = bytes;
+    return SRE2_OK;
+}
+
+size_t sre2_workspace_bytes(int N, int dtype, int form) {
+    if (N < 1 || N > SRE2_MAX_N || !dtype_ok(dtype) || !form_ok(form)) return 0;
+    const size_t n = size_t(1) << N;
+    size_t b = 3 * kMaxRed * sizeof(double) + n * sizeof(double);
+    if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
+    const Chunking ch = chunking(N, form, (int64_t)n, size_t(4) << 30);
+    if (ch.cs) {
+        b += (size_t)ch.cs * n * (size_t)elem_bytes(work_dtype(form));
+        b += (size_t)ch.cs * ch.P * sizeof(double);
+    }
+    return b;
+}
+
+int sre2_m2(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, void* stream, double* out,
+            double* partials) {
+    int rc = validate(ctx, psi, N, dtype, form);
+    if (rc) return rc;
+    if (!out) return SRE2_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, partials);
+}
+
+int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
+                  int64_t x_count, void* stream, double* partials) {
+    int rc = validate(ctx, psi, N, dtype, form);
+    if (rc) return rc;
+    const int64_t n = int64_t(1) << N;
+    if (!partials || x_begin < 0 || x_count < 1 || x_begin > n || x_count > n - x_begin)
+        return SRE2_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    const hipStream_t st = (hipStream_t)stream;
+    const void* work = nullptr;
+    rc = stage_input(ctx, psi, N, dtype, form, st, &work);
+    if (rc) return rc;
+    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, st);
+}
+
+int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,
+                    int dtype, int form, void* stream, double* out) {
+    if (!ctx || !psi_list || !N_list || !out || count < 1) return SRE2_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate(ctx, psi_list[i], N_list[i], dtype, form);
+        if (rc) return rc;
+    }
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    for (int i = 0; i < count; ++i) {
+        const int rc = m2_one(ctx, psi_list[i], N_list[i], dtype, form, (hipStream_t)stream,
+                              out + (size_t)SRE2_OUT_LEN * i, nullptr);
+        if (rc) return rc;
+    }
+    return SRE2_OK;
+}
+
+int sre2_set_timing(sre2_ctx* ctx, int enable) {
+    if (!ctx) return SRE2_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->pending.clear();
+    return SRE2_OK;
+}
+
+int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches) {
+    if (!ctx || !ms || !launches) return SRE2_EINVAL;
+    for (int k = 0; k < SRE2_KIND_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (ctx->pending.empty()) return SRE2_OK;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    if (hipEventSynchronize(ctx->events[ctx->pending.size() * 2 - 1]) != hipSuccess)
+        return SRE2_EHIP;
+    for (size_t i = 0; i < ctx->pending.size(); ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]) != hipSuccess)
+            return SRE2_EHIP;
+        ms[ctx->pending[i]] += t;
+        launches[ctx->pending[i]] += 1;
+    }
+    ctx->pending.clear();
+    return SRE2_OK;
+}
+
+int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups) {
+    if (!ctx || !shifts_per_chunk || !groups || N < 1 || N > SRE2_MAX_N || !form_ok(form))
+        return SRE2_EINVAL;
+    const Chunking ch = chunking(N, form, int64_t(1) << N, ctx->scratch_limit);
+    *shifts_per_chunk = ch.cs;
+    *groups = ch.P;
+    return SRE2_OK;
+}
+
+}  // extern "C"

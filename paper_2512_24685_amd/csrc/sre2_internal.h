@@ -1,0 +1,37 @@
+// sre2_internal.h - declarations shared by the kernel and API translation units
+// of libsre2 (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <utility>
+
+namespace sre2 {
+
+constexpr int kMaxN = 26;
+constexpr int kC64 = 0;
+constexpr int kC128 = 1;
+
+// S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (N < RB) or fused
+// kernel (N <= TB).
+template <typename Real>
+hipError_t launch_shift_kernel(const void* psi, int N, int64_t x0, int64_t xc, double* S,
+                               hipStream_t st);
+// Two-pass (N > TB), one chunk of cs shifts starting at x0: pass 1 writes the
+// row-transformed slabs (cs * 2^N complex values) to `scratch`; pass 2 writes
+// part[s*P + p], the p-th column-group partial of shift x0+s.
+template <typename Real>
+hipError_t launch_pass1(const void* psi, int N, int64_t x0, int cs, void* scratch, hipStream_t st);
+template <typename Real>
+hipError_t launch_pass2(const void* scratch, int N, int cs, int P, double* part, hipStream_t st);
+
+hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
+                          hipStream_t st);
+hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, double* part,
+                       double* flag, hipStream_t st);
+hipError_t launch_sum(const double* v, int64_t nshift, int P, int nblocks, double* part,
+                      double* Sx, hipStream_t st);
+hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, hipStream_t st);
+hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
+                        int nn, int N, double* out, hipStream_t st);
+
+}  // namespace sre2

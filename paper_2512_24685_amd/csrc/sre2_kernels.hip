@@ -1,0 +1,572 @@
+// sre2_kernels.hip - gfx950 kernels for the XOR-FWHT evaluation of the
+// second-order stabilizer Renyi entropy (arXiv:2512.24685, Algorithm 1 and
+// Eq. final1):
+//
+//   S_x = sum_z |W_x(z)|^4,  W_x = FWHT_k( conj(psi[k ^ x]) * psi[k] ),
+//   S   = sum_x S_x,          M2  = -log2( S / (2^N n^4) ),  n = sum_k |psi[k]|^2.
+//
+// W_x(z) equals <psi| X^x Z^z |psi> (Eq. Pauli_expect), so every W is a Pauli
+// expectation.  Shifts x are independent units of work (main text: the shift
+// loop is parallel); each kernel below owns a set of shifts or a slice of one.
+//
+//  k_tiny      N < RB: one thread per shift, whole transform in registers.
+//  k_fused     RB <= N <= TB: a workgroup holds 2^(TB-N) complete shifts in a
+//              2^TB tile; rounds of register butterflies with LDS transposes.
+//  k_pass1     N > TB: row transform over the low TB bits of k, f_x built on
+//              the fly from psi, written to a scratch slab.
+//  k_pass2     N > TB: column transform over the high N-TB bits, |W|^4 and a
+//              per-workgroup FP64 partial sum; nothing is written back.
+//  k_convert / k_norm_part / k_sum_part / k_final: input staging, FP64 norm,
+//              fixed-order FP64 reductions and the logarithm.
+//
+// Accumulation: |W|^2 is formed in the working precision, squared and summed
+// in FP64 per element; per-thread sums are combined by fixed-shape trees, so a
+// result depends only on (psi, N, form), never on scheduling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "sre2_plan.h"
+#include "sre2_internal.h"
+
+namespace sre2 {
+
+template <typename Real> struct CT;
+template <> struct CT<float> { using T = float2; };
+template <> struct CT<double> { using T = double2; };
+
+template <typename C>
+__device__ __forceinline__ C cmul_conj_a(C a, C b) {  // conj(a) * b
+    C r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.x * b.y - a.y * b.x;
+    return r;
+}
+
+template <typename C>
+__device__ __forceinline__ double abs4(C w) {  // |w|^4 with the square in FP64
+    const auto m = w.x * w.x + w.y * w.y;
+    const double md = (double)m;
+    return md * md;
+}
+
+// Butterflies over the register bits of `bfly` (a subset of `reg`), one tile
+// bit at a time (compile-time recursion keeps every register index constant).
+template <int RB, uint32_t REG, uint32_t BFLY, int B = 0, typename C>
+__device__ __forceinline__ void butterflies(C (&v)[1 << RB]) {
+    if constexpr (B < 32) {
+        if constexpr (((BFLY >> B) & 1u) != 0) {
+            constexpr int rbit = popc(REG & ((1u << B) - 1u));
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                if ((i >> rbit) & 1) continue;
+                const int j = i | (1 << rbit);
+                const C a = v[i], c = v[j];
+                v[i].x = a.x + c.x;
+                v[i].y = a.y + c.y;
+                v[j].x = a.x - c.x;
+                v[j].y = a.y - c.y;
+            }
+        }
+        butterflies<RB, REG, BFLY, B + 1>(v);
+    }
+}
+
+template <uint32_t LANE, uint32_t WAVE>
+__device__ __forceinline__ uint32_t thread_base() {
+    const uint32_t t = threadIdx.x;
+    return pdep(t & 63u, LANE) | pdep(t >> 6, WAVE);
+}
+
+template <int SB, int RB, uint32_t REG, uint32_t LANE, uint32_t WAVE, typename C>
+__device__ __forceinline__ void lds_put(C* lds, const C (&v)[1 << RB]) {
+    const uint32_t pb = swz<SB>(thread_base<LANE, WAVE>());
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))] = v[i];
+}
+
+template <int SB, int RB, uint32_t REG, uint32_t LANE, uint32_t WAVE, typename C>
+__device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
+    const uint32_t pb = swz<SB>(thread_base<LANE, WAVE>());
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) v[i] = lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))];
+}
+
+// Rounds 1 .. nrounds-1 of a plan: LDS transpose, then butterflies.
+template <typename Real, int PK, int J>
+struct RoundRunner;
+
+// Plan selector: PK encodes (kind, parameter) so that plans are constexpr.
+//   PK = 1000 + N : fused over bits [0, N)
+//   PK = 2000     : pass 1 over all TB bits
+//   PK = 3000 + H : pass 2 over the top H bits
+template <typename Real, int PK>
+__host__ __device__ constexpr Plan plan_of() {
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB, SB = Geo<Real>::SB;
+    if (PK >= 3000) return make_plan(TB, RB, SB, TB - (PK - 3000), TB);
+    if (PK >= 2000) return make_plan(TB, RB, SB, 0, TB);
+    return make_plan(TB, RB, SB, 0, PK - 1000);
+}
+
+template <typename Real, int PK, int J>
+struct RoundRunner {
+    using C = typename CT<Real>::T;
+    static constexpr Plan P = plan_of<Real, PK>();
+    static constexpr int RB = Geo<Real>::RB, SB = Geo<Real>::SB;
+    __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB]) {
+        if constexpr (J < P.nrounds) {
+            constexpr Round prev = P.r[J - 1];
+            constexpr Round cur = P.r[J];
+            __syncthreads();  // previous readers of the LDS tile are done
+            lds_put<SB, RB, prev.reg, prev.lane, prev.wave>(lds, v);
+            __syncthreads();
+            lds_get<SB, RB, cur.reg, cur.lane, cur.wave>(lds, v);
+            butterflies<RB, cur.reg, cur.bfly>(v);
+            RoundRunner<Real, PK, J + 1>::run(lds, v);
+        }
+    }
+};
+
+// Fixed-shape tree over T doubles in LDS; segments of `seg` consecutive entries
+// are reduced independently (seg divides T, both powers of two).  Result of
+// segment j lands in red[j * seg].
+template <int T>
+__device__ __forceinline__ void seg_tree(double* red, int seg) {
+    for (int s = seg >> 1; s >= 1; s >>= 1) {
+        __syncthreads();
+        const int i = threadIdx.x;
+        if ((i & (2 * s - 1)) < s) red[i] += red[i + s];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Tiny N (N < RB): one thread per shift.
+// ---------------------------------------------------------------------------
+template <typename Real, int N>
+__global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restrict__ psi,
+                                             int64_t x_begin, int64_t x_count,
+                                             double* __restrict__ S_out) {
+    using C = typename CT<Real>::T;
+    constexpr int D = 1 << N;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (idx >= x_count) return;
+    const uint32_t x = (uint32_t)(x_begin + idx);
+    C v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = cmul_conj_a(psi[k ^ x], psi[k]);
+    butterflies<N, (1u << N) - 1u, (1u << N) - 1u>(v);
+    double s = 0.0;
+#pragma unroll
+    for (int z = 0; z < D; ++z) s += abs4(v[z]);
+    S_out[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Fused: RB <= N <= TB.  Tile = SPT = 2^(TB-N) consecutive shifts.
+// ---------------------------------------------------------------------------
+template <typename Real, int N>
+__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
+             double* __restrict__ S_out) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int T = 1 << (TB - RB);
+    constexpr int PK = 1000 + N;
+    constexpr Plan P = plan_of<Real, PK>();
+    constexpr Round r0 = P.r[0];
+    constexpr Round rl = P.r[P.nrounds - 1];
+    constexpr int SPT = 1 << (TB - N);
+    constexpr uint32_t KMASK = (1u << N) - 1u;
+    __shared__ C lds[1 << TB];
+    double* red = reinterpret_cast<double*>(lds);
+
+    const int64_t ntiles = (x_count + SPT - 1) / SPT;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t x0 = x_begin + tile * SPT;  // first shift of the tile
+        C v[1 << RB];
+        {
+            const uint32_t base = thread_base<r0.lane, r0.wave>();
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                const uint32_t e = base | pdep((uint32_t)i, r0.reg);
+                const uint32_t k = e & KMASK;
+                const int64_t j = e >> N;  // shift slot in the tile
+                if (tile * SPT + j < x_count) {
+                    const uint32_t x = (uint32_t)(x0 + j);
+                    v[i] = cmul_conj_a(psi[k ^ x], psi[k]);
+                } else {
+                    v[i].x = 0;
+                    v[i].y = 0;
+                }
+            }
+        }
+        butterflies<RB, r0.reg, r0.bfly>(v);
+        RoundRunner<Real, PK, 1>::run(lds, v);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < (1 << RB); ++i) s += abs4(v[i]);
+        // thread order index: tile bits outside the last round's registers,
+        // compressed; its top TB-N bits are the shift slot.
+        const uint32_t q = pext(thread_base<rl.lane, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
+        __syncthreads();
+        red[q] = s;
+        seg_tree<T>(red, T / SPT);
+        if (threadIdx.x < SPT) {
+            const int64_t j = threadIdx.x;
+            if (tile * SPT + j < x_count) S_out[tile * SPT + j] = red[j * (T / SPT)];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass, pass 1: row transform over k_lo (TB bits) of f_x for a chunk of
+// shifts.  Block b -> row = b / cs, shift slot = b % cs, so neighbouring blocks
+// read the same psi rows.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, int cs,
+             typename CT<Real>::T* __restrict__ scratch) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int PK = 2000;
+    constexpr Plan P = plan_of<Real, PK>();
+    constexpr Round r0 = P.r[0];
+    constexpr Round rl = P.r[P.nrounds - 1];
+    __shared__ C lds[1 << TB];
+
+    const int64_t b = blockIdx.x;
+    const int64_t row = b / cs;
+    const int64_t s = b % cs;
+    const uint64_t x = (uint64_t)(x0 + s);
+    const uint64_t rowbase = (uint64_t)row << TB;
+    const uint64_t prow = rowbase ^ (x & ~(uint64_t)((1u << TB) - 1u));  // partner row
+    const uint32_t xlo = (uint32_t)(x & ((1u << TB) - 1u));
+    const C* __restrict__ pa = psi + rowbase;
+    const C* __restrict__ pb = psi + prow;
+    C v[1 << RB];
+    {
+        const uint32_t base = thread_base<r0.lane, r0.wave>();
+#pragma unroll
+        for (int i = 0; i < (1 << RB); ++i) {
+            const uint32_t e = base | pdep((uint32_t)i, r0.reg);
+            v[i] = cmul_conj_a(pb[e ^ xlo], pa[e]);
+        }
+    }
+    butterflies<RB, r0.reg, r0.bfly>(v);
+    RoundRunner<Real, PK, 1>::run(lds, v);
+    C* __restrict__ out = scratch + ((uint64_t)s << N) + rowbase;
+    const uint32_t base = thread_base<rl.lane, rl.wave>();
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) out[base | pdep((uint32_t)i, rl.reg)] = v[i];
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass, pass 2: column transform over k_hi (H = N - TB bits).  A tile is
+// 2^H rows x 2^(TB-H) columns of one shift's slab.  Block b -> shift slot
+// b / P, column group b % P; the group loops over its column tiles and writes
+// one FP64 partial.
+// ---------------------------------------------------------------------------
+template <typename Real, int H>
+__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
+             double* __restrict__ part) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int T = 1 << (TB - RB);
+    constexpr int PK = 3000 + H;
+    constexpr Plan PL = plan_of<Real, PK>();
+    constexpr Round r0 = PL.r[0];
+    constexpr int CB = TB - H;  // column bits per tile
+    constexpr uint32_t CMASK = (1u << CB) - 1u;
+    __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
+    __shared__ double red[T];
+
+    const int64_t b = blockIdx.x;
+    const int64_t s = b / P;
+    const int g = (int)(b % P);
+    const int L = N - H;  // == TB
+    const int ntile = 1 << (L - CB);  // column tiles per shift
+    const int per = ntile / P;
+    const C* __restrict__ slab = scratch + ((uint64_t)s << N);
+    double acc = 0.0;
+    for (int ct = g * per; ct < (g + 1) * per; ++ct) {
+        const C* __restrict__ src = slab + ((uint64_t)ct << CB);
+        C v[1 << RB];
+        const uint32_t base = thread_base<r0.lane, r0.wave>();
+#pragma unroll
+        for (int i = 0; i < (1 << RB); ++i) {
+            const uint32_t e = base | pdep((uint32_t)i, r0.reg);
+            v[i] = src[((uint64_t)(e >> CB) << L) + (e & CMASK)];
+        }
+        butterflies<RB, r0.reg, r0.bfly>(v);
+        if constexpr (PL.nrounds > 1) RoundRunner<Real, PK, 1>::run(lds, v);
+#pragma unroll
+        for (int i = 0; i < (1 << RB); ++i) acc += abs4(v[i]);
+    }
+    red[threadIdx.x] = acc;
+    seg_tree<T>(red, T);
+    if (threadIdx.x == 0) part[b] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Staging and reductions.
+// ---------------------------------------------------------------------------
+template <typename Src, typename Dst>
+__global__ void k_convert(const Src* __restrict__ in, Dst* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        Dst d;
+        d.x = in[i].x;
+        d.y = in[i].y;
+        out[i] = d;
+    }
+}
+
+constexpr int kRedThreads = 256;
+
+// part[b] = sum of |psi|^2 over block b's fixed range; flag[b] = non-finite seen.
+template <typename C>
+__global__ __launch_bounds__(kRedThreads) void k_norm_part(const C* __restrict__ psi, int64_t n,
+                                                           int64_t per_block,
+                                                           double* __restrict__ part,
+                                                           double* __restrict__ flag) {
+    __shared__ double red[kRedThreads];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < n ? lo + per_block : n;
+    double s = 0.0;
+    int bad = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedThreads) {
+        const double re = (double)psi[i].x, im = (double)psi[i].y;
+        if (!isfinite(re) || !isfinite(im)) bad = 1;
+        s += re * re + im * im;
+    }
+    red[threadIdx.x] = s;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    const double tot = red[0];
+    __syncthreads();
+    red[threadIdx.x] = bad ? 1.0 : 0.0;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = tot;
+        flag[blockIdx.x] = red[0];
+    }
+}
+
+// part[b] = sum of v over block b's fixed range (optionally with stride-P
+// grouping: entry x*P+p belongs to shift x; Sx, when non-null, receives
+// sum_p v[x*P+p] in p order).
+__global__ __launch_bounds__(kRedThreads) void k_sum_part(const double* __restrict__ v,
+                                                          int64_t nshift, int P,
+                                                          int64_t per_block,
+                                                          double* __restrict__ part,
+                                                          double* __restrict__ Sx) {
+    __shared__ double red[kRedThreads];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < nshift ? lo + per_block : nshift;
+    double s = 0.0;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kRedThreads) {
+        double sx = 0.0;
+        for (int p = 0; p < P; ++p) sx += v[x * P + p];
+        if (Sx) Sx[x] = sx;
+        s += sx;
+    }
+    red[threadIdx.x] = s;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Sx[s] = sum_p part[s*P + p] in p order (one thread per shift).
+__global__ __launch_bounds__(256) void k_group_sum(const double* __restrict__ part, int64_t ns,
+                                                   int P, double* __restrict__ Sx) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= ns) return;
+    double a = 0.0;
+    for (int p = 0; p < P; ++p) a += part[s * P + p];
+    Sx[s] = a;
+}
+
+// out[0] = M2, out[1] = S, out[2] = n, out[3] = status (0 ok, 1 bad input).
+__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ spart, int ns,
+                                                       const double* __restrict__ npart,
+                                                       const double* __restrict__ nflag, int nn,
+                                                       int N, double* __restrict__ out) {
+    __shared__ double red[kRedThreads];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < ns; i += kRedThreads) a += spart[i];
+    for (int i = threadIdx.x; i < nn; i += kRedThreads) {
+        b += npart[i];
+        c += nflag[i];
+    }
+    red[threadIdx.x] = a;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    const double S = red[0];
+    __syncthreads();
+    red[threadIdx.x] = b;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    const double n = red[0];
+    __syncthreads();
+    red[threadIdx.x] = c;
+    seg_tree<kRedThreads>(red, kRedThreads);
+    const double bad = red[0];
+    if (threadIdx.x == 0) {
+        const bool ok = bad == 0.0 && n > 0.0 && isfinite(n) && isfinite(S);
+        const double n2 = n * n;
+        out[0] = ok ? -log2(S / (ldexp(1.0, N) * n2 * n2)) : NAN;
+        out[1] = S;
+        out[2] = n;
+        out[3] = ok ? 0.0 : 1.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called from sre2_api.hip).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename Real, int N>
+hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
+    using C = typename CT<Real>::T;
+    const int64_t blocks = (xc + 63) / 64;
+    hipLaunchKernelGGL((k_tiny<Real, N>), dim3((unsigned)blocks), dim3(64), 0, st,
+                       (const C*)psi, x0, xc, S);
+    return hipGetLastError();
+}
+
+template <typename Real, int N>
+hipError_t launch_fused_n(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int SPT = 1 << (TB - N);
+    const int64_t ntiles = (xc + SPT - 1) / SPT;
+    const int64_t grid = ntiles < 65536 ? ntiles : 65536;
+    hipLaunchKernelGGL((k_fused<Real, N>), dim3((unsigned)grid), dim3(1 << (TB - RB)), 0, st,
+                       (const C*)psi, x0, xc, S);
+    return hipGetLastError();
+}
+
+template <typename Real, int H>
+hipError_t launch_pass2_h(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    hipLaunchKernelGGL((k_pass2<Real, H>), dim3((unsigned)((int64_t)cs * P)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, N, P, part);
+    return hipGetLastError();
+}
+
+template <typename Real, int... Ns>
+hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st,
+                         std::integer_sequence<int, Ns...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((N == Ns + 1 ? (e = launch_tiny_n<Real, Ns + 1>(psi, x0, xc, S, st), 0) : 0), ...);
+    return e;
+}
+
+template <typename Real, int... Ns>
+hipError_t dispatch_fused(int N, const void* psi, int64_t x0, int64_t xc, double* S,
+                          hipStream_t st, std::integer_sequence<int, Ns...>) {
+    constexpr int RB = Geo<Real>::RB;
+    hipError_t e = hipErrorInvalidValue;
+    ((N == Ns + RB ? (e = launch_fused_n<Real, Ns + RB>(psi, x0, xc, S, st), 0) : 0), ...);
+    return e;
+}
+
+template <typename Real, int... Hs>
+hipError_t dispatch_pass2(int H, const void* scratch, int N, int cs, int P, double* part,
+                          hipStream_t st, std::integer_sequence<int, Hs...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((H == Hs + 1 ? (e = launch_pass2_h<Real, Hs + 1>(scratch, N, cs, P, part, st), 0) : 0), ...);
+    return e;
+}
+
+}  // namespace
+
+template <typename Real>
+hipError_t launch_shift_kernel(const void* psi, int N, int64_t x0, int64_t xc, double* S,
+                               hipStream_t st) {
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    if (N < RB)
+        return dispatch_tiny<Real>(N, psi, x0, xc, S, st, std::make_integer_sequence<int, RB - 1>{});
+    if (N <= TB)
+        return dispatch_fused<Real>(N, psi, x0, xc, S, st,
+                                    std::make_integer_sequence<int, TB - RB + 1>{});
+    return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t launch_pass1(const void* psi, int N, int64_t x0, int cs, void* scratch, hipStream_t st) {
+    using C = typename CT<Real>::T;
+    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    if (N <= TB || N > kMaxN) return hipErrorInvalidValue;
+    const int64_t rows = (int64_t)1 << (N - TB);
+    hipLaunchKernelGGL((k_pass1<Real>), dim3((unsigned)(rows * cs)), dim3(1 << (TB - RB)), 0, st,
+                       (const C*)psi, N, x0, cs, (C*)scratch);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_pass2(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
+    constexpr int TB = Geo<Real>::TB;
+    if (N <= TB || N > kMaxN) return hipErrorInvalidValue;
+    return dispatch_pass2<Real>(N - TB, scratch, N, cs, P, part, st,
+                                std::make_integer_sequence<int, kMaxN - TB>{});
+}
+
+template hipError_t launch_shift_kernel<float>(const void*, int, int64_t, int64_t, double*,
+                                               hipStream_t);
+template hipError_t launch_shift_kernel<double>(const void*, int, int64_t, int64_t, double*,
+                                                hipStream_t);
+template hipError_t launch_pass1<float>(const void*, int, int64_t, int, void*, hipStream_t);
+template hipError_t launch_pass1<double>(const void*, int, int64_t, int, void*, hipStream_t);
+template hipError_t launch_pass2<float>(const void*, int, int, int, double*, hipStream_t);
+template hipError_t launch_pass2<double>(const void*, int, int, int, double*, hipStream_t);
+
+hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
+                          hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (in_dtype == kC128 && out_dtype == kC64)
+        hipLaunchKernelGGL((k_convert<double2, float2>), dim3(blocks), dim3(256), 0, st,
+                           (const double2*)in, (float2*)out, n);
+    else if (in_dtype == kC64 && out_dtype == kC128)
+        hipLaunchKernelGGL((k_convert<float2, double2>), dim3(blocks), dim3(256), 0, st,
+                           (const float2*)in, (double2*)out, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, double* part,
+                       double* flag, hipStream_t st) {
+    const int64_t per = (n + nblocks - 1) / nblocks;
+    if (dtype == kC64)
+        hipLaunchKernelGGL((k_norm_part<float2>), dim3(nblocks), dim3(kRedThreads), 0, st,
+                           (const float2*)psi, n, per, part, flag);
+    else
+        hipLaunchKernelGGL((k_norm_part<double2>), dim3(nblocks), dim3(kRedThreads), 0, st,
+                           (const double2*)psi, n, per, part, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* v, int64_t nshift, int P, int nblocks, double* part,
+                      double* Sx, hipStream_t st) {
+    const int64_t per = (nshift + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL(k_sum_part, dim3(nblocks), dim3(kRedThreads), 0, st, v, nshift, P, per,
+                       part, Sx);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, hipStream_t st) {
+    hipLaunchKernelGGL(k_group_sum, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, part, ns,
+                       P, Sx);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
+                        int nn, int N, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, spart, ns, npart, nflag, nn, N,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace sre2

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/sre2.h declares, and rejects bad arguments on the host before any
+device work (no compute calls are made here)."""
+import ctypes
+
+import pytest
+
+import paper_2512_24685_amd as sre2
+
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+@pytest.fixture(scope="module")
+def L():
+    return sre2.lib()
+
+
+@pytest.fixture()
+def ctx(L):
+    c = sre2.Context(0)
+    yield c
+    c.close()
+
+
+def test_exports_every_header_function(L):
+    names = sre2.header_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_strerror(L):
+    assert L.sre2_version() >= 100
+    for code in range(0, -10, -1):
+        s = L.sre2_strerror(code)
+        assert s and s != b"unknown status code"
+    assert L.sre2_strerror(12345) == b"unknown status code"
+
+
+def test_create_destroy_without_device_work(L):
+    p = ctypes.c_void_p()
+    assert L.sre2_create(None, 0) == sre2.EINVAL
+    assert L.sre2_create(ctypes.byref(p), -1) == sre2.EINVAL
+    assert L.sre2_create(ctypes.byref(p), 0) == sre2.OK
+    assert L.sre2_set_scratch_limit(p, 1 << 20) == sre2.OK
+    assert L.sre2_destroy(p) == sre2.OK
+    assert L.sre2_destroy(None) == sre2.OK
+    assert L.sre2_set_scratch_limit(None, 1) == sre2.EINVAL
+
+
+def test_m2_argument_validation(L, ctx):
+    out = FAKE
+    h = ctx.handle
+    assert L.sre2_m2(None, FAKE, 10, 0, 0, None, out, None) == sre2.EINVAL
+    assert L.sre2_m2(h, None, 10, 0, 0, None, out, None) == sre2.EINVAL
+    assert L.sre2_m2(h, FAKE, 0, 0, 0, None, out, None) == sre2.EINVAL
+    assert L.sre2_m2(h, FAKE, sre2.MAX_N + 1, 0, 0, None, out, None) == sre2.EINVAL
+    assert L.sre2_m2(h, FAKE, 10, 7, 0, None, out, None) == sre2.EDTYPE
+    assert L.sre2_m2(h, FAKE, 10, 0, 99, None, out, None) == sre2.EFORM
+    assert L.sre2_m2(h, FAKE, 10, 0, 0, None, None, None) == sre2.EINVAL
+
+
+def test_partials_argument_validation(L, ctx):
+    h = ctx.handle
+    assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 17, None, FAKE) == sre2.EINVAL
+    assert L.sre2_partials(h, FAKE, 4, 0, 0, -1, 2, None, FAKE) == sre2.EINVAL
+    assert L.sre2_partials(h, FAKE, 4, 0, 0, 15, 2, None, FAKE) == sre2.EINVAL
+    assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 4, None, None) == sre2.EINVAL
+    assert L.sre2_partials(h, FAKE, 4, 3, 0, 0, 4, None, FAKE) == sre2.EDTYPE
+
+
+def test_batched_argument_validation(L, ctx):
+    h = ctx.handle
+    ptrs = (ctypes.c_void_p * 2)(0x10000, 0x20000)
+    Ns = (ctypes.c_int * 2)(8, 40)
+    assert L.sre2_m2_batched(h, ptrs, Ns, 0, 0, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 0, None, FAKE) == sre2.EINVAL  # N=40
+    Ns[1] = 9
+    assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 5, None, FAKE) == sre2.EFORM
+    assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 0, None, None) == sre2.EINVAL
+
+
+def test_workspace_bytes(L):
+    assert L.sre2_workspace_bytes(0, 0, 0) == 0
+    assert L.sre2_workspace_bytes(10, 9, 0) == 0
+    small = L.sre2_workspace_bytes(10, sre2.C64, sre2.FORMS["fp32"])
+    big = L.sre2_workspace_bytes(20, sre2.C64, sre2.FORMS["fp32"])
+    assert 0 < small < big
+    # FP64 on complex64 input stages a widened copy
+    assert (L.sre2_workspace_bytes(12, sre2.C64, sre2.FORMS["fp64"])
+            > L.sre2_workspace_bytes(12, sre2.C128, sre2.FORMS["fp64"]))
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        sre2.m2(torch.zeros(16, dtype=torch.complex64))

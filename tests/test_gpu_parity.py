@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (bars of the method's two precisions):
+  * FP64 form:  |dM2| <= 1e-9, per-shift S_x relative <= 1e-11.
+  * FP32 form:  |dM2| <= 1e-5, per-shift S_x relative <= 1e-4 (FP32 butterflies
+    over up to 26 stages; S_x = sum |W|^4 is dominated by the largest |W|,
+    whose relative error is a few FP32 ulps times sqrt(N)).
+The oracle always receives the exact bytes the GPU receives, upcast to FP64.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2512_24685_amd as sre2  # noqa: E402
+
+LOG43 = np.log2(4.0 / 3.0)
+TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9}
+TOL_SX = {"fp32": 1e-4, "fp64": 1e-11}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+
+
+def dev(psi):
+    return torch.from_numpy(np.ascontiguousarray(psi)).to("cuda")
+
+
+def case_id(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sre2.lib()
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("N", list(range(1, 17)))
+def test_haar_m2_and_partials(oracle_mod, form, N):
+    dtype = np.complex64 if form == "fp32" else np.complex128
+    psi = W.haar(N, 1000 + N, dtype)
+    case_id("haar", N, form)
+    r = sre2.m2(dev(psi), form=form, partials=True)
+    S_ref, n_ref = oracle_mod.total(psi)
+    m_ref = oracle_mod.m2_from_total(S_ref, n_ref, N)
+    assert r.status == 0
+    assert abs(r.m2 - m_ref) <= TOL_M2[form], (r.m2, m_ref)
+    assert abs(r.n - n_ref) <= 1e-12 * n_ref
+    Sx = r.partials.cpu().numpy()
+    ref = oracle_mod.partials(psi)
+    rel = np.max(np.abs(Sx - ref) / ref)
+    assert rel <= TOL_SX[form], rel
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_input_dtype_conversion(oracle_mod, form, dtype):
+    for N in (9, 15):
+        psi = W.haar(N, 77, dtype)
+        case_id("dtype", N, form, np.dtype(dtype).name)
+        r = sre2.m2(dev(psi), form=form)
+        ref = oracle_mod.m2(psi)
+        tol = TOL_M2[form] if (form == "fp32" or dtype == np.complex128) else 1e-9
+        assert abs(r.m2 - ref) <= max(tol, 1e-9)
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("N", [2, 4, 5, 10, 14, 16])
+def test_closed_forms(form, N):
+    case_id("closed", N, form)
+    r = sre2.m2(dev(W.t_product(N, np.complex64)), form=form)
+    assert abs(r.m2 - N * LOG43) <= 1e-6
+    r = sre2.m2(dev(W.t_product(N, np.complex128)), form=form)
+    assert abs(r.m2 - N * LOG43) <= (1e-12 if form == "fp64" else 1e-6)
+    g = sre2.m2(dev(W.graph(N, 900 + N, dtype=np.complex64)), form=form)
+    if N % 2 == 0:
+        assert g.m2 == 0.0  # every value is an exact dyadic in both forms
+    else:
+        assert abs(g.m2) <= 1e-6
+    m = min(N, 5)
+    psi, _ = W.graph_t(N, m, 50 + N, dtype=np.complex64)
+    r = sre2.m2(dev(psi), form=form)
+    assert abs(r.m2 - m * LOG43) <= 1e-6
+
+
+def test_scale_invariance_and_bad_inputs(oracle_mod):
+    psi = W.haar(12, 5)
+    case_id("scale")
+    a = sre2.m2(dev(psi * (3.0 - 1.0j)), form="fp64")
+    assert abs(a.m2 - oracle_mod.m2(psi)) <= 1e-9
+    z = sre2.m2(dev(np.zeros(1 << 8, np.complex64)))
+    assert z.status == 1 and np.isnan(z.m2)
+    bad = W.haar(8, 1, np.complex64)
+    bad[3] = np.nan
+    b = sre2.m2(dev(bad))
+    assert b.status == 1 and np.isnan(b.m2)
+    inf = W.haar(16, 1, np.complex64)
+    inf[5] = np.inf
+    assert sre2.m2(dev(inf)).status == 1
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("N,x0,xc", [(3, 1, 5), (9, 7, 301), (13, 4095, 3), (15, 100, 37),
+                                     (17, 65530, 6)])
+def test_shift_ranges_ragged(oracle_mod, form, N, x0, xc):
+    psi = W.haar(N, 3 + N, np.complex64)
+    case_id("range", N, x0, xc, form)
+    got = sre2.shift_partials(dev(psi), x0, xc, form=form).cpu().numpy()
+    ref = oracle_mod.partials(psi, np.arange(x0, x0 + xc))
+    assert np.max(np.abs(got - ref) / ref) <= TOL_SX[form]
+
+
+def test_shard_sum_equals_whole():
+    """Per-GPU shift shards (design of the multi-GPU split) add up to S."""
+    psi = dev(W.haar(16, 8, np.complex64))
+    case_id("shards")
+    r = sre2.m2(psi)
+    parts = [sre2.shift_partials(psi, g << 13, 1 << 13).double().sum().item() for g in range(8)]
+    assert abs(sum(parts) - r.S) <= 1e-12 * r.S
+
+
+def test_determinism_and_batched():
+    psis = [dev(W.haar(N, 60 + N, np.complex64)) for N in (3, 8, 12, 15, 16)]
+    case_id("determinism")
+    single = [sre2.m2(p) for p in psis]
+    again = [sre2.m2(p) for p in psis]
+    batch = sre2.m2_batched(psis)
+    for a, b, c in zip(single, again, batch):
+        assert a.m2 == b.m2 and a.S == b.S
+        assert a.m2 == c.m2 and a.S == c.S
+
+
+def test_scratch_limit_does_not_change_result():
+    psi = dev(W.haar(17, 4, np.complex64))
+    case_id("scratch-limit")
+    a = sre2.m2(psi)
+    ctx = sre2.Context(0)
+    ctx.set_scratch_limit(1 << 20)  # one slab at a time
+    b = sre2.m2(psi, ctx=ctx)
+    ctx.close()
+    assert abs(a.m2 - b.m2) <= 1e-12
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _sha(psi):
+    return hashlib.sha256(np.ascontiguousarray(psi).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_n20_full_size(oracle_mod, form):
+    """Benchmark shape (N=20, complex64, default launch configuration)."""
+    g = _golden()
+    psi = W.haar(20, W.config_seed(3), np.complex64)
+    d = dev(psi)
+    case_id("n20", form)
+    r = sre2.m2(d, form=form, partials=True)
+    assert r.status == 0
+    rec = g.get("haar20_cfg3_sampled")
+    xs = rec["shifts"] if rec and rec["sha256"] == _sha(psi) else [0, 1, 12345, (1 << 20) - 1]
+    ref = np.array(rec["partials"]) if rec and rec["sha256"] == _sha(psi) else \
+        oracle_mod.partials(psi, xs)
+    got = r.partials.cpu().numpy()[xs]
+    assert np.max(np.abs(got - ref) / ref) <= TOL_SX[form]
+    full = g.get("haar20_cfg3")
+    if full and full["sha256"] == _sha(psi):
+        assert abs(r.m2 - full["m2"]) <= TOL_M2[form], (r.m2, full["m2"])
+    else:
+        assert abs(r.m2 - (np.log2(2 ** 20 + 3) - 2)) < 1e-3  # Haar law (sanity)
+    psi_t, _ = W.graph_t(20, 10, W.config_seed(3) + 1, dtype=np.complex64)
+    rt = sre2.m2(dev(psi_t), form=form)
+    assert abs(rt.m2 - 10 * LOG43) <= 1e-6
+
+
+@pytest.mark.parametrize("N", [22, 24])
+def test_large_n_sampled_shifts(N):
+    g = _golden()
+    name = f"haar{N}_cfg5_sampled"
+    seed = W.config_seed(5) + (0 if N == 22 else 1)
+    psi = W.haar(N, seed, np.complex64)
+    rec = g.get(name)
+    if not rec or rec["sha256"] != _sha(psi):
+        pytest.skip("no stored oracle values for this input")
+    d = dev(psi)
+    case_id("large", N)
+    xs = rec["shifts"][:: max(1, len(rec["shifts"]) // 12)]
+    ref = dict(zip(rec["shifts"], rec["partials"]))
+    for x in xs:
+        got = sre2.shift_partials(d, x, 1).item()
+        assert abs(got - ref[x]) <= TOL_SX["fp32"] * ref[x], x

@@ -1,0 +1,259 @@
+"""CPU checks of the GPU tile engine's layout plans (no GPU needed).
+
+The constexpr plan builder of the kernels (paper_2512_24685_amd/csrc/sre2_plan.h)
+is compiled into a small host probe.  The tests then replay, with numpy, the
+exact index arithmetic of the kernels - global load mapping, register
+butterflies, swizzled LDS transposes between rounds, final mapping, two-pass
+scratch layout - and compare with the Walsh-Hadamard transform over the same
+bits and with the oracle's per-shift sums.  They also check that every round's
+LDS accesses hit distinct bank slots within each group of 2^SB lanes.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "plan_probe.cpp")
+
+
+@pytest.fixture(scope="module")
+def probe(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("probe") / "plan_probe.so")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-o", so, SRC], check=True)
+    lib = ctypes.CDLL(so)
+    lib.probe_plan.restype = ctypes.c_int
+    lib.probe_swz.restype = ctypes.c_uint
+    return lib
+
+
+def geo(lib, precision):
+    tb, rb, sb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib.probe_geo(precision, ctypes.byref(tb), ctypes.byref(rb), ctypes.byref(sb))
+    return tb.value, rb.value, sb.value
+
+
+def plan(lib, tb, rb, sb, lo, hi):
+    out = (ctypes.c_uint * 32)()
+    n = lib.probe_plan(tb, rb, sb, lo, hi, out)
+    return [tuple(out[4 * j:4 * j + 4]) for j in range(n)]
+
+
+def pdep(v: np.ndarray, mask: int) -> np.ndarray:
+    r = np.zeros_like(v)
+    k = 0
+    for b in range(32):
+        if (mask >> b) & 1:
+            r |= ((v >> k) & 1) << b
+            k += 1
+    return r
+
+
+def swz_np(sb, e):
+    h = e >> sb
+    f = np.zeros_like(e)
+    while np.any(h):
+        f ^= h & ((1 << sb) - 1)
+        h >>= sb
+    return e ^ f
+
+
+def mapping(rd, tb, rb):
+    T = 1 << (tb - rb)
+    t = np.arange(T, dtype=np.int64)
+    base = pdep(t & 63, rd[2]) | pdep(t >> 6, rd[3])
+    i = np.arange(1 << rb, dtype=np.int64)
+    return base[:, None] | pdep(i, rd[0])[None, :]
+
+
+def bfly(V, reg, bf):
+    V = V.copy()
+    for b in range(32):
+        if (bf >> b) & 1:
+            rbit = bin(reg & ((1 << b) - 1)).count("1")
+            i = np.arange(V.shape[1])
+            lo = i[((i >> rbit) & 1) == 0]
+            hi = lo | (1 << rbit)
+            a, c = V[:, lo].copy(), V[:, hi].copy()
+            V[:, lo], V[:, hi] = a + c, a - c
+    return V
+
+
+def run_tile(X, rounds, tb, rb, sb):
+    """Replay one tile through the plan; returns the tile after the transform."""
+    E = [mapping(rd, tb, rb) for rd in rounds]
+    V = X[E[0]]
+    V = bfly(V, rounds[0][0], rounds[0][1])
+    for j in range(1, len(rounds)):
+        lds = np.full(1 << tb, np.nan + 0j)
+        lds[swz_np(sb, E[j - 1])] = V
+        V = lds[swz_np(sb, E[j])]
+        V = bfly(V, rounds[j][0], rounds[j][1])
+    out = np.empty_like(X)
+    out[E[-1]] = V
+    return out
+
+
+def wht_bits(X, lo, hi):
+    """Unnormalised Walsh-Hadamard transform along index bits [lo, hi)."""
+    X = X.copy()
+    for b in range(lo, hi):
+        Y = X.reshape(-1, 2, 1 << b)
+        a, c = Y[:, 0, :].copy(), Y[:, 1, :].copy()
+        Y[:, 0, :], Y[:, 1, :] = a + c, a - c
+        X = Y.reshape(-1)
+    return X
+
+
+def test_wht_bits_helper_is_sylvester():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    assert np.allclose(wht_bits(x, 0, 6), scipy.linalg.hadamard(64) @ x)
+    # transform along bits [2, 5) only = I_2 (x) H_8 (x) I_4
+    H = np.kron(np.kron(np.eye(2), scipy.linalg.hadamard(8)), np.eye(4))
+    assert np.allclose(wht_bits(x, 2, 5), H @ x)
+
+
+def all_plans(lib):
+    for prec in (0, 1):
+        tb, rb, sb = geo(lib, prec)
+        for N in range(rb, tb + 1):
+            yield prec, "fused", N, (tb, rb, sb, 0, N)
+        yield prec, "pass1", tb, (tb, rb, sb, 0, tb)
+        for H in range(1, 26 - tb + 1):
+            yield prec, "pass2", H, (tb, rb, sb, tb - H, tb)
+
+
+def test_plan_structure(probe):
+    for prec, kind, par, args in all_plans(probe):
+        tb, rb, sb, lo, hi = args
+        rounds = plan(probe, *args)
+        full = (1 << tb) - 1
+        tmask = sum(1 << b for b in range(lo, hi))
+        seen = 0
+        for reg, bf, lane, wave in rounds:
+            assert reg & lane == 0 and reg & wave == 0 and lane & wave == 0
+            assert reg | lane | wave == full
+            assert bin(reg).count("1") == rb and bin(lane).count("1") == 6
+            assert bf & ~reg == 0 and bf & seen == 0
+            seen |= bf
+        assert seen == tmask, (prec, kind, par)
+        if kind == "fused":  # last round holds one shift per thread
+            assert rounds[-1][0] & ~((1 << par) - 1) == 0
+        # first round: lanes on the lowest tile bits outside the registers
+        reg0, _, lane0, _ = rounds[0]
+        free = [b for b in range(tb) if not (reg0 >> b) & 1]
+        low = sum(1 << b for b in free[:4])
+        assert lane0 & low == low, (prec, kind, par)  # coalesced global access
+
+
+def test_swizzle_bijective_and_linear(probe):
+    for sb in (4, 5):
+        e = np.arange(1 << 14, dtype=np.int64)
+        s = np.array([probe.probe_swz(sb, int(v)) for v in e[:4096]])
+        assert np.array_equal(s, swz_np(sb, e[:4096]))
+        full = swz_np(sb, e)
+        assert np.array_equal(np.sort(full), e)
+        a, b = 0x1234 & 0x3FFF, 0x0F0F & 0x3FFF
+        assert swz_np(sb, np.array([a ^ b]))[0] == swz_np(sb, np.array([a]))[0] ^ swz_np(sb, np.array([b]))[0]
+
+
+def test_lds_bank_slots_distinct(probe):
+    for prec, kind, par, args in all_plans(probe):
+        tb, rb, sb, lo, hi = args
+        rounds = plan(probe, *args)
+        if len(rounds) == 1:
+            continue
+        for rd in rounds:
+            E = swz_np(sb, mapping(rd, tb, rb))
+            slots = E & ((1 << sb) - 1)
+            g = 1 << sb
+            T = E.shape[0]
+            for t0 in range(0, T, g):
+                blk = slots[t0:t0 + g]  # lanes of one group, every register index
+                for i in range(blk.shape[1]):
+                    assert len(set(blk[:, i].tolist())) == g, (prec, kind, par, rd, t0, i)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tile_transform_matches_wht(probe, prec):
+    tb, rb, sb = geo(probe, prec)
+    rng = np.random.default_rng(prec)
+    X = rng.standard_normal(1 << tb) + 1j * rng.standard_normal(1 << tb)
+    for N in sorted({rb, rb + 1, (rb + tb) // 2, tb - 1, tb}):
+        out = run_tile(X, plan(probe, tb, rb, sb, 0, N), tb, rb, sb)
+        assert np.allclose(out, wht_bits(X, 0, N)), N
+    for H in (1, 3, rb, rb + 1, 2 * rb + 1, 26 - tb):
+        out = run_tile(X, plan(probe, tb, rb, sb, tb - H, tb), tb, rb, sb)
+        assert np.allclose(out, wht_bits(X, tb - H, tb)), H
+
+
+def emulate_fused_partials(probe, psi, prec):
+    """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-N) shifts)."""
+    tb, rb, sb = geo(probe, prec)
+    N = psi.size.bit_length() - 1
+    rounds = plan(probe, tb, rb, sb, 0, N)
+    spt = 1 << (tb - N)
+    d = 1 << N
+    S = np.zeros(d)
+    e = np.arange(1 << tb)
+    k = e & (d - 1)
+    for t0 in range(0, d, spt):
+        x = t0 + (e >> N)
+        valid = x < d
+        X = np.where(valid, np.conj(psi[(k ^ x) % d]) * psi[k], 0)
+        out = run_tile(X, rounds, tb, rb, sb)
+        q = np.abs(out) ** 4
+        for j in range(spt):
+            if t0 + j < d:
+                S[t0 + j] = q[j * d:(j + 1) * d].sum()
+    return S
+
+
+def emulate_two_pass_partials(probe, psi, prec, xs):
+    """Per-shift sums as k_pass1 / k_pass2 index them (row slab, then columns)."""
+    tb, rb, sb = geo(probe, prec)
+    N = psi.size.bit_length() - 1
+    H = N - tb
+    p1 = plan(probe, tb, rb, sb, 0, tb)
+    p2 = plan(probe, tb, rb, sb, tb - H, tb)
+    e = np.arange(1 << tb)
+    out = []
+    for x in xs:
+        slab = np.empty(1 << N, dtype=np.complex128)
+        for row in range(1 << H):
+            rowbase = row << tb
+            prow = rowbase ^ (x & ~((1 << tb) - 1))
+            X = np.conj(psi[prow + (e ^ (x & ((1 << tb) - 1)))]) * psi[rowbase + e]
+            slab[rowbase:rowbase + (1 << tb)] = run_tile(X, p1, tb, rb, sb)
+        cb = tb - H
+        acc = 0.0
+        for ct in range(1 << H):
+            src = (e >> cb << tb) + (ct << cb) + (e & ((1 << cb) - 1))
+            acc += np.sum(np.abs(run_tile(slab[src], p2, tb, rb, sb)) ** 4)
+        out.append(acc)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec,N", [(0, 6), (0, 9), (1, 5), (1, 8)])
+def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N):
+    psi = W.haar(N, 42 + N)
+    S = emulate_fused_partials(probe, psi, prec)
+    ref = oracle_mod.partials(psi)
+    assert np.allclose(S, ref, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec):
+    tb, _, _ = geo(probe, prec)
+    N = tb + 2
+    psi = W.haar(N, 7)
+    xs = [0, 1, (1 << N) - 1, 0x2A5A % (1 << N), 1 << (N - 1)]
+    S = emulate_two_pass_partials(probe, psi, prec, xs)
+    ref = oracle_mod.partials(psi, xs)
+    assert np.allclose(S, ref, rtol=1e-11, atol=0)
