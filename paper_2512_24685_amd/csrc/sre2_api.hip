@@ -88,7 +88,12 @@ bool dtype_ok(int dtype) { return dtype == SRE2_C64 || dtype == SRE2_C128; }
 int elem_bytes(int dtype) { return dtype == SRE2_C64 ? 8 : 16; }
 int work_dtype(int form) { return form == SRE2_FORM_FP64 ? kC128 : kC64; }
 
-int tile_bits(int form) { return form == SRE2_FORM_FP64 ? Geo<double>::TB : Geo<float>::TB; }
+int fused_max(int form) {
+    return form == SRE2_FORM_FP64 ? fused_max_n<double>() : fused_max_n<float>();
+}
+int row_bits(int form) {
+    return form == SRE2_FORM_FP64 ? pass1_row_bits<double>() : pass1_row_bits<float>();
+}
 
 // Two-pass chunking: shifts per chunk (power of two) and column groups per shift.
 struct Chunking {
@@ -98,14 +103,13 @@ struct Chunking {
 
 Chunking chunking(int N, int form, int64_t x_count, size_t limit) {
     Chunking c;
-    const int TB = tile_bits(form);
-    if (N <= TB) return c;
+    if (N <= fused_max(form)) return c;
     const size_t slab = (size_t(1) << N) * (size_t)elem_bytes(work_dtype(form));
     int64_t cs = 1;
     while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << 14))
         cs *= 2;
     c.cs = cs;
-    const int H = N - TB;
+    const int H = N - row_bits(form);
     int P = 1;
     while (cs * P < 2048 && P * 2 <= (1 << H)) P *= 2;
     c.P = P;
@@ -149,6 +153,7 @@ int validate(const sre2_ctx* ctx, const void* psi, int N, int dtype, int form) {
     if (N < 1 || N > SRE2_MAX_N) return SRE2_EINVAL;
     if (!dtype_ok(dtype)) return SRE2_EDTYPE;
     if (!form_ok(form)) return SRE2_EFORM;
+    if (N > (form == SRE2_FORM_FP64 ? max_n<double>() : max_n<float>())) return SRE2_EFORM;
     return SRE2_OK;
 }
 
@@ -175,9 +180,8 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
 // S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).
 int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
                double* Sx, hipStream_t st) {
-    const int TB = tile_bits(form);
     const bool f64 = form == SRE2_FORM_FP64;
-    if (N <= TB) {
+    if (N <= fused_max(form)) {
         Timed tm(ctx, st, SRE2_KIND_SHIFT);
         return hip_status(f64 ? launch_shift_kernel<double>(work, N, x0, xc, Sx, st)
                               : launch_shift_kernel<float>(work, N, x0, xc, Sx, st));

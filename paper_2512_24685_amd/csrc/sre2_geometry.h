@@ -1,0 +1,110 @@
+// sre2_geometry.h - tile geometry of every kernel of libsre2 (compile-time).
+// Shared by the kernels and by the host-side plan checks, so both see the
+// same layouts.
+#pragma once
+#include "sre2_plan.h"
+
+namespace sre2 {
+
+constexpr int kMaxNAll = 26;
+
+// ---------------------------------------------------------------------------
+// Tile geometry per kernel (compile-time; the macros exist for tuning sweeps).
+//   RB_*        log2 of complex values per thread
+//   FUSED_MIN   smallest fused tile (tiles of smaller N hold several shifts)
+//   FUSED_MAX   largest N evaluated by the fused kernel
+//   ROW         row bits L of pass 1 (its tile is exactly one row)
+//   P2_MIN      smallest pass-2 tile; a pass-2 tile holds all 2^H rows and at
+//               least 16 consecutive columns when the LDS allows it
+// ---------------------------------------------------------------------------
+#ifndef SRE2_F32_RB_FUSED
+#define SRE2_F32_RB_FUSED 5
+#endif
+#ifndef SRE2_F32_FUSED_MIN
+#define SRE2_F32_FUSED_MIN 12
+#endif
+#ifndef SRE2_F32_FUSED_MAX
+#define SRE2_F32_FUSED_MAX 14
+#endif
+#ifndef SRE2_F32_ROW
+#define SRE2_F32_ROW 12
+#endif
+#ifndef SRE2_F32_RB1
+#define SRE2_F32_RB1 5
+#endif
+#ifndef SRE2_F32_RB2
+#define SRE2_F32_RB2 5
+#endif
+#ifndef SRE2_F32_P2_MIN
+#define SRE2_F32_P2_MIN 12
+#endif
+#ifndef SRE2_F64_RB_FUSED
+#define SRE2_F64_RB_FUSED 4
+#endif
+#ifndef SRE2_F64_FUSED_MIN
+#define SRE2_F64_FUSED_MIN 11
+#endif
+#ifndef SRE2_F64_FUSED_MAX
+#define SRE2_F64_FUSED_MAX 13
+#endif
+#ifndef SRE2_F64_ROW
+#define SRE2_F64_ROW 11
+#endif
+#ifndef SRE2_F64_RB1
+#define SRE2_F64_RB1 4
+#endif
+#ifndef SRE2_F64_RB2
+#define SRE2_F64_RB2 4
+#endif
+#ifndef SRE2_F64_P2_MIN
+#define SRE2_F64_P2_MIN 11
+#endif
+
+template <typename Real> struct Tune;
+template <> struct Tune<float> {
+    static constexpr int RBF = SRE2_F32_RB_FUSED, FMIN = SRE2_F32_FUSED_MIN;
+    static constexpr int FMAX = SRE2_F32_FUSED_MAX, ROW = SRE2_F32_ROW;
+    static constexpr int RB1 = SRE2_F32_RB1, RB2 = SRE2_F32_RB2, P2MIN = SRE2_F32_P2_MIN;
+};
+template <> struct Tune<double> {
+    static constexpr int RBF = SRE2_F64_RB_FUSED, FMIN = SRE2_F64_FUSED_MIN;
+    static constexpr int FMAX = SRE2_F64_FUSED_MAX, ROW = SRE2_F64_ROW;
+    static constexpr int RB1 = SRE2_F64_RB1, RB2 = SRE2_F64_RB2, P2MIN = SRE2_F64_P2_MIN;
+};
+
+template <typename Real>
+constexpr int fused_tb(int N) {
+    return N > Tune<Real>::FMIN ? N : Tune<Real>::FMIN;
+}
+template <typename Real>
+constexpr int pass2_tb(int H) {
+    int tb = H + 4 > Tune<Real>::P2MIN ? H + 4 : Tune<Real>::P2MIN;
+    if (tb > Prec<Real>::MAXTB) tb = Prec<Real>::MAXTB;
+    if (tb < H) tb = H;
+    if (tb < Tune<Real>::RB2 + 6) tb = Tune<Real>::RB2 + 6;
+    return tb;
+}
+
+static_assert(Tune<float>::FMAX <= Prec<float>::MAXTB && Tune<double>::FMAX <= Prec<double>::MAXTB);
+static_assert(Tune<float>::ROW <= Tune<float>::FMAX && Tune<double>::ROW <= Tune<double>::FMAX);
+// every tile holds at least one full wave of threads
+static_assert(Tune<float>::FMIN >= Tune<float>::RBF + 6 && Tune<double>::FMIN >= Tune<double>::RBF + 6);
+static_assert(Tune<float>::ROW >= Tune<float>::RB1 + 6 && Tune<double>::ROW >= Tune<double>::RB1 + 6);
+// Largest N per precision: a pass-2 tile must hold all 2^(N - ROW) rows.
+template <typename Real>
+constexpr int max_n_of() {
+    return kMaxNAll < Tune<Real>::ROW + Prec<Real>::MAXTB ? kMaxNAll : Tune<Real>::ROW + Prec<Real>::MAXTB;
+}
+
+// A pass-2 tile reads whole columns inside one row of pass 1's output.
+template <typename Real>
+constexpr bool pass2_tiles_fit() {
+    for (int H = 1; H <= max_n_of<Real>() - Tune<Real>::ROW; ++H) {
+        const int tb = pass2_tb<Real>(H);
+        if (tb < H || tb - H > Tune<Real>::ROW || tb > Prec<Real>::MAXTB) return false;
+    }
+    return true;
+}
+static_assert(pass2_tiles_fit<float>() && pass2_tiles_fit<double>());
+
+}  // namespace sre2

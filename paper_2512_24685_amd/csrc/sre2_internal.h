@@ -11,6 +11,12 @@ constexpr int kMaxN = 26;
 constexpr int kC64 = 0;
 constexpr int kC128 = 1;
 
+// Largest N handled by the tiny/fused kernels, and the row bits L of pass 1
+// (two-pass: N > fused_max_n; pass 2 transforms the top N - L bits).
+template <typename Real> int fused_max_n();
+template <typename Real> int max_n();
+template <typename Real> int pass1_row_bits();
+
 // S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (N < RB) or fused
 // kernel (N <= TB).
 template <typename Real>

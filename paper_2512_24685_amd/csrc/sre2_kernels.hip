@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include "sre2_plan.h"
+#include "sre2_geometry.h"
 #include "sre2_internal.h"
 
 namespace sre2 {
@@ -92,27 +93,24 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
     for (int i = 0; i < (1 << RB); ++i) v[i] = lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))];
 }
 
-// Rounds 1 .. nrounds-1 of a plan: LDS transpose, then butterflies.
-template <typename Real, int PK, int J>
-struct RoundRunner;
-
-// Plan selector: PK encodes (kind, parameter) so that plans are constexpr.
-//   PK = 1000 + N : fused over bits [0, N)
-//   PK = 2000     : pass 1 over all TB bits
-//   PK = 3000 + H : pass 2 over the top H bits
-template <typename Real, int PK>
+// Plan selector (PK encodes the kind so that plans stay constexpr):
+//   PK = 1000 + N : whole transform over tile bits [0, N)        (fused)
+//   PK = 2000     : row transform over all TB tile bits          (pass 1)
+//   PK = 3000 + H : column transform over the top H tile bits    (pass 2)
+template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB, SB = Geo<Real>::SB;
+    constexpr int SB = Prec<Real>::SB;
     if (PK >= 3000) return make_plan(TB, RB, SB, TB - (PK - 3000), TB);
     if (PK >= 2000) return make_plan(TB, RB, SB, 0, TB);
     return make_plan(TB, RB, SB, 0, PK - 1000);
 }
 
-template <typename Real, int PK, int J>
+// Rounds J .. nrounds-1 of a plan: LDS transpose, then butterflies.
+template <typename Real, int TB, int RB, int PK, int J>
 struct RoundRunner {
     using C = typename CT<Real>::T;
-    static constexpr Plan P = plan_of<Real, PK>();
-    static constexpr int RB = Geo<Real>::RB, SB = Geo<Real>::SB;
+    static constexpr Plan P = plan_of<Real, TB, RB, PK>();
+    static constexpr int SB = Prec<Real>::SB;
     __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB]) {
         if constexpr (J < P.nrounds) {
             constexpr Round prev = P.r[J - 1];
@@ -122,7 +120,7 @@ struct RoundRunner {
             __syncthreads();
             lds_get<SB, RB, cur.reg, cur.lane, cur.wave>(lds, v);
             butterflies<RB, cur.reg, cur.bfly>(v);
-            RoundRunner<Real, PK, J + 1>::run(lds, v);
+            RoundRunner<Real, TB, RB, PK, J + 1>::run(lds, v);
         }
     }
 };
@@ -165,15 +163,14 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 // ---------------------------------------------------------------------------
 // Fused: RB <= N <= TB.  Tile = SPT = 2^(TB-N) consecutive shifts.
 // ---------------------------------------------------------------------------
-template <typename Real, int N>
-__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+template <typename Real, int N, int TB, int RB>
+__global__ __launch_bounds__(1 << (TB - RB))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 1000 + N;
-    constexpr Plan P = plan_of<Real, PK>();
+    constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
     constexpr int SPT = 1 << (TB - N);
@@ -202,7 +199,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
             }
         }
         butterflies<RB, r0.reg, r0.bfly>(v);
-        RoundRunner<Real, PK, 1>::run(lds, v);
+        RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) s += abs4(v[i]);
@@ -224,14 +221,13 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // shifts.  Block b -> row = b / cs, shift slot = b % cs, so neighbouring blocks
 // read the same psi rows.
 // ---------------------------------------------------------------------------
-template <typename Real>
-__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+template <typename Real, int TB, int RB>
+__global__ __launch_bounds__(1 << (TB - RB))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
     constexpr int PK = 2000;
-    constexpr Plan P = plan_of<Real, PK>();
+    constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
     __shared__ C lds[1 << TB];
@@ -255,7 +251,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, in
         }
     }
     butterflies<RB, r0.reg, r0.bfly>(v);
-    RoundRunner<Real, PK, 1>::run(lds, v);
+    RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
     C* __restrict__ out = scratch + ((uint64_t)s << N) + rowbase;
     const uint32_t base = thread_base<rl.lane, rl.wave>();
 #pragma unroll
@@ -268,15 +264,14 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, in
 // b / P, column group b % P; the group loops over its column tiles and writes
 // one FP64 partial.
 // ---------------------------------------------------------------------------
-template <typename Real, int H>
-__global__ __launch_bounds__(1 << (Geo<Real>::TB - Geo<Real>::RB))
+template <typename Real, int H, int TB, int RB>
+__global__ __launch_bounds__(1 << (TB - RB))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
              double* __restrict__ part) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 3000 + H;
-    constexpr Plan PL = plan_of<Real, PK>();
+    constexpr Plan PL = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = PL.r[0];
     constexpr int CB = TB - H;  // column bits per tile
     constexpr uint32_t CMASK = (1u << CB) - 1u;
@@ -286,7 +281,7 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
     const int64_t b = blockIdx.x;
     const int64_t s = b / P;
     const int g = (int)(b % P);
-    const int L = N - H;  // == TB
+    const int L = N - H;  // row bits of pass 1
     const int ntile = 1 << (L - CB);  // column tiles per shift
     const int per = ntile / P;
     const C* __restrict__ slab = scratch + ((uint64_t)s << N);
@@ -301,7 +296,7 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
             v[i] = src[((uint64_t)(e >> CB) << L) + (e & CMASK)];
         }
         butterflies<RB, r0.reg, r0.bfly>(v);
-        if constexpr (PL.nrounds > 1) RoundRunner<Real, PK, 1>::run(lds, v);
+        if constexpr (PL.nrounds > 1) RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) acc += abs4(v[i]);
     }
@@ -437,20 +432,20 @@ hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S, hip
 template <typename Real, int N>
 hipError_t launch_fused_n(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int TB = fused_tb<Real>(N), RB = Tune<Real>::RBF;
     constexpr int SPT = 1 << (TB - N);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL((k_fused<Real, N>), dim3((unsigned)grid), dim3(1 << (TB - RB)), 0, st,
-                       (const C*)psi, x0, xc, S);
+    hipLaunchKernelGGL((k_fused<Real, N, TB, RB>), dim3((unsigned)grid), dim3(1 << (TB - RB)), 0,
+                       st, (const C*)psi, x0, xc, S);
     return hipGetLastError();
 }
 
 template <typename Real, int H>
 hipError_t launch_pass2_h(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
-    hipLaunchKernelGGL((k_pass2<Real, H>), dim3((unsigned)((int64_t)cs * P)),
+    constexpr int TB = pass2_tb<Real>(H), RB = Tune<Real>::RB2;
+    hipLaunchKernelGGL((k_pass2<Real, H, TB, RB>), dim3((unsigned)((int64_t)cs * P)),
                        dim3(1 << (TB - RB)), 0, st, (const C*)scratch, N, P, part);
     return hipGetLastError();
 }
@@ -466,7 +461,7 @@ hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double*
 template <typename Real, int... Ns>
 hipError_t dispatch_fused(int N, const void* psi, int64_t x0, int64_t xc, double* S,
                           hipStream_t st, std::integer_sequence<int, Ns...>) {
-    constexpr int RB = Geo<Real>::RB;
+    constexpr int RB = Tune<Real>::RBF;
     hipError_t e = hipErrorInvalidValue;
     ((N == Ns + RB ? (e = launch_fused_n<Real, Ns + RB>(psi, x0, xc, S, st), 0) : 0), ...);
     return e;
@@ -483,34 +478,53 @@ hipError_t dispatch_pass2(int H, const void* scratch, int N, int cs, int P, doub
 }  // namespace
 
 template <typename Real>
+int fused_max_n() {
+    return Tune<Real>::FMAX;
+}
+template <typename Real>
+int pass1_row_bits() {
+    return Tune<Real>::ROW;
+}
+template <typename Real>
+int max_n() {
+    return max_n_of<Real>();
+}
+template int max_n<float>();
+template int max_n<double>();
+template int fused_max_n<float>();
+template int fused_max_n<double>();
+template int pass1_row_bits<float>();
+template int pass1_row_bits<double>();
+
+template <typename Real>
 hipError_t launch_shift_kernel(const void* psi, int N, int64_t x0, int64_t xc, double* S,
                                hipStream_t st) {
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
+    constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
     if (N < RB)
         return dispatch_tiny<Real>(N, psi, x0, xc, S, st, std::make_integer_sequence<int, RB - 1>{});
-    if (N <= TB)
+    if (N <= FMAX)
         return dispatch_fused<Real>(N, psi, x0, xc, S, st,
-                                    std::make_integer_sequence<int, TB - RB + 1>{});
+                                    std::make_integer_sequence<int, FMAX - RB + 1>{});
     return hipErrorInvalidValue;
 }
 
 template <typename Real>
 hipError_t launch_pass1(const void* psi, int N, int64_t x0, int cs, void* scratch, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Geo<Real>::TB, RB = Geo<Real>::RB;
-    if (N <= TB || N > kMaxN) return hipErrorInvalidValue;
+    constexpr int TB = Tune<Real>::ROW, RB = Tune<Real>::RB1;
+    if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
     const int64_t rows = (int64_t)1 << (N - TB);
-    hipLaunchKernelGGL((k_pass1<Real>), dim3((unsigned)(rows * cs)), dim3(1 << (TB - RB)), 0, st,
-                       (const C*)psi, N, x0, cs, (C*)scratch);
+    hipLaunchKernelGGL((k_pass1<Real, TB, RB>), dim3((unsigned)(rows * cs)), dim3(1 << (TB - RB)), 0,
+                       st, (const C*)psi, N, x0, cs, (C*)scratch);
     return hipGetLastError();
 }
 
 template <typename Real>
 hipError_t launch_pass2(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
-    constexpr int TB = Geo<Real>::TB;
-    if (N <= TB || N > kMaxN) return hipErrorInvalidValue;
-    return dispatch_pass2<Real>(N - TB, scratch, N, cs, P, part, st,
-                                std::make_integer_sequence<int, kMaxN - TB>{});
+    constexpr int ROW = Tune<Real>::ROW;
+    if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
+    return dispatch_pass2<Real>(N - ROW, scratch, N, cs, P, part, st,
+                                std::make_integer_sequence<int, max_n_of<Real>() - ROW>{});
 }
 
 template hipError_t launch_shift_kernel<float>(const void*, int, int64_t, int64_t, double*,

@@ -182,17 +182,16 @@ __host__ __device__ constexpr Plan make_plan(int tb, int rb, int sb, int lo, int
     return p;
 }
 
-// Tile geometry per working precision.
-template <typename Real> struct Geo;
-template <> struct Geo<float> {
-    static constexpr int TB = 14;  // 2^14 complex64 = 128 KiB of LDS
-    static constexpr int RB = 5;   // 32 complex values per thread
-    static constexpr int SB = 5;   // 8-byte slots
+// Per-precision constants: slot bits of one complex value and the largest tile
+// that fits the 160 KiB LDS (128 KiB of tile).
+template <typename Real> struct Prec;
+template <> struct Prec<float> {
+    static constexpr int SB = 5;      // 8-byte complex64 slots
+    static constexpr int MAXTB = 14;  // 2^14 complex64 = 128 KiB
 };
-template <> struct Geo<double> {
-    static constexpr int TB = 13;  // 2^13 complex128 = 128 KiB of LDS
-    static constexpr int RB = 4;   // 16 complex values per thread
-    static constexpr int SB = 4;   // 16-byte slots
+template <> struct Prec<double> {
+    static constexpr int SB = 4;      // 16-byte complex128 slots
+    static constexpr int MAXTB = 13;  // 2^13 complex128 = 128 KiB
 };
 
 }  // namespace sre2

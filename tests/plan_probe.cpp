@@ -1,23 +1,46 @@
-// Host-only probe of the tile-engine layout plans (sre2_plan.h), compiled with
-// g++ by tests/test_plan.py so the plans can be checked on a machine without a
-// GPU.  It exposes exactly the constexpr plan builder the kernels use.
+// Host-only probe of the tile-engine layout plans (sre2_plan.h) and of the
+// kernels' tile geometry (sre2_geometry.h), compiled with g++ by
+// tests/test_plan.py so the layouts can be checked without a GPU.
 #define __host__
 #define __device__
-#include "../paper_2512_24685_amd/csrc/sre2_plan.h"
+#include "../paper_2512_24685_amd/csrc/sre2_geometry.h"
+
+namespace {
+template <typename Real>
+int geometry(int kind, int param, int* tb, int* rb, int* sb) {
+    using T = sre2::Tune<Real>;
+    *sb = sre2::Prec<Real>::SB;
+    switch (kind) {
+        case 0:  // fused, param = N
+            if (param < T::RBF || param > T::FMAX) return -1;
+            *tb = sre2::fused_tb<Real>(param);
+            *rb = T::RBF;
+            return 0;
+        case 1:  // pass 1
+            *tb = T::ROW;
+            *rb = T::RB1;
+            return 0;
+        case 2:  // pass 2, param = H
+            if (param < 1 || param > sre2::max_n_of<Real>() - T::ROW) return -1;
+            *tb = sre2::pass2_tb<Real>(param);
+            *rb = T::RB2;
+            return 0;
+        case 3:  // limits: tb = largest fused N, rb = row bits, sb = largest N
+            *tb = T::FMAX;
+            *rb = T::ROW;
+            *sb = sre2::max_n_of<Real>();
+            return 0;
+    }
+    return -1;
+}
+}  // namespace
 
 extern "C" {
 
 // precision 0 = float (complex64 tiles), 1 = double (complex128 tiles)
-void probe_geo(int precision, int* tb, int* rb, int* sb) {
-    if (precision == 0) {
-        *tb = sre2::Geo<float>::TB;
-        *rb = sre2::Geo<float>::RB;
-        *sb = sre2::Geo<float>::SB;
-    } else {
-        *tb = sre2::Geo<double>::TB;
-        *rb = sre2::Geo<double>::RB;
-        *sb = sre2::Geo<double>::SB;
-    }
+int probe_geometry(int precision, int kind, int param, int* tb, int* rb, int* sb) {
+    return precision == 0 ? geometry<float>(kind, param, tb, rb, sb)
+                          : geometry<double>(kind, param, tb, rb, sb);
 }
 
 int probe_plan(int tb, int rb, int sb, int lo, int hi, unsigned* out) {

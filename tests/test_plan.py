@@ -32,9 +32,16 @@ def probe(tmp_path_factory):
     return lib
 
 
-def geo(lib, precision):
+FUSED, PASS1, PASS2, LIMITS = 0, 1, 2, 3
+
+
+def geo(lib, precision, kind, param=0):
+    """(TB, RB, SB) of a kernel: fused(N), pass1, pass2(H); LIMITS gives
+    (largest fused N, pass-1 row bits, largest N)."""
     tb, rb, sb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    lib.probe_geo(precision, ctypes.byref(tb), ctypes.byref(rb), ctypes.byref(sb))
+    rc = lib.probe_geometry(precision, kind, param, ctypes.byref(tb), ctypes.byref(rb),
+                            ctypes.byref(sb))
+    assert rc == 0, (precision, kind, param)
     return tb.value, rb.value, sb.value
 
 
@@ -120,13 +127,31 @@ def test_wht_bits_helper_is_sylvester():
 
 
 def all_plans(lib):
+    """Every (tile geometry, transform range) a compiled kernel uses."""
     for prec in (0, 1):
-        tb, rb, sb = geo(lib, prec)
-        for N in range(rb, tb + 1):
+        fmax, row, nmax = geo(lib, prec, LIMITS)
+        rbf = geo(lib, prec, FUSED, fmax)[1]
+        for N in range(rbf, fmax + 1):
+            tb, rb, sb = geo(lib, prec, FUSED, N)
             yield prec, "fused", N, (tb, rb, sb, 0, N)
+        tb, rb, sb = geo(lib, prec, PASS1)
+        assert tb == row
         yield prec, "pass1", tb, (tb, rb, sb, 0, tb)
-        for H in range(1, 26 - tb + 1):
+        for H in range(1, nmax - row + 1):
+            tb, rb, sb = geo(lib, prec, PASS2, H)
             yield prec, "pass2", H, (tb, rb, sb, tb - H, tb)
+
+
+def test_geometry_limits(probe):
+    for prec in (0, 1):
+        fmax, row, nmax = geo(probe, prec, LIMITS)
+        assert row <= fmax < nmax and nmax >= 24
+        for H in range(1, nmax - row + 1):
+            tb, rb, _ = geo(probe, prec, PASS2, H)
+            assert H <= tb and tb - H <= row and tb - rb >= 6
+        for N in range(geo(probe, prec, FUSED, fmax)[1], fmax + 1):
+            tb, rb, _ = geo(probe, prec, FUSED, N)
+            assert tb >= N and tb - rb >= 6
 
 
 def test_plan_structure(probe):
@@ -180,23 +205,18 @@ def test_lds_bank_slots_distinct(probe):
                     assert len(set(blk[:, i].tolist())) == g, (prec, kind, par, rd, t0, i)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_tile_transform_matches_wht(probe, prec):
-    tb, rb, sb = geo(probe, prec)
-    rng = np.random.default_rng(prec)
-    X = rng.standard_normal(1 << tb) + 1j * rng.standard_normal(1 << tb)
-    for N in sorted({rb, rb + 1, (rb + tb) // 2, tb - 1, tb}):
-        out = run_tile(X, plan(probe, tb, rb, sb, 0, N), tb, rb, sb)
-        assert np.allclose(out, wht_bits(X, 0, N)), N
-    for H in (1, 3, rb, rb + 1, 2 * rb + 1, 26 - tb):
-        out = run_tile(X, plan(probe, tb, rb, sb, tb - H, tb), tb, rb, sb)
-        assert np.allclose(out, wht_bits(X, tb - H, tb)), H
+def test_tile_transform_matches_wht(probe):
+    rng = np.random.default_rng(3)
+    for prec, kind, par, (tb, rb, sb, lo, hi) in all_plans(probe):
+        X = rng.standard_normal(1 << tb) + 1j * rng.standard_normal(1 << tb)
+        out = run_tile(X, plan(probe, tb, rb, sb, lo, hi), tb, rb, sb)
+        assert np.allclose(out, wht_bits(X, lo, hi)), (prec, kind, par)
 
 
 def emulate_fused_partials(probe, psi, prec):
     """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-N) shifts)."""
-    tb, rb, sb = geo(probe, prec)
     N = psi.size.bit_length() - 1
+    tb, rb, sb = geo(probe, prec, FUSED, N)
     rounds = plan(probe, tb, rb, sb, 0, N)
     spt = 1 << (tb - N)
     d = 1 << N
@@ -217,25 +237,27 @@ def emulate_fused_partials(probe, psi, prec):
 
 def emulate_two_pass_partials(probe, psi, prec, xs):
     """Per-shift sums as k_pass1 / k_pass2 index them (row slab, then columns)."""
-    tb, rb, sb = geo(probe, prec)
     N = psi.size.bit_length() - 1
-    H = N - tb
-    p1 = plan(probe, tb, rb, sb, 0, tb)
-    p2 = plan(probe, tb, rb, sb, tb - H, tb)
-    e = np.arange(1 << tb)
+    L, rb1, sb = geo(probe, prec, PASS1)
+    H = N - L
+    tb2, rb2, _ = geo(probe, prec, PASS2, H)
+    p1 = plan(probe, L, rb1, sb, 0, L)
+    p2 = plan(probe, tb2, rb2, sb, tb2 - H, tb2)
+    e1 = np.arange(1 << L)
+    e2 = np.arange(1 << tb2)
+    cb = tb2 - H
     out = []
     for x in xs:
         slab = np.empty(1 << N, dtype=np.complex128)
         for row in range(1 << H):
-            rowbase = row << tb
-            prow = rowbase ^ (x & ~((1 << tb) - 1))
-            X = np.conj(psi[prow + (e ^ (x & ((1 << tb) - 1)))]) * psi[rowbase + e]
-            slab[rowbase:rowbase + (1 << tb)] = run_tile(X, p1, tb, rb, sb)
-        cb = tb - H
+            rowbase = row << L
+            prow = rowbase ^ (x & ~((1 << L) - 1))
+            X = np.conj(psi[prow + (e1 ^ (x & ((1 << L) - 1)))]) * psi[rowbase + e1]
+            slab[rowbase:rowbase + (1 << L)] = run_tile(X, p1, L, rb1, sb)
         acc = 0.0
-        for ct in range(1 << H):
-            src = (e >> cb << tb) + (ct << cb) + (e & ((1 << cb) - 1))
-            acc += np.sum(np.abs(run_tile(slab[src], p2, tb, rb, sb)) ** 4)
+        for ct in range(1 << (L - cb)):
+            src = (e2 >> cb << L) + (ct << cb) + (e2 & ((1 << cb) - 1))
+            acc += np.sum(np.abs(run_tile(slab[src], p2, tb2, rb2, sb)) ** 4)
         out.append(acc)
     return np.array(out)
 
@@ -248,10 +270,10 @@ def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N):
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec):
-    tb, _, _ = geo(probe, prec)
-    N = tb + 2
+@pytest.mark.parametrize("prec,extra", [(0, 1), (0, 3), (1, 1), (1, 3)])
+def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec, extra):
+    fmax, _, _ = geo(probe, prec, LIMITS)
+    N = fmax + extra
     psi = W.haar(N, 7)
     xs = [0, 1, (1 << N) - 1, 0x2A5A % (1 << N), 1 << (N - 1)]
     S = emulate_two_pass_partials(probe, psi, prec, xs)
