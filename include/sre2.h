@@ -70,6 +70,15 @@ extern "C" {
 #define SRE2_FORM_FP32 0
 /* FP64: everything in float64 (complex64 input is widened exactly). */
 #define SRE2_FORM_FP64 3
+/* Hermitian-pair forms: same arithmetic precision as FP32 / FP64 and the same
+ * result up to rounding, at half the work.  For x != 0, f_x(k ^ x) equals
+ * conj f_x(k) (from Eq. Pauli_expect), so with j the top set bit of x the
+ * transform of f_x restricted to the half-space k_j = 0 gives every W_x(z):
+ * W_x(z) = 2 Re or 2i Im of it, and S_x = 16 sum (Re^4 + Im^4).  Shift 0 (and,
+ * for N >= 15 in FP32 / 14 in FP64, the shifts below 2^12 / 2^11) use the plain
+ * kernels. */
+#define SRE2_FORM_FP32_HERM 4
+#define SRE2_FORM_FP64_HERM 5
 
 #define SRE2_MAX_N 26
 

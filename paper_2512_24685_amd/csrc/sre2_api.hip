@@ -18,7 +18,6 @@
 
 #include "../../include/sre2.h"
 #include "sre2_internal.h"
-#include "sre2_plan.h"
 
 using namespace sre2;
 
@@ -82,17 +81,22 @@ int ensure(void** buf, size_t* have, size_t need) {
     return SRE2_OK;
 }
 
-bool form_ok(int form) { return form == SRE2_FORM_FP32 || form == SRE2_FORM_FP64; }
+bool form_ok(int form) {
+    return form == SRE2_FORM_FP32 || form == SRE2_FORM_FP64 || form == SRE2_FORM_FP32_HERM ||
+           form == SRE2_FORM_FP64_HERM;
+}
+bool is_f64(int form) { return form == SRE2_FORM_FP64 || form == SRE2_FORM_FP64_HERM; }
+bool is_herm(int form) { return form == SRE2_FORM_FP32_HERM || form == SRE2_FORM_FP64_HERM; }
 bool dtype_ok(int dtype) { return dtype == SRE2_C64 || dtype == SRE2_C128; }
 
 int elem_bytes(int dtype) { return dtype == SRE2_C64 ? 8 : 16; }
-int work_dtype(int form) { return form == SRE2_FORM_FP64 ? kC128 : kC64; }
+int work_dtype(int form) { return is_f64(form) ? kC128 : kC64; }
 
-int fused_max(int form) {
-    return form == SRE2_FORM_FP64 ? fused_max_n<double>() : fused_max_n<float>();
-}
-int row_bits(int form) {
-    return form == SRE2_FORM_FP64 ? pass1_row_bits<double>() : pass1_row_bits<float>();
+int fused_max(int form) { return is_f64(form) ? fused_max_n<double>() : fused_max_n<float>(); }
+int row_bits(int form) { return is_f64(form) ? pass1_row_bits<double>() : pass1_row_bits<float>(); }
+int herm_min(int form) { return is_f64(form) ? herm_min_n<double>() : herm_min_n<float>(); }
+int64_t col_tiles(int N, int form, bool herm) {
+    return is_f64(form) ? pass2_col_tiles<double>(N, herm) : pass2_col_tiles<float>(N, herm);
 }
 
 // Two-pass chunking: shifts per chunk (power of two) and column groups per shift.
@@ -101,17 +105,18 @@ struct Chunking {
     int P = 1;
 };
 
-Chunking chunking(int N, int form, int64_t x_count, size_t limit) {
+Chunking chunking(int N, int form, bool herm, int64_t x_count, size_t limit) {
     Chunking c;
     if (N <= fused_max(form)) return c;
-    const size_t slab = (size_t(1) << N) * (size_t)elem_bytes(work_dtype(form));
+    const int L = row_bits(form);
+    const size_t slab = (size_t(1) << (N - (herm ? 1 : 0))) * (size_t)elem_bytes(work_dtype(form));
     int64_t cs = 1;
-    while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << 14))
+    while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << L))
         cs *= 2;
     c.cs = cs;
-    const int H = N - row_bits(form);
+    const int64_t tiles = col_tiles(N, form, herm);
     int P = 1;
-    while (cs * P < 2048 && P * 2 <= (1 << H)) P *= 2;
+    while (cs * P < 2048 && P * 2 <= tiles) P *= 2;
     c.P = P;
     return c;
 }
@@ -153,7 +158,7 @@ int validate(const sre2_ctx* ctx, const void* psi, int N, int dtype, int form) {
     if (N < 1 || N > SRE2_MAX_N) return SRE2_EINVAL;
     if (!dtype_ok(dtype)) return SRE2_EDTYPE;
     if (!form_ok(form)) return SRE2_EFORM;
-    if (N > (form == SRE2_FORM_FP64 ? max_n<double>() : max_n<float>())) return SRE2_EFORM;
+    if (N > (is_f64(form) ? max_n<double>() : max_n<float>())) return SRE2_EFORM;
     return SRE2_OK;
 }
 
@@ -177,35 +182,25 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
     return rc;
 }
 
-// S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).
-int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
-               double* Sx, hipStream_t st) {
-    const bool f64 = form == SRE2_FORM_FP64;
-    if (N <= fused_max(form)) {
-        Timed tm(ctx, st, SRE2_KIND_SHIFT);
-        return hip_status(f64 ? launch_shift_kernel<double>(work, N, x0, xc, Sx, st)
-                              : launch_shift_kernel<float>(work, N, x0, xc, Sx, st));
-    }
-    const Chunking ch = chunking(N, form, xc, ctx->scratch_limit);
-    const size_t slab = (size_t(1) << N) * (size_t)elem_bytes(work_dtype(form));
-    int rc = ensure(&ctx->scratch, &ctx->scratch_bytes, (size_t)ch.cs * slab);
-    if (rc) return rc;
-    rc = ensure((void**)&ctx->part, &ctx->part_bytes, (size_t)ch.cs * ch.P * sizeof(double));
-    if (rc) return rc;
+// Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
+int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
+             double* Sx, hipStream_t st) {
+    const bool f64 = is_f64(form);
+    const Chunking ch = chunking(N, form, herm, xc, ctx->scratch_limit);
     for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
         // a short last chunk keeps the same column grouping
         const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
         hipError_t e;
         {
             Timed tm(ctx, st, SRE2_KIND_PASS1);
-            e = f64 ? launch_pass1<double>(work, N, x0 + c0, cs, ctx->scratch, st)
-                    : launch_pass1<float>(work, N, x0 + c0, cs, ctx->scratch, st);
+            e = f64 ? launch_pass1<double>(work, N, herm, x0 + c0, cs, ctx->scratch, st)
+                    : launch_pass1<float>(work, N, herm, x0 + c0, cs, ctx->scratch, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
             Timed tm(ctx, st, SRE2_KIND_PASS2);
-            e = f64 ? launch_pass2<double>(ctx->scratch, N, cs, ch.P, ctx->part, st)
-                    : launch_pass2<float>(ctx->scratch, N, cs, ch.P, ctx->part, st);
+            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, cs, ch.P, ctx->part, st)
+                    : launch_pass2<float>(ctx->scratch, N, herm, cs, ch.P, ctx->part, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
@@ -215,6 +210,61 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
         if (e != hipSuccess) return SRE2_EHIP;
     }
     return SRE2_OK;
+}
+
+// S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).  The Hermitian
+// forms route the shifts they cannot take (x = 0 fused, x < 2^L two-pass,
+// or N too small) through the plain kernels of the same precision.
+int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
+               double* Sx, hipStream_t st) {
+    const bool f64 = is_f64(form);
+    const int64_t x1 = x0 + xc;
+    if (N <= fused_max(form)) {
+        const bool herm = is_herm(form) && N >= herm_min(form);
+        const int64_t split = herm ? (x0 > 1 ? x0 : (x1 < 1 ? x1 : 1)) : x1;  // plain: [x0, split)
+        if (split > x0) {
+            Timed tm(ctx, st, SRE2_KIND_SHIFT);
+            const hipError_t e =
+                f64 ? launch_shift_kernel<double>(work, N, false, x0, split - x0, Sx, st)
+                    : launch_shift_kernel<float>(work, N, false, x0, split - x0, Sx, st);
+            if (e != hipSuccess) return SRE2_EHIP;
+        }
+        if (x1 > split) {
+            Timed tm(ctx, st, SRE2_KIND_SHIFT);
+            const hipError_t e =
+                f64 ? launch_shift_kernel<double>(work, N, true, split, x1 - split, Sx + (split - x0), st)
+                    : launch_shift_kernel<float>(work, N, true, split, x1 - split, Sx + (split - x0), st);
+            if (e != hipSuccess) return SRE2_EHIP;
+        }
+        return SRE2_OK;
+    }
+    const bool herm = is_herm(form);
+    const int64_t lim = int64_t(1) << row_bits(form);
+    const int64_t split = herm ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
+    // workspace for the larger of the two chunk shapes
+    size_t need = 0, need_part = 0;
+    const int elem = elem_bytes(work_dtype(form));
+    if (split > x0) {
+        const Chunking c = chunking(N, form, false, split - x0, ctx->scratch_limit);
+        need = (size_t)c.cs * (size_t(1) << N) * elem;
+        need_part = (size_t)c.cs * c.P;
+    }
+    if (x1 > split) {
+        const Chunking c = chunking(N, form, true, x1 - split, ctx->scratch_limit);
+        const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
+        need = need > b ? need : b;
+        need_part = need_part > (size_t)c.cs * c.P ? need_part : (size_t)c.cs * c.P;
+    }
+    int rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
+    if (rc) return rc;
+    rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
+    if (rc) return rc;
+    if (split > x0) {
+        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, st);
+        if (rc) return rc;
+    }
+    if (x1 > split) rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), st);
+    return rc;
 }
 
 int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st, double* out,
@@ -309,7 +359,7 @@ size_t sre2_workspace_bytes(int N, int dtype, int form) {
     const size_t n = size_t(1) << N;
     size_t b = 3 * kMaxRed * sizeof(double) + n * sizeof(double);
     if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
-    const Chunking ch = chunking(N, form, (int64_t)n, size_t(4) << 30);
+    const Chunking ch = chunking(N, form, false, (int64_t)n, size_t(4) << 30);
     if (ch.cs) {
         b += (size_t)ch.cs * n * (size_t)elem_bytes(work_dtype(form));
         b += (size_t)ch.cs * ch.P * sizeof(double);
@@ -392,7 +442,7 @@ int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches) {
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups) {
     if (!ctx || !shifts_per_chunk || !groups || N < 1 || N > SRE2_MAX_N || !form_ok(form))
         return SRE2_EINVAL;
-    const Chunking ch = chunking(N, form, int64_t(1) << N, ctx->scratch_limit);
+    const Chunking ch = chunking(N, form, is_herm(form), int64_t(1) << N, ctx->scratch_limit);
     *shifts_per_chunk = ch.cs;
     *groups = ch.P;
     return SRE2_OK;

@@ -11,24 +11,31 @@ constexpr int kMaxN = 26;
 constexpr int kC64 = 0;
 constexpr int kC128 = 1;
 
-// Largest N handled by the tiny/fused kernels, and the row bits L of pass 1
-// (two-pass: N > fused_max_n; pass 2 transforms the top N - L bits).
-template <typename Real> int fused_max_n();
+// Geometry queries.  Two-pass is used for N > fused_max_n; pass 1 transforms
+// the low L = pass1_row_bits bits.  The Hermitian-pair forms need
+// N >= herm_min_n (fused) and shifts x >= 1 (fused) or x >= 2^L (two-pass);
+// other shifts go through the plain kernels.
 template <typename Real> int max_n();
+template <typename Real> int fused_max_n();
 template <typename Real> int pass1_row_bits();
+template <typename Real> int herm_min_n();
+// Column tiles per shift in pass 2 (upper bound of the column groups P).
+template <typename Real> int64_t pass2_col_tiles(int N, bool herm);
 
-// S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (N < RB) or fused
-// kernel (N <= TB).
+// S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (plain, N < RB) or
+// fused kernel (N <= fused_max_n).
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, int64_t x0, int64_t xc, double* S,
-                               hipStream_t st);
-// Two-pass (N > TB), one chunk of cs shifts starting at x0: pass 1 writes the
-// row-transformed slabs (cs * 2^N complex values) to `scratch`; pass 2 writes
-// part[s*P + p], the p-th column-group partial of shift x0+s.
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int64_t x0, int64_t xc,
+                               double* S, hipStream_t st);
+// Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
+// row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
+// pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, int64_t x0, int cs, void* scratch, hipStream_t st);
+hipError_t launch_pass1(const void* psi, int N, bool herm, int64_t x0, int cs, void* scratch,
+                        hipStream_t st);
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, int cs, int P, double* part, hipStream_t st);
+hipError_t launch_pass2(const void* scratch, int N, bool herm, int cs, int P, double* part,
+                        hipStream_t st);
 
 hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                           hipStream_t st);

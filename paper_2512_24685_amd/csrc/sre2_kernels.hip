@@ -51,6 +51,19 @@ __device__ __forceinline__ double abs4(C w) {  // |w|^4 with the square in FP64
     return md * md;
 }
 
+// Hermitian-pair form: 16 (Re^4 + Im^4) of one half-space transform value
+// equals the sum of |W|^4 over the two Pauli strings it stands for.
+template <typename C>
+__device__ __forceinline__ double abs4h(C w) {
+    const double a = (double)(w.x * w.x), b = (double)(w.y * w.y);
+    return a * a + b * b;
+}
+
+// Insert a zero bit at position `hb` of `v`.
+__device__ __forceinline__ uint32_t insert0(uint32_t v, uint32_t hb) {
+    return ((v >> hb) << (hb + 1)) | (v & ((1u << hb) - 1u));
+}
+
 // Butterflies over the register bits of `bfly` (a subset of `reg`), one tile
 // bit at a time (compile-time recursion keeps every register index constant).
 template <int RB, uint32_t REG, uint32_t BFLY, int B = 0, typename C>
@@ -161,20 +174,27 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Fused: RB <= N <= TB.  Tile = SPT = 2^(TB-N) consecutive shifts.
+// Fused: whole transforms of NT bits in a 2^TB tile of SPT = 2^(TB-NT) shifts.
+//  HERM = false: NT = N, the tile element (slot j, k) is f_x(k), x = x0 + j.
+//  HERM = true : NT = N - 1 (Hermitian pair, x >= 1): with hb the top set bit
+//                of x, element (j, k') is f_x(k) for k = k' with a 0 inserted
+//                at bit hb, i.e. only the half-space k_hb = 0.  Because
+//                f_x(k ^ x) = conj f_x(k), W_x(z) over the full space is twice
+//                Re or twice i Im of this half transform, so
+//                S_x = 16 sum_z' (Re^4 + Im^4).
 // ---------------------------------------------------------------------------
-template <typename Real, int N, int TB, int RB>
+template <typename Real, int NT, int TB, int RB, bool HERM>
 __global__ __launch_bounds__(1 << (TB - RB))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 1000 + N;
+    constexpr int PK = 1000 + NT;
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
-    constexpr int SPT = 1 << (TB - N);
-    constexpr uint32_t KMASK = (1u << N) - 1u;
+    constexpr int SPT = 1 << (TB - NT);
+    constexpr uint32_t KMASK = (1u << NT) - 1u;
     __shared__ C lds[1 << TB];
     double* red = reinterpret_cast<double*>(lds);
 
@@ -187,10 +207,11 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) {
                 const uint32_t e = base | pdep((uint32_t)i, r0.reg);
-                const uint32_t k = e & KMASK;
-                const int64_t j = e >> N;  // shift slot in the tile
+                const int64_t j = e >> NT;  // shift slot in the tile
                 if (tile * SPT + j < x_count) {
                     const uint32_t x = (uint32_t)(x0 + j);
+                    uint32_t k = e & KMASK;
+                    if constexpr (HERM) k = insert0(k, 31u - __clz(x));
                     v[i] = cmul_conj_a(psi[k ^ x], psi[k]);
                 } else {
                     v[i].x = 0;
@@ -202,9 +223,10 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
         RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < (1 << RB); ++i) s += abs4(v[i]);
+        for (int i = 0; i < (1 << RB); ++i) s += HERM ? abs4h(v[i]) : abs4(v[i]);
+        if constexpr (HERM) s *= 16.0;
         // thread order index: tile bits outside the last round's registers,
-        // compressed; its top TB-N bits are the shift slot.
+        // compressed; its top TB-NT bits are the shift slot.
         const uint32_t q = pext(thread_base<rl.lane, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
         __syncthreads();
         red[q] = s;
@@ -217,13 +239,15 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 }
 
 // ---------------------------------------------------------------------------
-// Two-pass, pass 1: row transform over k_lo (TB bits) of f_x for a chunk of
-// shifts.  Block b -> row = b / cs, shift slot = b % cs, so neighbouring blocks
-// read the same psi rows.
+// Two-pass, pass 1: row transform over k_lo (TB = L bits) of f_x for a chunk
+// of shifts; the slab of one shift holds 2^NS values (NS = N, or N - 1 in the
+// Hermitian-pair form, which needs x >= 2^L so that the dropped bit hb is a
+// row bit and only rows with that bit clear are built).  Block b -> slab row
+// b / cs, shift slot b % cs, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
-template <typename Real, int TB, int RB>
+template <typename Real, int TB, int RB, bool HERM>
 __global__ __launch_bounds__(1 << (TB - RB))
-void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, int cs,
+void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch) {
     using C = typename CT<Real>::T;
     constexpr int PK = 2000;
@@ -233,9 +257,11 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, in
     __shared__ C lds[1 << TB];
 
     const int64_t b = blockIdx.x;
-    const int64_t row = b / cs;
+    const uint32_t srow = (uint32_t)(b / cs);  // row within the slab
     const int64_t s = b % cs;
     const uint64_t x = (uint64_t)(x0 + s);
+    uint32_t row = srow;
+    if constexpr (HERM) row = insert0(srow, (63u - (uint32_t)__clzll(x)) - TB);
     const uint64_t rowbase = (uint64_t)row << TB;
     const uint64_t prow = rowbase ^ (x & ~(uint64_t)((1u << TB) - 1u));  // partner row
     const uint32_t xlo = (uint32_t)(x & ((1u << TB) - 1u));
@@ -252,28 +278,28 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int N, int64_t x0, in
     }
     butterflies<RB, r0.reg, r0.bfly>(v);
     RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
-    C* __restrict__ out = scratch + ((uint64_t)s << N) + rowbase;
+    C* __restrict__ out = scratch + ((uint64_t)s << NS) + ((uint64_t)srow << TB);
     const uint32_t base = thread_base<rl.lane, rl.wave>();
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i) out[base | pdep((uint32_t)i, rl.reg)] = v[i];
 }
 
 // ---------------------------------------------------------------------------
-// Two-pass, pass 2: column transform over k_hi (H = N - TB bits).  A tile is
-// 2^H rows x 2^(TB-H) columns of one shift's slab.  Block b -> shift slot
-// b / P, column group b % P; the group loops over its column tiles and writes
-// one FP64 partial.
+// Two-pass, pass 2: column transform over the HT slab-row bits of one shift's
+// slab (2^NS values = 2^HT rows of 2^L).  A tile is 2^HT rows x 2^(TB-HT)
+// columns.  Block b -> shift slot b / P, column group b % P; the group loops
+// over its column tiles and writes one FP64 partial of S_x.
 // ---------------------------------------------------------------------------
-template <typename Real, int H, int TB, int RB>
+template <typename Real, int HT, int TB, int RB, bool HERM>
 __global__ __launch_bounds__(1 << (TB - RB))
-void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
+void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 3000 + H;
+    constexpr int PK = 3000 + HT;
     constexpr Plan PL = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = PL.r[0];
-    constexpr int CB = TB - H;  // column bits per tile
+    constexpr int CB = TB - HT;  // column bits per tile
     constexpr uint32_t CMASK = (1u << CB) - 1u;
     __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
     __shared__ double red[T];
@@ -281,10 +307,10 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
     const int64_t b = blockIdx.x;
     const int64_t s = b / P;
     const int g = (int)(b % P);
-    const int L = N - H;  // row bits of pass 1
+    const int L = NS - HT;  // row bits of pass 1
     const int ntile = 1 << (L - CB);  // column tiles per shift
     const int per = ntile / P;
-    const C* __restrict__ slab = scratch + ((uint64_t)s << N);
+    const C* __restrict__ slab = scratch + ((uint64_t)s << NS);
     double acc = 0.0;
     for (int ct = g * per; ct < (g + 1) * per; ++ct) {
         const C* __restrict__ src = slab + ((uint64_t)ct << CB);
@@ -298,8 +324,9 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int N, int P,
         butterflies<RB, r0.reg, r0.bfly>(v);
         if constexpr (PL.nrounds > 1) RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
 #pragma unroll
-        for (int i = 0; i < (1 << RB); ++i) acc += abs4(v[i]);
+        for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
     }
+    if constexpr (HERM) acc *= 16.0;
     red[threadIdx.x] = acc;
     seg_tree<T>(red, T);
     if (threadIdx.x == 0) part[b] = red[0];
@@ -429,24 +456,25 @@ hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S, hip
     return hipGetLastError();
 }
 
-template <typename Real, int N>
-hipError_t launch_fused_n(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
+template <typename Real, int NT, bool HERM>
+hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = fused_tb<Real>(N), RB = Tune<Real>::RBF;
-    constexpr int SPT = 1 << (TB - N);
+    constexpr int TB = fused_tb<Real>(NT), RB = Tune<Real>::RBF;
+    constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL((k_fused<Real, N, TB, RB>), dim3((unsigned)grid), dim3(1 << (TB - RB)), 0,
-                       st, (const C*)psi, x0, xc, S);
+    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM>), dim3((unsigned)grid),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S);
     return hipGetLastError();
 }
 
-template <typename Real, int H>
-hipError_t launch_pass2_h(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
+template <typename Real, int HT, bool HERM>
+hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part,
+                           hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = pass2_tb<Real>(H), RB = Tune<Real>::RB2;
-    hipLaunchKernelGGL((k_pass2<Real, H, TB, RB>), dim3((unsigned)((int64_t)cs * P)),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, N, P, part);
+    constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
+    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM>), dim3((unsigned)((int64_t)cs * P)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part);
     return hipGetLastError();
 }
 
@@ -458,25 +486,38 @@ hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double*
     return e;
 }
 
-template <typename Real, int... Ns>
-hipError_t dispatch_fused(int N, const void* psi, int64_t x0, int64_t xc, double* S,
+template <typename Real, bool HERM, int... Ns>
+hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, double* S,
                           hipStream_t st, std::integer_sequence<int, Ns...>) {
     constexpr int RB = Tune<Real>::RBF;
     hipError_t e = hipErrorInvalidValue;
-    ((N == Ns + RB ? (e = launch_fused_n<Real, Ns + RB>(psi, x0, xc, S, st), 0) : 0), ...);
+    ((NT == Ns + RB ? (e = launch_fused_nt<Real, Ns + RB, HERM>(psi, x0, xc, S, st), 0) : 0), ...);
+    return e;
+}
+
+template <typename Real, bool HERM, int... Hs>
+hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, double* part,
+                          hipStream_t st, std::integer_sequence<int, Hs...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((HT == Hs + 1 ? (e = launch_pass2_ht<Real, Hs + 1, HERM>(scratch, NS, cs, P, part, st), 0)
+                   : 0),
+     ...);
     return e;
 }
 
 template <typename Real, int... Hs>
-hipError_t dispatch_pass2(int H, const void* scratch, int N, int cs, int P, double* part,
-                          hipStream_t st, std::integer_sequence<int, Hs...>) {
-    hipError_t e = hipErrorInvalidValue;
-    ((H == Hs + 1 ? (e = launch_pass2_h<Real, Hs + 1>(scratch, N, cs, P, part, st), 0) : 0), ...);
-    return e;
+int pass2_tb_rt(int HT, std::integer_sequence<int, Hs...>) {
+    int tb = 0;
+    ((HT == Hs + 1 ? (tb = pass2_tb<Real>(Hs + 1), 0) : 0), ...);
+    return tb;
 }
 
 }  // namespace
 
+template <typename Real>
+int max_n() {
+    return max_n_of<Real>();
+}
 template <typename Real>
 int fused_max_n() {
     return Tune<Real>::FMAX;
@@ -486,8 +527,15 @@ int pass1_row_bits() {
     return Tune<Real>::ROW;
 }
 template <typename Real>
-int max_n() {
-    return max_n_of<Real>();
+int herm_min_n() {
+    return Tune<Real>::RBF + 1;
+}
+template <typename Real>
+int64_t pass2_col_tiles(int N, bool herm) {
+    const int NS = N - (herm ? 1 : 0);
+    const int HT = NS - Tune<Real>::ROW;
+    const int tb = pass2_tb_rt<Real>(HT, std::make_integer_sequence<int, Prec<Real>::MAXTB>{});
+    return tb > 0 ? (int64_t)1 << (NS - tb) : 0;
 }
 template int max_n<float>();
 template int max_n<double>();
@@ -495,46 +543,67 @@ template int fused_max_n<float>();
 template int fused_max_n<double>();
 template int pass1_row_bits<float>();
 template int pass1_row_bits<double>();
+template int herm_min_n<float>();
+template int herm_min_n<double>();
+template int64_t pass2_col_tiles<float>(int, bool);
+template int64_t pass2_col_tiles<double>(int, bool);
 
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, int64_t x0, int64_t xc, double* S,
-                               hipStream_t st) {
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int64_t x0, int64_t xc,
+                               double* S, hipStream_t st) {
     constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
+    if (N > FMAX) return hipErrorInvalidValue;
+    if (herm) {
+        if (x0 < 1 || N - 1 < RB) return hipErrorInvalidValue;
+        return dispatch_fused<Real, true>(N - 1, psi, x0, xc, S, st,
+                                          std::make_integer_sequence<int, FMAX - RB>{});
+    }
     if (N < RB)
         return dispatch_tiny<Real>(N, psi, x0, xc, S, st, std::make_integer_sequence<int, RB - 1>{});
-    if (N <= FMAX)
-        return dispatch_fused<Real>(N, psi, x0, xc, S, st,
-                                    std::make_integer_sequence<int, FMAX - RB + 1>{});
-    return hipErrorInvalidValue;
+    return dispatch_fused<Real, false>(N, psi, x0, xc, S, st,
+                                       std::make_integer_sequence<int, FMAX - RB + 1>{});
 }
 
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, int64_t x0, int cs, void* scratch, hipStream_t st) {
+hipError_t launch_pass1(const void* psi, int N, bool herm, int64_t x0, int cs, void* scratch,
+                        hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = Tune<Real>::ROW, RB = Tune<Real>::RB1;
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    const int64_t rows = (int64_t)1 << (N - TB);
-    hipLaunchKernelGGL((k_pass1<Real, TB, RB>), dim3((unsigned)(rows * cs)), dim3(1 << (TB - RB)), 0,
-                       st, (const C*)psi, N, x0, cs, (C*)scratch);
+    if (herm && x0 < ((int64_t)1 << TB)) return hipErrorInvalidValue;
+    const int NS = N - (herm ? 1 : 0);
+    const int64_t rows = (int64_t)1 << (NS - TB);
+    if (herm)
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true>), dim3((unsigned)(rows * cs)),
+                           dim3(1 << (TB - RB)), 0, st, (const C*)psi, NS, x0, cs, (C*)scratch);
+    else
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, false>), dim3((unsigned)(rows * cs)),
+                           dim3(1 << (TB - RB)), 0, st, (const C*)psi, NS, x0, cs, (C*)scratch);
     return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, int cs, int P, double* part, hipStream_t st) {
+hipError_t launch_pass2(const void* scratch, int N, bool herm, int cs, int P, double* part,
+                        hipStream_t st) {
     constexpr int ROW = Tune<Real>::ROW;
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    return dispatch_pass2<Real>(N - ROW, scratch, N, cs, P, part, st,
-                                std::make_integer_sequence<int, max_n_of<Real>() - ROW>{});
+    const int NS = N - (herm ? 1 : 0);
+    constexpr int HMAX = max_n_of<Real>() - ROW;
+    if (herm)
+        return dispatch_pass2<Real, true>(NS - ROW, scratch, NS, cs, P, part, st,
+                                          std::make_integer_sequence<int, HMAX>{});
+    return dispatch_pass2<Real, false>(NS - ROW, scratch, NS, cs, P, part, st,
+                                       std::make_integer_sequence<int, HMAX>{});
 }
 
-template hipError_t launch_shift_kernel<float>(const void*, int, int64_t, int64_t, double*,
+template hipError_t launch_shift_kernel<float>(const void*, int, bool, int64_t, int64_t, double*,
                                                hipStream_t);
-template hipError_t launch_shift_kernel<double>(const void*, int, int64_t, int64_t, double*,
+template hipError_t launch_shift_kernel<double>(const void*, int, bool, int64_t, int64_t, double*,
                                                 hipStream_t);
-template hipError_t launch_pass1<float>(const void*, int, int64_t, int, void*, hipStream_t);
-template hipError_t launch_pass1<double>(const void*, int, int64_t, int, void*, hipStream_t);
-template hipError_t launch_pass2<float>(const void*, int, int, int, double*, hipStream_t);
-template hipError_t launch_pass2<double>(const void*, int, int, int, double*, hipStream_t);
+template hipError_t launch_pass1<float>(const void*, int, bool, int64_t, int, void*, hipStream_t);
+template hipError_t launch_pass1<double>(const void*, int, bool, int64_t, int, void*, hipStream_t);
+template hipError_t launch_pass2<float>(const void*, int, bool, int, int, double*, hipStream_t);
+template hipError_t launch_pass2<double>(const void*, int, bool, int, int, double*, hipStream_t);
 
 hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                           hipStream_t st) {

@@ -77,7 +77,7 @@ def test_batched_argument_validation(L, ctx):
     assert L.sre2_m2_batched(h, ptrs, Ns, 0, 0, 0, None, FAKE) == sre2.EINVAL
     assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 0, None, FAKE) == sre2.EINVAL  # N=40
     Ns[1] = 9
-    assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 5, None, FAKE) == sre2.EFORM
+    assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 99, None, FAKE) == sre2.EFORM
     assert L.sre2_m2_batched(h, ptrs, Ns, 2, 0, 0, None, None) == sre2.EINVAL
 
 

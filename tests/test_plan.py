@@ -213,69 +213,95 @@ def test_tile_transform_matches_wht(probe):
         assert np.allclose(out, wht_bits(X, lo, hi)), (prec, kind, par)
 
 
-def emulate_fused_partials(probe, psi, prec):
-    """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-N) shifts)."""
+def insert0(v, hb):
+    return ((v >> hb) << (hb + 1)) | (v & ((1 << hb) - 1))
+
+
+def reduce4(v, herm):
+    if herm:  # Hermitian pair: 16 (Re^4 + Im^4)
+        return 16.0 * np.sum(v.real ** 4 + v.imag ** 4)
+    return np.sum(np.abs(v) ** 4)
+
+
+def emulate_fused_partials(probe, psi, prec, herm=False, x_begin=0):
+    """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-NT) shifts)."""
     N = psi.size.bit_length() - 1
-    tb, rb, sb = geo(probe, prec, FUSED, N)
-    rounds = plan(probe, tb, rb, sb, 0, N)
-    spt = 1 << (tb - N)
+    NT = N - int(herm)
+    tb, rb, sb = geo(probe, prec, FUSED, NT)
+    rounds = plan(probe, tb, rb, sb, 0, NT)
+    spt = 1 << (tb - NT)
     d = 1 << N
-    S = np.zeros(d)
+    S = {}
     e = np.arange(1 << tb)
-    k = e & (d - 1)
-    for t0 in range(0, d, spt):
-        x = t0 + (e >> N)
-        valid = x < d
-        X = np.where(valid, np.conj(psi[(k ^ x) % d]) * psi[k], 0)
+    for t0 in range(x_begin, d, spt):
+        out = np.zeros(1 << tb, dtype=np.complex128)
+        X = np.zeros(1 << tb, dtype=np.complex128)
+        for j in range(spt):
+            x = t0 + j
+            if x >= d:
+                continue
+            kp = e[j << NT:(j + 1) << NT] & ((1 << NT) - 1)
+            k = insert0(kp, x.bit_length() - 1) if herm else kp
+            X[j << NT:(j + 1) << NT] = np.conj(psi[k ^ x]) * psi[k]
         out = run_tile(X, rounds, tb, rb, sb)
-        q = np.abs(out) ** 4
         for j in range(spt):
             if t0 + j < d:
-                S[t0 + j] = q[j * d:(j + 1) * d].sum()
-    return S
+                S[t0 + j] = reduce4(out[j << NT:(j + 1) << NT], herm)
+    return np.array([S[x] for x in range(x_begin, d)])
 
 
-def emulate_two_pass_partials(probe, psi, prec, xs):
+def emulate_two_pass_partials(probe, psi, prec, xs, herm=False):
     """Per-shift sums as k_pass1 / k_pass2 index them (row slab, then columns)."""
     N = psi.size.bit_length() - 1
+    NS = N - int(herm)
     L, rb1, sb = geo(probe, prec, PASS1)
-    H = N - L
-    tb2, rb2, _ = geo(probe, prec, PASS2, H)
+    HT = NS - L
+    tb2, rb2, _ = geo(probe, prec, PASS2, HT)
     p1 = plan(probe, L, rb1, sb, 0, L)
-    p2 = plan(probe, tb2, rb2, sb, tb2 - H, tb2)
+    p2 = plan(probe, tb2, rb2, sb, tb2 - HT, tb2)
     e1 = np.arange(1 << L)
     e2 = np.arange(1 << tb2)
-    cb = tb2 - H
+    cb = tb2 - HT
     out = []
     for x in xs:
-        slab = np.empty(1 << N, dtype=np.complex128)
-        for row in range(1 << H):
+        assert not herm or x >= (1 << L)
+        slab = np.empty(1 << NS, dtype=np.complex128)
+        for srow in range(1 << HT):
+            row = insert0(srow, x.bit_length() - 1 - L) if herm else srow
             rowbase = row << L
             prow = rowbase ^ (x & ~((1 << L) - 1))
             X = np.conj(psi[prow + (e1 ^ (x & ((1 << L) - 1)))]) * psi[rowbase + e1]
-            slab[rowbase:rowbase + (1 << L)] = run_tile(X, p1, L, rb1, sb)
+            slab[srow << L:(srow + 1) << L] = run_tile(X, p1, L, rb1, sb)
         acc = 0.0
         for ct in range(1 << (L - cb)):
             src = (e2 >> cb << L) + (ct << cb) + (e2 & ((1 << cb) - 1))
-            acc += np.sum(np.abs(run_tile(slab[src], p2, tb2, rb2, sb)) ** 4)
+            acc += reduce4(run_tile(slab[src], p2, tb2, rb2, sb), herm)
         out.append(acc)
     return np.array(out)
 
 
-@pytest.mark.parametrize("prec,N", [(0, 6), (0, 9), (1, 5), (1, 8)])
-def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N):
+@pytest.mark.parametrize("prec,N,herm", [(0, 6, False), (0, 9, False), (1, 5, False),
+                                         (1, 8, False), (0, 6, True), (0, 9, True), (1, 5, True),
+                                         (1, 8, True)])
+def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N, herm):
     psi = W.haar(N, 42 + N)
-    S = emulate_fused_partials(probe, psi, prec)
-    ref = oracle_mod.partials(psi)
+    x0 = 1 if herm else 0
+    S = emulate_fused_partials(probe, psi, prec, herm, x0)
+    ref = oracle_mod.partials(psi)[x0:]
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
 
 
-@pytest.mark.parametrize("prec,extra", [(0, 1), (0, 3), (1, 1), (1, 3)])
-def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec, extra):
-    fmax, _, _ = geo(probe, prec, LIMITS)
+@pytest.mark.parametrize("prec,extra,herm", [(0, 1, False), (0, 3, False), (1, 1, False),
+                                             (1, 3, False), (0, 1, True), (0, 3, True),
+                                             (1, 1, True), (1, 3, True)])
+def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec, extra, herm):
+    fmax, L, _ = geo(probe, prec, LIMITS)
     N = fmax + extra
     psi = W.haar(N, 7)
-    xs = [0, 1, (1 << N) - 1, 0x2A5A % (1 << N), 1 << (N - 1)]
-    S = emulate_two_pass_partials(probe, psi, prec, xs)
+    if herm:
+        xs = [1 << L, (1 << N) - 1, 0x2A5A % (1 << N) | (1 << L), 1 << (N - 1), 3 << (N - 2)]
+    else:
+        xs = [0, 1, (1 << N) - 1, 0x2A5A % (1 << N), 1 << (N - 1)]
+    S = emulate_two_pass_partials(probe, psi, prec, xs, herm)
     ref = oracle_mod.partials(psi, xs)
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
