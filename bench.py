@@ -1,19 +1,23 @@
 """Throughput benchmark: Pauli strings per second of one exact M2 evaluation.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|fp64] [--N 20]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32]
+                    [--also fp32h,fp64] [--N 20] [--no-cpu]
+    python bench.py --copy-calibration MiB     (plain device copy, for counters)
 
 One step = one full evaluation (every shift x, its FWHT, sum |W|^4, the final
 reduction and logarithm) of an N=20 Haar-random complex64 state that is
 already resident in device memory.  Pauli strings per step = 4^N.
 
-Printed (one JSON line on stdout): throughput, ms per step, the dominant
-kernel's roofline position (timed live with HIP events around every launch in
-the timed region), and the FP64 CPU oracle timed on this host's cores on a
-bounded sample of the same workload.
+Printed (one JSON line on stdout): throughput of the headline form (plain
+FP32 XOR-FWHT), ms per step, the dominant kernel's roofline position (timed
+live with HIP events around every launch in the timed region), the other
+forms measured the same way, and the FP64 CPU oracle timed on this host's
+cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,44 +31,89 @@ sys.path.insert(0, ROOT)
 METRIC = ("Pauli strings/s at N=20 (fp32 vs split-fp16 MFMA, |ΔM2|≤1e-5); "
           "p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
-# Non-packed FP32 VALU issue rate: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
+# Non-packed FP32/FP64 VALU issue rate: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# Bytes of the slab round trip per Pauli string and pass (complex values).
-SLAB_BYTES = {"fp32": 8, "fp64": 16}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCES = ["paper_2512_24685_amd/csrc/sre2_kernels.hip",
+                  "paper_2512_24685_amd/csrc/sre2_geometry.h",
+                  "paper_2512_24685_amd/csrc/sre2_plan.h"]
+
+# Geometry of the two-pass kernels (must match sre2_geometry.h defaults).
+ROW_BITS = {"fp32": 12, "fp64": 11}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_roofline(N: int, form: str, kind: str, ms: float, launches: int, cs: int, P: int):
-    """Roofline entry of one kernel class from its measured average duration."""
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def alg_units(N: int, form: str, kind: str, cs: int):
+    """Algorithmic bytes and VALU ops per launch of one kernel class.
+
+    Two-pass slab: every complex value of a shift's (half-)slab is written once
+    by pass 1 and read once by pass 2: 8 B (FP32) / 16 B (FP64) per value,
+    2^N values per shift (2^(N-1) in the Hermitian-pair forms).
+    VALU ops per slab value: pass 1 = 4 (conj product) + 2 per butterfly stage
+    over the L row bits; pass 2 = 2 per stage over the remaining bits + 5
+    (|W|^2, square in FP64, FP64 add); Hermitian pass 2: + 1 (two squares).
+    """
+    base = form.rstrip("h")
+    herm = form.endswith("h")
+    ns = N - (1 if herm else 0)
+    vals = cs * (1 << ns)
+    eb = 8 if base == "fp32" else 16
+    L = ROW_BITS[base]
+    if kind == "pass1":
+        return eb * vals, (4 + 2 * L) * vals
+    if kind == "pass2":
+        return eb * vals, (2 * (ns - L) + (6 if herm else 5)) * vals
+    raise ValueError(kind)
+
+
+def roofline(N, form, kind, ms, launches, cs, traffic):
     avg_s = ms / 1e3 / launches
-    d = 1 << N
     if kind in ("pass1", "pass2"):
-        pauli_per_launch = cs * d
-        by = SLAB_BYTES[form] * pauli_per_launch
-        tb = 14 if form == "fp32" else 13
-        ops = (4 + 2 * tb) if kind == "pass1" else (2 * (N - tb) + 5)
+        by, ops = alg_units(N, form, kind, cs)
         gbs = by / avg_s / 1e9
-        alu = ops * pauli_per_launch / avg_s
+        alu = ops / avg_s
         ent = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                "kernel": "k_pass1" if kind == "pass1" else "k_pass2",
                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-               "alu_ops_per_pauli": ops, "alu_frac": round(alu / VALU_PEAK_OPS, 4)}
-        if alu / VALU_PEAK_OPS > gbs / HBM_PEAK_GBS:
-            ent.update(bound="alu", achieved=round(alu / 1e12, 3), peak=round(VALU_PEAK_OPS / 1e12, 2),
-                       unit="Tops/s", frac=round(alu / VALU_PEAK_OPS, 4),
-                       hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+               "alg_bytes_per_launch": by, "alu_tops": round(alu / 1e12, 3),
+               "alu_frac": round(alu / VALU_PEAK_OPS, 4)}
         return ent
-    ops = 4 + 2 * N + 5
-    pauli_per_launch = d * d
-    alu = ops * pauli_per_launch / avg_s
+    # fused kernel: every value stays on chip; VALU-bound
+    herm = form.endswith("h")
+    nt = N - (1 if herm else 0)
+    ops = (4 + 2 * nt + (6 if herm else 5)) * (1 << N) * (1 << nt)
+    alu = ops / avg_s
     return {"bound": "alu", "achieved": round(alu / 1e12, 3), "peak": round(VALU_PEAK_OPS / 1e12, 2),
-            "unit": "Tops/s", "frac": round(alu / VALU_PEAK_OPS, 4), "traffic": None,
-            "kernel": "k_fused", "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-            "alu_ops_per_pauli": ops}
+            "unit": "Tops/s", "frac": round(alu / VALU_PEAK_OPS, 4), "traffic": traffic,
+            "kernel": "k_fused", "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
+
+
+def stored_traffic(kernel: str, N: int, form: str):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, scaled by a plain copy of known size), if they were taken on
+    the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    for r in rec.get("entries", []):
+        if r["kernel"] == kernel and r["N"] == N and r["form"] == form:
+            if r.get("source_sha") != kernel_source_sha():
+                return None
+            return r["hbm_bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(psi: np.ndarray, target_s: float):
@@ -76,8 +125,7 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
     probe = rng.choice(1 << N, size=cores, replace=False)
     t0 = time.perf_counter()
     oracle.partials(psi, probe, threads=cores)
-    t1 = time.perf_counter() - t0
-    per_shift = t1 / len(probe)
+    per_shift = (time.perf_counter() - t0) / len(probe)
     count = int(max(cores, min(1 << N, target_s / max(per_shift, 1e-9))))
     count = max(cores, (count // cores) * cores)
     xs = rng.choice(1 << N, size=count, replace=False)
@@ -86,8 +134,46 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
     dt = time.perf_counter() - t0
     return {"value": count * float(1 << N) / dt, "unit": "Pauli strings/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{count} random shifts of the N={N} state (2^{N} Pauli strings each), "
-                      f"{dt:.1f} s on {cores} threads"}
+            "sample": f"{count} random shifts x of the N={N} state, each a full FP64 FWHT over "
+                      f"2^{N} Pauli strings (Algorithm 1 loop body), {dt:.1f} s on {cores} threads"}
+
+
+def measure(sre2, torch, d_psi, form, steps, warmup):
+    ctx = sre2.Context(0)
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        out, _ = sre2.m2_async(d_psi, form=form, ctx=ctx)
+        torch.cuda.synchronize()
+        log(f"[{form}] warmup {i}: M2={out[0].item():.10f}")
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    outs = [sre2.m2_async(d_psi, form=form, ctx=ctx)[0] for _ in range(steps)]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    kt = ctx.timing_read()
+    ctx.set_timing(False)
+    m2s = [o[0].item() for o in outs]
+    if len(set(m2s)) != 1:
+        raise RuntimeError(f"{form}: results differ between steps: {m2s}")
+    cs, P = ctx.chunking(d_psi.numel().bit_length() - 1, form)
+    ctx.close()
+    log(f"[{form}] {steps} steps: {elapsed_ms:.1f} ms; M2={m2s[0]:.12f}; kernels={kt}")
+    return elapsed_ms / steps, m2s[0], kt, cs, P
+
+
+def copy_calibration(mib: int):
+    import torch
+
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {mib} MiB ten times ({n * 4} bytes read and written per copy)")
 
 
 def main():
@@ -95,16 +181,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--form", default="fp32")
+    ap.add_argument("--also", default="fp32h", help="other forms, comma separated")
     ap.add_argument("--N", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--profile-chunks", type=int, default=0, metavar="C",
+                    help="run only C two-pass chunks (the benchmark's launch shape) from "
+                         "x = 2^(N-1), for counter collection")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the evaluation shards over shifts x with no "
               "communication, so multi-GPU throughput is N x the one-GPU value; "
               "--gpus above 1 is not measured here.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -112,37 +206,38 @@ def main():
     import workloads as W
 
     N = args.N
-    log(f"bench: N={N} form={args.form} steps={args.steps} warmup={args.warmup}")
+    log(f"bench: N={N} form={args.form} also={args.also} steps={args.steps} warmup={args.warmup}")
     psi = W.haar(N, W.config_seed(3), np.complex64)
     d_psi = torch.from_numpy(psi).to("cuda:0")
-    ctx = sre2.Context(0)
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        out, _ = sre2.m2_async(d_psi, form=args.form, ctx=ctx)
-        torch.cuda.synchronize()
-        log(f"warmup {i}: M2={out[0].item():.10f}")
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    outs = []
-    for i in range(args.steps):
-        out, _ = sre2.m2_async(d_psi, form=args.form, ctx=ctx)
-        outs.append(out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
-    kt = ctx.timing_read()
-    ctx.set_timing(False)
-    m2s = [o[0].item() for o in outs]
-    log(f"timed {args.steps} steps: {elapsed_ms:.1f} ms; M2={m2s[0]:.12f}; kernels={kt}")
-    assert len(set(m2s)) == 1, "results differ between steps"
-    ms_per_step = elapsed_ms / args.steps
+    if args.profile_chunks:
+        ctx = sre2.Context(0)
+        cs, _ = ctx.chunking(N, args.form)
+        x0 = 1 << (N - 1)
+        for c in range(args.profile_chunks):
+            sre2.shift_partials(d_psi, x0 + c * cs, cs, form=args.form, ctx=ctx)
+            torch.cuda.synchronize()
+            log(f"profile chunk {c}: shifts [{x0 + c * cs}, {x0 + (c + 1) * cs})")
+        return
+
+    ms_per_step, m2, kt, cs, P = measure(sre2, torch, d_psi, args.form, args.steps, args.warmup)
     value = float(4 ** N) / (ms_per_step / 1e3)
-    cs, P = ctx.chunking(N, args.form)
     dom = max((k for k in kt if k != "aux" and kt[k][1] > 0), key=lambda k: kt[k][0])
-    roof = kernel_roofline(N, args.form, dom, kt[dom][0], kt[dom][1], cs, P)
+    kname = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[dom]
+    roof = roofline(N, args.form, dom, kt[dom][0], kt[dom][1], cs,
+                    stored_traffic(kname, N, args.form))
     roof["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
+
+    forms = {}
+    for f in [x for x in args.also.split(",") if x and x != args.form]:
+        fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, max(1, args.steps // 2), 1)
+        fdom = max((k for k in fkt if k != "aux" and fkt[k][1] > 0), key=lambda k: fkt[k][0])
+        fk = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[fdom]
+        forms[f] = {"value": float(4 ** N) / (fms / 1e3), "ms_per_step": fms, "M2": fm2,
+                    "abs_dM2_vs_headline": abs(fm2 - m2),
+                    "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1], fcs,
+                                         stored_traffic(fk, N, f)),
+                    "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps // 2), 3)
+                                            for k, v in fkt.items()}}
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: timing the FP64 oracle on a sample of shifts ...")
@@ -159,13 +254,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.form == "fp32" else "f64",
+        "dtype": "f64" if args.form.startswith("fp64") else "f32",
         "data": "synthetic",
-        "config": {"workload": f"exact M2 of one N={N} Haar-random complex64 state "
-                               f"(plain XOR-FWHT, {args.form} butterflies, FP64 sums)",
+        "config": {"workload": f"exact M2 of one N={N} Haar-random complex64 state, plain "
+                               f"XOR-FWHT ({args.form} butterflies, FP64 sums), two-pass "
+                               f"row/column transform through an HBM slab",
                    "N": N, "pauli_strings_per_step": 4 ** N, "form": args.form,
-                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2s[0]},
+                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2},
         "roofline": roof,
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
