@@ -68,6 +68,14 @@ extern "C" {
 /* FP32: f_x and every butterfly in float32; |W|^2 in float32, squared and
  * accumulated in float64 (complex128 input is rounded to complex64 first). */
 #define SRE2_FORM_FP32 0
+/* SPLIT_F16: the FP32 form with every group of four butterfly stages replaced
+ * by one H_16 = H_2^{(x)4} Kronecker factor on the matrix cores: each FP32
+ * value, pre-scaled by an exact power of two so that all values stay below
+ * 2^14, is split into FP16 hi + lo halves, and v_mfma_f32_16x16x32_f16 applies
+ * the exact +-1 matrix to both with FP32 accumulation (the scale is removed in
+ * FP64 at the end).  Stages left over (N mod 4) use FP32 butterflies; N < 5
+ * uses the FP32 kernel. */
+#define SRE2_FORM_SPLIT_F16 1
 /* FP64: everything in float64 (complex64 input is widened exactly). */
 #define SRE2_FORM_FP64 3
 /* Hermitian-pair forms: same arithmetic precision as FP32 / FP64 and the same

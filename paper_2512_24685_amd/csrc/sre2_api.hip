@@ -83,8 +83,9 @@ int ensure(void** buf, size_t* have, size_t need) {
 
 bool form_ok(int form) {
     return form == SRE2_FORM_FP32 || form == SRE2_FORM_FP64 || form == SRE2_FORM_FP32_HERM ||
-           form == SRE2_FORM_FP64_HERM;
+           form == SRE2_FORM_FP64_HERM || form == SRE2_FORM_SPLIT_F16;
 }
+bool is_split(int form) { return form == SRE2_FORM_SPLIT_F16; }
 bool is_f64(int form) { return form == SRE2_FORM_FP64 || form == SRE2_FORM_FP64_HERM; }
 bool is_herm(int form) { return form == SRE2_FORM_FP32_HERM || form == SRE2_FORM_FP64_HERM; }
 bool dtype_ok(int dtype) { return dtype == SRE2_C64 || dtype == SRE2_C128; }
@@ -184,8 +185,8 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
 
 // Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
 int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
-             double* Sx, hipStream_t st) {
-    const bool f64 = is_f64(form);
+             double* Sx, const int* se, hipStream_t st) {
+    const bool f64 = is_f64(form), split = is_split(form);
     const Chunking ch = chunking(N, form, herm, xc, ctx->scratch_limit);
     for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
         // a short last chunk keeps the same column grouping
@@ -193,14 +194,14 @@ int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_
         hipError_t e;
         {
             Timed tm(ctx, st, SRE2_KIND_PASS1);
-            e = f64 ? launch_pass1<double>(work, N, herm, x0 + c0, cs, ctx->scratch, st)
-                    : launch_pass1<float>(work, N, herm, x0 + c0, cs, ctx->scratch, st);
+            e = f64 ? launch_pass1<double>(work, N, herm, split, x0 + c0, cs, ctx->scratch, se, st)
+                    : launch_pass1<float>(work, N, herm, split, x0 + c0, cs, ctx->scratch, se, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
             Timed tm(ctx, st, SRE2_KIND_PASS2);
-            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, cs, ch.P, ctx->part, st)
-                    : launch_pass2<float>(ctx->scratch, N, herm, cs, ch.P, ctx->part, st);
+            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se, st)
+                    : launch_pass2<float>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
@@ -216,8 +217,8 @@ int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_
 // forms route the shifts they cannot take (x = 0 fused, x < 2^L two-pass,
 // or N too small) through the plain kernels of the same precision.
 int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
-               double* Sx, hipStream_t st) {
-    const bool f64 = is_f64(form);
+               double* Sx, const int* se, hipStream_t st) {
+    const bool f64 = is_f64(form), sp = is_split(form);
     const int64_t x1 = x0 + xc;
     if (N <= fused_max(form)) {
         const bool herm = is_herm(form) && N >= herm_min(form);
@@ -225,15 +226,17 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
         if (split > x0) {
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
-                f64 ? launch_shift_kernel<double>(work, N, false, x0, split - x0, Sx, st)
-                    : launch_shift_kernel<float>(work, N, false, x0, split - x0, Sx, st);
+                f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se, st)
+                    : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         if (x1 > split) {
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
-                f64 ? launch_shift_kernel<double>(work, N, true, split, x1 - split, Sx + (split - x0), st)
-                    : launch_shift_kernel<float>(work, N, true, split, x1 - split, Sx + (split - x0), st);
+                f64 ? launch_shift_kernel<double>(work, N, true, false, split, x1 - split,
+                                                  Sx + (split - x0), se, st)
+                    : launch_shift_kernel<float>(work, N, true, false, split, x1 - split,
+                                                 Sx + (split - x0), se, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         return SRE2_OK;
@@ -260,10 +263,39 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
     rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
     if (rc) return rc;
     if (split > x0) {
-        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, st);
+        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, st);
         if (rc) return rc;
     }
-    if (x1 > split) rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), st);
+    if (x1 > split)
+        rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), se, st);
+    return rc;
+}
+
+// Workspace layout of ctx->red: norm partials, non-finite flags, S partials
+// (kMaxRed doubles each), then one int: the split form's scale exponent.
+struct Red {
+    double* npart;
+    double* nflag;
+    double* spart;
+    int* se;
+};
+
+int red_buffers(sre2_ctx* ctx, Red* r) {
+    const int rc = ensure((void**)&ctx->red, &ctx->red_bytes, (3 * kMaxRed + 1) * sizeof(double));
+    if (rc) return rc;
+    r->npart = ctx->red;
+    r->nflag = ctx->red + kMaxRed;
+    r->spart = ctx->red + 2 * kMaxRed;
+    r->se = reinterpret_cast<int*>(ctx->red + 3 * kMaxRed);
+    return SRE2_OK;
+}
+
+// Norm partials (and, for the split form, its scale exponent).
+int norm_stage(sre2_ctx* ctx, const void* work, int N, int form, const Red& r, int nb,
+               hipStream_t st) {
+    Timed tm(ctx, st, SRE2_KIND_AUX);
+    int rc = hip_status(launch_norm(work, work_dtype(form), int64_t(1) << N, nb, r.npart, r.nflag, st));
+    if (!rc && is_split(form)) rc = hip_status(launch_split_scale(r.npart, nb, r.se, st));
     return rc;
 }
 
@@ -273,16 +305,11 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
     int rc = stage_input(ctx, psi, N, dtype, form, st, &work);
     if (rc) return rc;
     const int64_t n = int64_t(1) << N;
-    rc = ensure((void**)&ctx->red, &ctx->red_bytes, 3 * kMaxRed * sizeof(double));
+    Red r;
+    rc = red_buffers(ctx, &r);
     if (rc) return rc;
-    double* npart = ctx->red;
-    double* nflag = ctx->red + kMaxRed;
-    double* spart = ctx->red + 2 * kMaxRed;
     const int nb = red_blocks(n);
-    {
-        Timed tm(ctx, st, SRE2_KIND_AUX);
-        rc = hip_status(launch_norm(work, work_dtype(form), n, nb, npart, nflag, st));
-    }
+    rc = norm_stage(ctx, work, N, form, r, nb, st);
     if (rc) return rc;
     double* Sx = partials;
     if (!Sx) {
@@ -290,15 +317,15 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
         if (rc) return rc;
         Sx = ctx->sx;
     }
-    rc = shift_sums(ctx, work, N, form, 0, n, Sx, st);
+    rc = shift_sums(ctx, work, N, form, 0, n, Sx, r.se, st);
     if (rc) return rc;
     {
         Timed tm(ctx, st, SRE2_KIND_AUX);
-        rc = hip_status(launch_sum(Sx, n, 1, nb, spart, nullptr, st));
+        rc = hip_status(launch_sum(Sx, n, 1, nb, r.spart, nullptr, st));
     }
     if (rc) return rc;
     Timed tm(ctx, st, SRE2_KIND_AUX);
-    return hip_status(launch_final(spart, nb, npart, nflag, nb, N, out, st));
+    return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, st));
 }
 
 }  // namespace
@@ -357,7 +384,7 @@ int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes) {
 size_t sre2_workspace_bytes(int N, int dtype, int form) {
     if (N < 1 || N > SRE2_MAX_N || !dtype_ok(dtype) || !form_ok(form)) return 0;
     const size_t n = size_t(1) << N;
-    size_t b = 3 * kMaxRed * sizeof(double) + n * sizeof(double);
+    size_t b = (3 * kMaxRed + 1) * sizeof(double) + n * sizeof(double);
     if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
     const Chunking ch = chunking(N, form, false, (int64_t)n, size_t(4) << 30);
     if (ch.cs) {
@@ -390,7 +417,14 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
     const void* work = nullptr;
     rc = stage_input(ctx, psi, N, dtype, form, st, &work);
     if (rc) return rc;
-    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, st);
+    Red r;
+    rc = red_buffers(ctx, &r);
+    if (rc) return rc;
+    if (is_split(form)) {
+        rc = norm_stage(ctx, work, N, form, r, red_blocks(n), st);
+        if (rc) return rc;
+    }
+    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, r.se, st);
 }
 
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,

@@ -23,19 +23,22 @@ template <typename Real> int herm_min_n();
 template <typename Real> int64_t pass2_col_tiles(int N, bool herm);
 
 // S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (plain, N < RB) or
-// fused kernel (N <= fused_max_n).
+// fused kernel (N <= fused_max_n).  `split` selects the split-FP16 MFMA
+// transform (FP32 only, not with herm); it reads the scale exponent *se.
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int64_t x0, int64_t xc,
-                               double* S, hipStream_t st);
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
+                               int64_t xc, double* S, const int* se, hipStream_t st);
 // Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
 // row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
 // pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, int64_t x0, int cs, void* scratch,
-                        hipStream_t st);
+hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
+                        void* scratch, const int* se, hipStream_t st);
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, int cs, int P, double* part,
-                        hipStream_t st);
+hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
+                        double* part, const int* se, hipStream_t st);
+// Scale exponent of the split form from the norm partials.
+hipError_t launch_split_scale(const double* npart, int nb, int* se, hipStream_t st);
 
 hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                           hipStream_t st);

@@ -59,6 +59,45 @@ __device__ __forceinline__ double abs4h(C w) {
     return a * a + b * b;
 }
 
+// Slab traffic: streamed through the caches (no reuse until the other pass).
+#ifndef SRE2_NT_SLAB
+#define SRE2_NT_SLAB 1
+#endif
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void slab_store(float2* p, float2 v) {
+    if constexpr (SRE2_NT_SLAB) {
+        f32x2v w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x2v*>(p));
+    } else {
+        *p = v;
+    }
+}
+__device__ __forceinline__ void slab_store(double2* p, double2 v) {
+    if constexpr (SRE2_NT_SLAB) {
+        f64x2v w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<f64x2v*>(p));
+    } else {
+        *p = v;
+    }
+}
+__device__ __forceinline__ float2 slab_load(const float2* p) {
+    if constexpr (SRE2_NT_SLAB) {
+        const f32x2v w = __builtin_nontemporal_load(reinterpret_cast<const f32x2v*>(p));
+        return make_float2(w.x, w.y);
+    } else {
+        return *p;
+    }
+}
+__device__ __forceinline__ double2 slab_load(const double2* p) {
+    if constexpr (SRE2_NT_SLAB) {
+        const f64x2v w = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p));
+        return make_double2(w.x, w.y);
+    } else {
+        return *p;
+    }
+}
+
 // Insert a zero bit at position `hb` of `v`.
 __device__ __forceinline__ uint32_t insert0(uint32_t v, uint32_t hb) {
     return ((v >> hb) << (hb + 1)) | (v & ((1u << hb) - 1u));
@@ -138,6 +177,140 @@ struct RoundRunner {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Split-FP16 MFMA form.  H_16 = H_2^{(x)4} applied along four tile bits is a
+// 16x16 matrix of +-1 (exact in FP16).  Each FP32 value v (pre-scaled by a
+// power of two so that every |v| <= 2^14) is split into hi = fp16(v) and
+// lo = fp16(v - hi) (both rounded to nearest; v - hi is exact in FP32), and
+// one v_mfma_f32_16x16x32_f16 computes H_16 (hi + lo) with FP32 accumulation
+// for a 16 x 16 block: K = 32 holds the hi and lo halves of 16 rows.
+// Operand layout (lane l, i = l % 16, g = l / 16):
+//   A[i][8g + j], B[8g + j][i] for j = 0..7,  D[4g + r][i] for r = 0..3.
+// K order used here: k = 8g + j  ->  row 4g + (j & 3), part j >> 2 (hi, lo),
+// so lane l feeds rows 4g..4g+3 and receives the same rows back.
+// ---------------------------------------------------------------------------
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ half8 h16_operand() {
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, g = l >> 4;
+    half8 a;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = 4 * g + (j & 3);
+        a[j] = (__builtin_popcount(i & k) & 1) ? (_Float16)-1.0f : (_Float16)1.0f;
+    }
+    return a;
+}
+
+typedef float f32x2c __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to FP16, rounded to nearest (v_cvt_pk_f16_f32).
+__device__ __forceinline__ half2v pk_rne(float a, float b) {
+    const f32x2c v = {a, b};
+    return __builtin_convertvector(v, half2v);
+}
+
+// hi/lo halves of four values in the K order above.  hi = fp16(v) rounded to
+// nearest; v - hi is exact in FP32 (it is an integer multiple of v's FP32 ulp
+// below 2^13 of them), and lo = fp16(v - hi), also rounded to nearest, so the
+// split carries no systematic bias.
+__device__ __forceinline__ half8 split4(float a, float b, float c, float d) {
+    const half2v hab = pk_rne(a, b);
+    const half2v hcd = pk_rne(c, d);
+    const half2v lab = pk_rne(a - (float)hab[0], b - (float)hab[1]);
+    const half2v lcd = pk_rne(c - (float)hcd[0], d - (float)hcd[1]);
+    half8 r = {hab[0], hab[1], hcd[0], hcd[1], lab[0], lab[1], lcd[0], lcd[1]};
+    return r;
+}
+
+// H_16 along the four tile bits of F on a complex FP32 tile held in LDS
+// (swizzled addresses).  Columns: the lowest four tile bits outside F; the
+// other TB - 8 bits enumerate 16 x 16 blocks, shared round-robin by the waves.
+// Every lane reads and rewrites the same four elements of a block.
+template <int TB, int SB, uint32_t F, int NWAVES>
+__device__ __forceinline__ void mfma_h16(float2* lds, const half8 amat) {
+    constexpr uint32_t FULL = (1u << TB) - 1u;
+    constexpr uint32_t CM = low_bits(FULL & ~F, 4);
+    constexpr uint32_t BM = FULL & ~F & ~CM;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t ecol = pdep((uint32_t)(l & 15), CM);
+    uint32_t erow[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) erow[j] = pdep((uint32_t)(4 * (l >> 4) + j), F) | ecol;
+    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+    for (int b = w; b < (1 << (TB - 8)); b += NWAVES) {
+        const uint32_t eb = pdep((uint32_t)b, BM);
+        float2 x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = lds[swz<SB>(eb | erow[j])];
+        const half8 br = split4(x[0].x, x[1].x, x[2].x, x[3].x);
+        const half8 bi = split4(x[0].y, x[1].y, x[2].y, x[3].y);
+        const floatx4 dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
+        const floatx4 di = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[swz<SB>(eb | erow[j])] = make_float2(dr[j], di[j]);
+    }
+}
+
+// Successive H_16 factors over the bits of FB, four at a time from the bottom.
+template <int TB, int SB, uint32_t FB, int NWAVES>
+__device__ __forceinline__ void mfma_factors(float2* lds, const half8 amat) {
+    if constexpr (FB != 0) {
+        constexpr uint32_t F = low_bits(FB, 4);
+        mfma_h16<TB, SB, F, NWAVES>(lds, amat);
+        __syncthreads();
+        mfma_factors<TB, SB, FB & ~F, NWAVES>(lds, amat);
+    }
+}
+
+template <int TB, int RB, int PK>
+__host__ __device__ constexpr uint32_t transform_mask() {
+    constexpr Plan P = plan_of<float, TB, RB, PK>();
+    uint32_t m = 0;
+    for (int j = 0; j < P.nrounds; ++j) m |= P.r[j].bfly;
+    return m;
+}
+
+// Bits of the split form done by VALU butterflies in the first round (the
+// transform bit count modulo 4, taken from the top of round 0's registers);
+// the rest go through H_16 factors.
+template <int TB, int RB, int PK>
+__host__ __device__ constexpr uint32_t split_rem_mask() {
+    constexpr Plan P = plan_of<float, TB, RB, PK>();
+    constexpr uint32_t T = transform_mask<TB, RB, PK>();
+    return top_bits(P.r[0].reg & T, popc(T) % 4);
+}
+
+// Whole transform from round 0's register layout to the last round's.
+template <typename Real, int TB, int RB, int PK, bool SPLIT>
+__device__ __forceinline__ void run_transform(typename CT<Real>::T* lds,
+                                              typename CT<Real>::T (&v)[1 << RB]) {
+    constexpr Plan P = plan_of<Real, TB, RB, PK>();
+    constexpr Round r0 = P.r[0];
+    if constexpr (!SPLIT) {
+        butterflies<RB, r0.reg, r0.bfly>(v);
+        RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
+    } else {
+        static_assert(sizeof(Real) == 4, "the split form works on FP32 values");
+        constexpr int SB = Prec<Real>::SB;
+        constexpr Round rl = P.r[P.nrounds - 1];
+        constexpr uint32_t REM = split_rem_mask<TB, RB, PK>();
+        constexpr uint32_t FB = transform_mask<TB, RB, PK>() & ~REM;
+        butterflies<RB, r0.reg, REM>(v);
+        if constexpr (FB != 0) {
+            const half8 amat = h16_operand();
+            __syncthreads();
+            lds_put<SB, RB, r0.reg, r0.lane, r0.wave>(lds, v);
+            __syncthreads();
+            mfma_factors<TB, SB, FB, (1 << (TB - RB)) / 64>(lds, amat);
+            lds_get<SB, RB, rl.reg, rl.lane, rl.wave>(lds, v);
+        }
+    }
+}
+
 // Fixed-shape tree over T doubles in LDS; segments of `seg` consecutive entries
 // are reduced independently (seg divides T, both powers of two).  Result of
 // segment j lands in red[j * seg].
@@ -183,10 +356,10 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 //                Re or twice i Im of this half transform, so
 //                S_x = 16 sum_z' (Re^4 + Im^4).
 // ---------------------------------------------------------------------------
-template <typename Real, int NT, int TB, int RB, bool HERM>
+template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
-             double* __restrict__ S_out) {
+             double* __restrict__ S_out, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 1000 + NT;
@@ -198,6 +371,9 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     __shared__ C lds[1 << TB];
     double* red = reinterpret_cast<double*>(lds);
 
+    const int se = SPLIT ? *scale_exp : 0;
+    const Real sc = SPLIT ? ldexpf(1.0f, se) : Real(1);
+    const double unscale = SPLIT ? ldexp(1.0, -4 * se) : 1.0;
     const int64_t ntiles = (x_count + SPT - 1) / SPT;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t x0 = x_begin + tile * SPT;  // first shift of the tile
@@ -213,18 +389,22 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
                     uint32_t k = e & KMASK;
                     if constexpr (HERM) k = insert0(k, 31u - __clz(x));
                     v[i] = cmul_conj_a(psi[k ^ x], psi[k]);
+                    if constexpr (SPLIT) {
+                        v[i].x *= sc;
+                        v[i].y *= sc;
+                    }
                 } else {
                     v[i].x = 0;
                     v[i].y = 0;
                 }
             }
         }
-        butterflies<RB, r0.reg, r0.bfly>(v);
-        RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
+        run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) s += HERM ? abs4h(v[i]) : abs4(v[i]);
         if constexpr (HERM) s *= 16.0;
+        if constexpr (SPLIT) s *= unscale;
         // thread order index: tile bits outside the last round's registers,
         // compressed; its top TB-NT bits are the shift slot.
         const uint32_t q = pext(thread_base<rl.lane, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
@@ -245,10 +425,10 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // row bit and only rows with that bit clear are built).  Block b -> slab row
 // b / cs, shift slot b % cs, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
-template <typename Real, int TB, int RB, bool HERM>
+template <typename Real, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
-             typename CT<Real>::T* __restrict__ scratch) {
+             typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
     constexpr int PK = 2000;
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
@@ -275,13 +455,20 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
             const uint32_t e = base | pdep((uint32_t)i, r0.reg);
             v[i] = cmul_conj_a(pb[e ^ xlo], pa[e]);
         }
+        if constexpr (SPLIT) {
+            const Real sc = ldexpf(1.0f, *scale_exp);
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                v[i].x *= sc;
+                v[i].y *= sc;
+            }
+        }
     }
-    butterflies<RB, r0.reg, r0.bfly>(v);
-    RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
+    run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
     C* __restrict__ out = scratch + ((uint64_t)s << NS) + ((uint64_t)srow << TB);
     const uint32_t base = thread_base<rl.lane, rl.wave>();
 #pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) out[base | pdep((uint32_t)i, rl.reg)] = v[i];
+    for (int i = 0; i < (1 << RB); ++i) slab_store(out + (base | pdep((uint32_t)i, rl.reg)), v[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -290,10 +477,10 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // columns.  Block b -> shift slot b / P, column group b % P; the group loops
 // over its column tiles and writes one FP64 partial of S_x.
 // ---------------------------------------------------------------------------
-template <typename Real, int HT, int TB, int RB, bool HERM>
+template <typename Real, int HT, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
-             double* __restrict__ part) {
+             double* __restrict__ part, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 3000 + HT;
@@ -301,7 +488,9 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     constexpr Round r0 = PL.r[0];
     constexpr int CB = TB - HT;  // column bits per tile
     constexpr uint32_t CMASK = (1u << CB) - 1u;
-    __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
+    constexpr bool NEED_LDS =
+        PL.nrounds > 1 || (SPLIT && (transform_mask<TB, RB, PK>() & ~split_rem_mask<TB, RB, PK>()));
+    __shared__ C lds[NEED_LDS ? (1 << TB) : 1];
     __shared__ double red[T];
 
     const int64_t b = blockIdx.x;
@@ -319,14 +508,14 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t e = base | pdep((uint32_t)i, r0.reg);
-            v[i] = src[((uint64_t)(e >> CB) << L) + (e & CMASK)];
+            v[i] = slab_load(src + ((uint64_t)(e >> CB) << L) + (e & CMASK));
         }
-        butterflies<RB, r0.reg, r0.bfly>(v);
-        if constexpr (PL.nrounds > 1) RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
+        run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
     }
     if constexpr (HERM) acc *= 16.0;
+    if constexpr (SPLIT) acc *= ldexp(1.0, -4 * *scale_exp);
     red[threadIdx.x] = acc;
     seg_tree<T>(red, T);
     if (threadIdx.x == 0) part[b] = red[0];
@@ -456,25 +645,26 @@ hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S, hip
     return hipGetLastError();
 }
 
-template <typename Real, int NT, bool HERM>
-hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
+template <typename Real, int NT, bool HERM, bool SPLIT>
+hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, const int* se,
+                           hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = fused_tb<Real>(NT), RB = Tune<Real>::RBF;
     constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM>), dim3((unsigned)grid),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S);
+    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT>), dim3((unsigned)grid),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se);
     return hipGetLastError();
 }
 
-template <typename Real, int HT, bool HERM>
-hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part,
+template <typename Real, int HT, bool HERM, bool SPLIT>
+hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part, const int* se,
                            hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
-    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM>), dim3((unsigned)((int64_t)cs * P)),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part);
+    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM, SPLIT>), dim3((unsigned)((int64_t)cs * P)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part, se);
     return hipGetLastError();
 }
 
@@ -486,21 +676,24 @@ hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double*
     return e;
 }
 
-template <typename Real, bool HERM, int... Ns>
+template <typename Real, bool HERM, bool SPLIT, int... Ns>
 hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, double* S,
-                          hipStream_t st, std::integer_sequence<int, Ns...>) {
+                          const int* se, hipStream_t st, std::integer_sequence<int, Ns...>) {
     constexpr int RB = Tune<Real>::RBF;
     hipError_t e = hipErrorInvalidValue;
-    ((NT == Ns + RB ? (e = launch_fused_nt<Real, Ns + RB, HERM>(psi, x0, xc, S, st), 0) : 0), ...);
+    ((NT == Ns + RB ? (e = launch_fused_nt<Real, Ns + RB, HERM, SPLIT>(psi, x0, xc, S, se, st), 0)
+                    : 0),
+     ...);
     return e;
 }
 
-template <typename Real, bool HERM, int... Hs>
+template <typename Real, bool HERM, bool SPLIT, int... Hs>
 hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, double* part,
-                          hipStream_t st, std::integer_sequence<int, Hs...>) {
+                          const int* se, hipStream_t st, std::integer_sequence<int, Hs...>) {
     hipError_t e = hipErrorInvalidValue;
-    ((HT == Hs + 1 ? (e = launch_pass2_ht<Real, Hs + 1, HERM>(scratch, NS, cs, P, part, st), 0)
-                   : 0),
+    ((HT == Hs + 1
+          ? (e = launch_pass2_ht<Real, Hs + 1, HERM, SPLIT>(scratch, NS, cs, P, part, se, st), 0)
+          : 0),
      ...);
     return e;
 }
@@ -549,61 +742,102 @@ template int64_t pass2_col_tiles<float>(int, bool);
 template int64_t pass2_col_tiles<double>(int, bool);
 
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int64_t x0, int64_t xc,
-                               double* S, hipStream_t st) {
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
+                               int64_t xc, double* S, const int* se, hipStream_t st) {
     constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
-    if (N > FMAX) return hipErrorInvalidValue;
+    if (N > FMAX || (split && (herm || sizeof(Real) != 4))) return hipErrorInvalidValue;
     if (herm) {
         if (x0 < 1 || N - 1 < RB) return hipErrorInvalidValue;
-        return dispatch_fused<Real, true>(N - 1, psi, x0, xc, S, st,
-                                          std::make_integer_sequence<int, FMAX - RB>{});
+        return dispatch_fused<Real, true, false>(N - 1, psi, x0, xc, S, se, st,
+                                                 std::make_integer_sequence<int, FMAX - RB>{});
     }
     if (N < RB)
         return dispatch_tiny<Real>(N, psi, x0, xc, S, st, std::make_integer_sequence<int, RB - 1>{});
-    return dispatch_fused<Real, false>(N, psi, x0, xc, S, st,
-                                       std::make_integer_sequence<int, FMAX - RB + 1>{});
+    if constexpr (sizeof(Real) == 4) {
+        if (split)
+            return dispatch_fused<Real, false, true>(N, psi, x0, xc, S, se, st,
+                                                     std::make_integer_sequence<int, FMAX - RB + 1>{});
+    }
+    return dispatch_fused<Real, false, false>(N, psi, x0, xc, S, se, st,
+                                              std::make_integer_sequence<int, FMAX - RB + 1>{});
 }
 
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, int64_t x0, int cs, void* scratch,
-                        hipStream_t st) {
+hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
+                        void* scratch, const int* se, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = Tune<Real>::ROW, RB = Tune<Real>::RB1;
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
+    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
     if (herm && x0 < ((int64_t)1 << TB)) return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
     const int64_t rows = (int64_t)1 << (NS - TB);
+    const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB));
     if (herm)
-        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true>), dim3((unsigned)(rows * cs)),
-                           dim3(1 << (TB - RB)), 0, st, (const C*)psi, NS, x0, cs, (C*)scratch);
-    else
-        hipLaunchKernelGGL((k_pass1<Real, TB, RB, false>), dim3((unsigned)(rows * cs)),
-                           dim3(1 << (TB - RB)), 0, st, (const C*)psi, NS, x0, cs, (C*)scratch);
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, false>), grid, block, 0, st, (const C*)psi,
+                           NS, x0, cs, (C*)scratch, se);
+    else if (split) {
+        if constexpr (sizeof(Real) == 4)
+            hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, true>), grid, block, 0, st,
+                               (const C*)psi, NS, x0, cs, (C*)scratch, se);
+    } else
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, false>), grid, block, 0, st,
+                           (const C*)psi, NS, x0, cs, (C*)scratch, se);
     return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, int cs, int P, double* part,
-                        hipStream_t st) {
+hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
+                        double* part, const int* se, hipStream_t st) {
     constexpr int ROW = Tune<Real>::ROW;
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
+    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
     constexpr int HMAX = max_n_of<Real>() - ROW;
     if (herm)
-        return dispatch_pass2<Real, true>(NS - ROW, scratch, NS, cs, P, part, st,
-                                          std::make_integer_sequence<int, HMAX>{});
-    return dispatch_pass2<Real, false>(NS - ROW, scratch, NS, cs, P, part, st,
-                                       std::make_integer_sequence<int, HMAX>{});
+        return dispatch_pass2<Real, true, false>(NS - ROW, scratch, NS, cs, P, part, se, st,
+                                                 std::make_integer_sequence<int, HMAX>{});
+    if constexpr (sizeof(Real) == 4) {
+        if (split)
+            return dispatch_pass2<Real, false, true>(NS - ROW, scratch, NS, cs, P, part, se, st,
+                                                     std::make_integer_sequence<int, HMAX>{});
+    }
+    return dispatch_pass2<Real, false, false>(NS - ROW, scratch, NS, cs, P, part, se, st,
+                                              std::make_integer_sequence<int, HMAX>{});
 }
 
-template hipError_t launch_shift_kernel<float>(const void*, int, bool, int64_t, int64_t, double*,
-                                               hipStream_t);
-template hipError_t launch_shift_kernel<double>(const void*, int, bool, int64_t, int64_t, double*,
-                                                hipStream_t);
-template hipError_t launch_pass1<float>(const void*, int, bool, int64_t, int, void*, hipStream_t);
-template hipError_t launch_pass1<double>(const void*, int, bool, int64_t, int, void*, hipStream_t);
-template hipError_t launch_pass2<float>(const void*, int, bool, int, int, double*, hipStream_t);
-template hipError_t launch_pass2<double>(const void*, int, bool, int, int, double*, hipStream_t);
+template hipError_t launch_shift_kernel<float>(const void*, int, bool, bool, int64_t, int64_t,
+                                               double*, const int*, hipStream_t);
+template hipError_t launch_shift_kernel<double>(const void*, int, bool, bool, int64_t, int64_t,
+                                                double*, const int*, hipStream_t);
+template hipError_t launch_pass1<float>(const void*, int, bool, bool, int64_t, int, void*,
+                                        const int*, hipStream_t);
+template hipError_t launch_pass1<double>(const void*, int, bool, bool, int64_t, int, void*,
+                                         const int*, hipStream_t);
+template hipError_t launch_pass2<float>(const void*, int, bool, bool, int, int, double*,
+                                        const int*, hipStream_t);
+template hipError_t launch_pass2<double>(const void*, int, bool, bool, int, int, double*,
+                                         const int*, hipStream_t);
+
+// s = 14 - ceil(log2 n) from the norm partials (0 when n is not positive and
+// finite): with every |value| of a transform bounded by n, the scaled values
+// of the split form stay below 2^14, inside FP16's range.
+__global__ void k_split_scale(const double* __restrict__ npart, int nb, int* __restrict__ se) {
+    if (threadIdx.x != 0) return;
+    double n = 0.0;
+    for (int i = 0; i < nb; ++i) n += npart[i];
+    int s = 0;
+    if (n > 0.0 && isfinite(n)) {
+        s = 14 - (int)ceil(log2(n));
+        s = s < -100 ? -100 : (s > 100 ? 100 : s);
+    }
+    *se = s;
+}
+
+hipError_t launch_split_scale(const double* npart, int nb, int* se, hipStream_t st) {
+    hipLaunchKernelGGL(k_split_scale, dim3(1), dim3(64), 0, st, npart, nb, se);
+    return hipGetLastError();
+}
 
 hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                           hipStream_t st) {

@@ -22,9 +22,16 @@ pytestmark = pytest.mark.gpu
 import paper_2512_24685_amd as sre2  # noqa: E402
 
 LOG43 = np.log2(4.0 / 3.0)
-TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9, "fp32h": 1e-5, "fp64h": 1e-9}
-TOL_SX = {"fp32": 1e-4, "fp64": 1e-11, "fp32h": 1e-4, "fp64h": 1e-11}
-FORMS = ["fp32", "fp64", "fp32h", "fp64h"]
+TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9, "fp32h": 1e-5, "fp64h": 1e-9, "split16": 1e-5}
+TOL_SX = {"fp32": 1e-4, "fp64": 1e-11, "fp32h": 1e-4, "fp64h": 1e-11, "split16": 1e-4}
+FORMS = ["fp32", "fp64", "fp32h", "fp64h", "split16"]
+# Closed forms on complex64 inputs: the amplitude rounding alone moves M2 by
+# < 1e-6; the split form's 22-bit hi/lo values add up to its 1e-5 bound.
+CLOSED_TOL = {"split16": 1e-5}
+
+
+def closed_tol(form):
+    return CLOSED_TOL.get(form, 1e-6)
 
 
 def is64(form):
@@ -83,18 +90,18 @@ def test_input_dtype_conversion(oracle_mod, form, dtype):
 def test_closed_forms(form, N):
     case_id("closed", N, form)
     r = sre2.m2(dev(W.t_product(N, np.complex64)), form=form)
-    assert abs(r.m2 - N * LOG43) <= 1e-6
+    assert abs(r.m2 - N * LOG43) <= closed_tol(form)
     r = sre2.m2(dev(W.t_product(N, np.complex128)), form=form)
-    assert abs(r.m2 - N * LOG43) <= (1e-12 if is64(form) else 1e-6)
+    assert abs(r.m2 - N * LOG43) <= (1e-12 if is64(form) else closed_tol(form))
     g = sre2.m2(dev(W.graph(N, 900 + N, dtype=np.complex64)), form=form)
     if N % 2 == 0:
-        assert g.m2 == 0.0  # every value is an exact dyadic in both forms
+        assert g.m2 == 0.0  # every value is an exact dyadic in every form
     else:
-        assert abs(g.m2) <= 1e-6
+        assert abs(g.m2) <= closed_tol(form)
     m = min(N, 5)
     psi, _ = W.graph_t(N, m, 50 + N, dtype=np.complex64)
     r = sre2.m2(dev(psi), form=form)
-    assert abs(r.m2 - m * LOG43) <= 1e-6
+    assert abs(r.m2 - m * LOG43) <= closed_tol(form)
 
 
 def test_scale_invariance_and_bad_inputs(oracle_mod):
@@ -133,7 +140,7 @@ def test_shard_sum_equals_whole():
     assert abs(sum(parts) - r.S) <= 1e-12 * r.S
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
 def test_determinism_and_batched(form):
     psis = [dev(W.haar(N, 60 + N, np.complex64)) for N in (3, 8, 12, 15, 16)]
     case_id("determinism", form)
@@ -198,10 +205,10 @@ def test_n20_full_size(oracle_mod, form):
         assert abs(r.m2 - (np.log2(2 ** 20 + 3) - 2)) < 1e-3  # Haar law (sanity)
     psi_t, _ = W.graph_t(20, 10, W.config_seed(3) + 1, dtype=np.complex64)
     rt = sre2.m2(dev(psi_t), form=form)
-    assert abs(rt.m2 - 10 * LOG43) <= 1e-6
+    assert abs(rt.m2 - 10 * LOG43) <= closed_tol(form)
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
 @pytest.mark.parametrize("N", [22, 24])
 def test_large_n_sampled_shifts(N, form):
     g = _golden()

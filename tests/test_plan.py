@@ -305,3 +305,87 @@ def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec, extra, herm):
     S = emulate_two_pass_partials(probe, psi, prec, xs, herm)
     ref = oracle_mod.partials(psi, xs)
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Split-FP16 MFMA form: remainder butterflies in round 0, then H_16 factors on
+# the LDS tile with the MFMA lane addressing (rows 4g+j on factor bits,
+# columns on the lowest four other bits, blocks on the rest).
+# ---------------------------------------------------------------------------
+
+def low_bits_mask(m, count):
+    r = 0
+    for b in range(32):
+        if count == 0:
+            break
+        if (m >> b) & 1:
+            r |= 1 << b
+            count -= 1
+    return r
+
+
+def top_bits_mask(m, count):
+    r = 0
+    for b in reversed(range(32)):
+        if count == 0:
+            break
+        if (m >> b) & 1:
+            r |= 1 << b
+            count -= 1
+    return r
+
+
+H16 = np.array([[(-1) ** bin(i & k).count("1") for k in range(16)] for i in range(16)], float)
+
+
+def mfma_h16_emul(lds, tb, sb, F):
+    full = (1 << tb) - 1
+    CM = low_bits_mask(full & ~F, 4)
+    BM = full & ~F & ~CM
+    lanes = np.arange(64)
+    for b in range(1 << (tb - 8)):
+        eb = pdep(np.array([b]), BM)[0]
+        ecol = pdep(lanes & 15, CM)
+        rows = [pdep(4 * (lanes >> 4) + j, F) | ecol | eb for j in range(4)]
+        X = np.zeros((16, 16), dtype=np.complex128)  # [k][n]
+        for j in range(4):
+            X[4 * (lanes >> 4) + j, lanes & 15] = lds[swz_np(sb, rows[j])]
+        D = H16 @ X
+        for j in range(4):
+            lds[swz_np(sb, rows[j])] = D[4 * (lanes >> 4) + j, lanes & 15]
+
+
+def run_tile_split(X, rounds, tb, rb, sb):
+    T = 0
+    for rd in rounds:
+        T |= rd[1]
+    r0, rl = rounds[0], rounds[-1]
+    REM = top_bits_mask(r0[0] & T, bin(T).count("1") % 4)
+    FB = T & ~REM
+    E0 = mapping(r0, tb, rb)
+    V = bfly(X[E0], r0[0], REM)
+    if FB == 0:
+        out = np.empty_like(X)
+        out[E0] = V
+        return out
+    lds = np.full(1 << tb, np.nan + 0j)
+    lds[swz_np(sb, E0)] = V
+    while FB:
+        F = low_bits_mask(FB, 4)
+        mfma_h16_emul(lds, tb, sb, F)
+        FB &= ~F
+    El = mapping(rl, tb, rb)
+    V = lds[swz_np(sb, El)]
+    out = np.empty_like(X)
+    out[El] = V
+    return out
+
+
+def test_split_transform_matches_wht(probe):
+    rng = np.random.default_rng(5)
+    for prec, kind, par, (tb, rb, sb, lo, hi) in all_plans(probe):
+        if prec != 0:
+            continue
+        X = rng.standard_normal(1 << tb) + 1j * rng.standard_normal(1 << tb)
+        out = run_tile_split(X, plan(probe, tb, rb, sb, lo, hi), tb, rb, sb)
+        assert np.allclose(out, wht_bits(X, lo, hi)), (kind, par)
