@@ -64,7 +64,7 @@ def alg_units(N: int, form: str, kind: str, cs: int):
     over the L row bits; pass 2 = 2 per stage over the remaining bits + 5
     (|W|^2, square in FP64, FP64 add); Hermitian pass 2: + 1 (two squares).
     """
-    base = form.rstrip("h")
+    base = "fp64" if form.startswith("fp64") else "fp32"
     herm = form.endswith("h")
     ns = N - (1 if herm else 0)
     vals = cs * (1 << ns)
@@ -176,17 +176,111 @@ def copy_calibration(mib: int):
     log(f"copied {mib} MiB ten times ({n * 4} bytes read and written per copy)")
 
 
+def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
+                      n_lo: int = 8, n_hi: int = 18):
+    """Poisson stream of `count` requests (N ~ U{n_lo..n_hi}, Haar or graph+T,
+    complex64 host states), replayed at the same arrival times against (a)
+    one-at-a-time sre2_m2 calls and (b) the continuous-batching server.
+    The arrival rate is `load` / (mean one-at-a-time service time)."""
+    reqs = W.serving_requests(count, n_min=n_lo, n_max=n_hi)
+    states = [W.build_request(r) for r in reqs]
+    log(f"serving: {count} requests generated")
+    # calibration of the one-at-a-time service time per N
+    t_n = {}
+    for N in sorted({r["N"] for r in reqs}):
+        psi = next(p for p, r in zip(states, reqs) if r["N"] == N)
+        best = 1e9
+        for _ in range(3):
+            t0 = time.perf_counter()
+            sre2.m2(torch.from_numpy(psi).to("cuda:0"), form=form)
+            best = min(best, time.perf_counter() - t0)
+        t_n[N] = best
+    mean_service = float(np.mean([t_n[r["N"]] for r in reqs]))
+    lam = load / mean_service
+    arrivals = np.cumsum(np.random.default_rng(W.config_seed(4) + 1).exponential(1 / lam, count))
+    work = float(sum(4.0 ** r["N"] for r in reqs))
+
+    def wait_until(t):
+        while True:
+            dt = t - time.perf_counter()
+            if dt <= 0:
+                return
+            time.sleep(min(dt, 0.0005))
+
+    # (a) one request at a time, in arrival order
+    base_res, base_lat = [], []
+    t0 = time.perf_counter() + 0.05
+    for i, psi in enumerate(states):
+        wait_until(t0 + arrivals[i])
+        r = sre2.m2(torch.from_numpy(psi).to("cuda:0"), form=form)
+        base_lat.append(time.perf_counter() - (t0 + arrivals[i]))
+        base_res.append(r)
+    base_makespan = time.perf_counter() - t0
+    log(f"serving: one-at-a-time done in {base_makespan:.1f} s")
+
+    # (b) continuous batching
+    srv = sre2.Server(form=form, hbm_budget=8 << 30, max_slots=2048)
+    tickets, lag = [], []
+    done = {}
+    t0 = time.perf_counter() + 0.05
+
+    def poll_some():
+        for j in range(len(tickets)):
+            if j in done:
+                continue
+            st, res, lat = srv.poll(tickets[j])
+            if st >= sre2.REQ_DONE:
+                done[j] = (st, res, lat + lag[j])
+
+    for i, psi in enumerate(states):
+        while time.perf_counter() < t0 + arrivals[i]:
+            poll_some()
+            time.sleep(0.0002)
+        lag.append(time.perf_counter() - (t0 + arrivals[i]))
+        tickets.append(srv.submit(psi))
+    while len(done) < count:
+        poll_some()
+        time.sleep(0.0002)
+    srv_makespan = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    log(f"serving: server done in {srv_makespan:.1f} s; stats={stats}")
+    mismatch = sum(1 for j in range(count)
+                   if done[j][1].m2 != base_res[j].m2 or done[j][1].S != base_res[j].S)
+    srv_lat = [done[j][2] for j in range(count)]
+
+    def pct(v, q):
+        return float(np.percentile(np.array(v) * 1e3, q))
+
+    return {
+        "requests": count, "N_range": [n_lo, n_hi], "form": form,
+        "arrival_rate_per_s": lam, "load_vs_one_at_a_time": load,
+        "pauli_strings": work,
+        "server": {"throughput_pauli_per_s": work / srv_makespan,
+                   "requests_per_s": count / srv_makespan, "makespan_s": srv_makespan,
+                   "p50_ms": pct(srv_lat, 50), "p99_ms": pct(srv_lat, 99), "stats": stats},
+        "one_at_a_time": {"throughput_pauli_per_s": work / base_makespan,
+                          "requests_per_s": count / base_makespan,
+                          "makespan_s": base_makespan,
+                          "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99)},
+        "results_bitwise_equal": mismatch == 0, "mismatches": mismatch,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="fp32")
-    ap.add_argument("--also", default="fp32h", help="other forms, comma separated")
+    ap.add_argument("--also", default="fp32h,split16", help="other forms, comma separated")
     ap.add_argument("--N", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--serving", type=int, default=160, metavar="R",
+                    help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--profile-chunks", type=int, default=0, metavar="C",
                     help="run only C two-pass chunks (the benchmark's launch shape) from "
                          "x = 2^(N-1), for counter collection")
@@ -204,6 +298,12 @@ def main():
 
     import paper_2512_24685_amd as sre2
     import workloads as W
+
+    if args.serving_only:
+        rec = serving_benchmark(sre2, torch, W, args.serving, "fp32")
+        print(json.dumps({"metric": "serving stream: Pauli strings/s and p50/p99 latency",
+                          "serving": rec}), flush=True)
+        return
 
     N = args.N
     log(f"bench: N={N} form={args.form} also={args.also} steps={args.steps} warmup={args.warmup}")
@@ -238,6 +338,9 @@ def main():
                                          stored_traffic(fk, N, f)),
                     "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps // 2), 3)
                                             for k, v in fkt.items()}}
+    serving = None
+    if args.serving:
+        serving = serving_benchmark(sre2, torch, W, args.serving, "fp32")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: timing the FP64 oracle on a sample of shifts ...")
@@ -263,6 +366,7 @@ def main():
                    "shifts_per_chunk": cs, "column_groups": P, "M2": m2},
         "roofline": roof,
         "forms": forms,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -142,7 +142,10 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
  *   psi_list  HOST array of `count` device pointers
  *   N_list    HOST array of `count` qubit counts
  *   out       device, SRE2_OUT_LEN * count doubles (state i at out + 4 i)
- * Each state's result is bitwise identical to a single sre2_m2 call. */
+ * States with the same N <= 14 (FP32 forms) / 13 (FP64 forms) are packed, up
+ * to 64 per launch, into shared launches of the same kernels (the grid's y
+ * index selects the state); larger N run one after another.  Each state's
+ * result is bitwise identical to a single sre2_m2 call. */
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,
                     int dtype, int form, void* stream, double* out);
 
@@ -169,6 +172,75 @@ int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches);
  * shifts per chunk (0 when N uses the fused kernel) and column groups per
  * shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups);
+
+/* ---- serving loop (continuous batching) ------------------------------- */
+/* A server owns a worker thread, two HIP streams, a device arena of
+ * hbm_budget_bytes and max_slots request slots.  Requests are admitted in FIFO
+ * order while a slot is free and their state fits the arena (admission by HBM
+ * footprint; a full arena is backpressure, later requests wait).  Newly
+ * admitted requests are enqueued at once, without waiting for running work:
+ * requests with N <= 14 (FP32 forms) / 13 (FP64 forms) admitted together are
+ * packed by N into shared launches on one stream, larger N run one by one on
+ * a second stream, so their work overlaps on the device.  A request's result
+ * is bitwise identical to a single sre2_m2 call on the same state and form. */
+typedef struct sre2_server sre2_server;
+
+#define SRE2_REQ_QUEUED 0    /* waiting for a slot / memory            */
+#define SRE2_REQ_RUNNING 1   /* admitted, work enqueued on the device  */
+#define SRE2_REQ_DONE 2      /* result available                       */
+#define SRE2_REQ_CANCELLED 3 /* cancelled; result undefined            */
+#define SRE2_REQ_FAILED 4    /* a HIP error hit its work               */
+
+#define SRE2_SERVER_STAT_SUBMITTED 0
+#define SRE2_SERVER_STAT_ADMITTED 1
+#define SRE2_SERVER_STAT_COMPLETED 2
+#define SRE2_SERVER_STAT_CANCELLED 3
+#define SRE2_SERVER_STAT_PACKS 4         /* packed launches (small N)        */
+#define SRE2_SERVER_STAT_PACKED_STATES 5 /* states that went through packs    */
+#define SRE2_SERVER_STAT_SINGLES 6       /* single-state launches (large N)  */
+#define SRE2_SERVER_STAT_PEAK_BYTES 7    /* peak arena bytes in use          */
+#define SRE2_SERVER_STAT_PEAK_INFLIGHT 8 /* peak admitted, unfinished requests */
+#define SRE2_SERVER_STAT_COUNT 9
+
+/* Create a server on `hip_device` for one arithmetic form.
+ * Errors: SRE2_EINVAL (null out, device < 0, max_slots < 1, budget < 1 MiB),
+ * SRE2_EFORM, SRE2_ENOMEM (arena or result buffers), SRE2_EHIP. */
+int sre2_server_create(sre2_server** out, int hip_device, int form, size_t hbm_budget_bytes,
+                       int max_slots);
+
+/* Submit one state of 2^N amplitudes of `dtype`; returns at once with a
+ * ticket.  psi_on_device = 0: psi is host memory, copied before return (a
+ * non-finite amplitude is rejected with SRE2_ENORM); 1: psi is device memory
+ * whose producing work is already complete (the server copies it on its own
+ * streams) and that stays valid until the request is done.
+ * Errors: SRE2_EINVAL, SRE2_EDTYPE, SRE2_EFORM, SRE2_ENORM, SRE2_ENOMEM (the
+ * state can never fit the arena), SRE2_EBUSY (server stopping). */
+int sre2_server_submit(sre2_server* s, const void* psi, int N, int dtype, int psi_on_device,
+                       uint64_t* ticket);
+
+/* Non-blocking: *state = SRE2_REQ_*.  When the state is final (DONE,
+ * CANCELLED, FAILED) the result (host, SRE2_OUT_LEN doubles: M2, S, n,
+ * status; may be NULL) and the latency from submit to completion (seconds, may
+ * be NULL) are returned and the ticket is released.
+ * Errors: SRE2_EINVAL, SRE2_ENOTFOUND (unknown or released ticket). */
+int sre2_server_poll(sre2_server* s, uint64_t ticket, int* state, double* result,
+                     double* latency_s);
+
+/* Cancel a request: a queued request is dropped before admission, a running
+ * one finishes but reports SRE2_REQ_CANCELLED.  Errors: SRE2_EINVAL,
+ * SRE2_ENOTFOUND. */
+int sre2_server_cancel(sre2_server* s, uint64_t ticket);
+
+/* Block until no request is queued or running, or the timeout passes
+ * (SRE2_EBUSY).  Returns SRE2_EHIP if device work failed. */
+int sre2_server_drain(sre2_server* s, double timeout_s);
+
+/* Counters SRE2_SERVER_STAT_* (host array of `count` int64). */
+int sre2_server_stats(sre2_server* s, int64_t* stats, int count);
+
+/* Stop admitting, finish queued and running work, free everything.  NULL is
+ * accepted.  Returns SRE2_EHIP if device work failed. */
+int sre2_server_destroy(sre2_server* s);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,14 @@ def lib():
         "sre2_set_timing": ([vp, c_int], c_int),
         "sre2_timing_read": ([vp, dp, ctypes.POINTER(i64)], c_int),
         "sre2_chunking": ([vp, c_int, c_int, ctypes.POINTER(i64), ctypes.POINTER(c_int)], c_int),
+        "sre2_server_create": ([ctypes.POINTER(vp), c_int, c_int, sz, c_int], c_int),
+        "sre2_server_submit": ([vp, vp, c_int, c_int, c_int, ctypes.POINTER(ctypes.c_uint64)],
+                               c_int),
+        "sre2_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(c_int), dp, dp], c_int),
+        "sre2_server_cancel": ([vp, ctypes.c_uint64], c_int),
+        "sre2_server_drain": ([vp, ctypes.c_double], c_int),
+        "sre2_server_stats": ([vp, ctypes.POINTER(i64), c_int], c_int),
+        "sre2_server_destroy": ([vp], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -256,3 +264,75 @@ def m2_batched(psis, form: str = "fp32", ctx: Context | None = None, stream=None
     _check(rc, "sre2_m2_batched")
     o = out.cpu().reshape(cnt, OUT_LEN)
     return [_result(o[i]) for i in range(cnt)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
+SERVER_STATS = ("submitted", "admitted", "completed", "cancelled", "packs", "packed_states",
+                "singles", "peak_bytes", "peak_inflight")
+
+
+class Server:
+    """Continuous-batching serving loop (sre2_server_* in include/sre2.h)."""
+
+    def __init__(self, device: int = 0, form: str = "fp32", hbm_budget: int = 8 << 30,
+                 max_slots: int = 4096):
+        self._p = ctypes.c_void_p()
+        _check(lib().sre2_server_create(ctypes.byref(self._p), int(device), FORMS[form],
+                                        int(hbm_budget), int(max_slots)), "sre2_server_create")
+
+    def submit(self, psi) -> int:
+        """Submit a numpy complex64/complex128 state (host memory, copied) or a
+        torch GPU tensor (device memory; keep it alive until done)."""
+        import numpy as np
+        t = ctypes.c_uint64()
+        if isinstance(psi, np.ndarray):
+            a = np.ascontiguousarray(psi)
+            if a.dtype not in (np.complex64, np.complex128):
+                raise TypeError("state must be complex64 or complex128")
+            N = a.size.bit_length() - 1
+            if (1 << N) != a.size:
+                raise ValueError("state length must be 2^N")
+            rc = lib().sre2_server_submit(self._p, ctypes.c_void_p(a.ctypes.data), N,
+                                          C64 if a.dtype == np.complex64 else C128, 0,
+                                          ctypes.byref(t))
+        else:
+            p = _prep(psi)
+            rc = lib().sre2_server_submit(self._p, ctypes.c_void_p(p.data_ptr()), _nqubits(p),
+                                          _dtype_code(p), 1, ctypes.byref(t))
+        _check(rc, "sre2_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(state, Result or None, latency seconds or None); a final state
+        releases the ticket."""
+        st = ctypes.c_int()
+        res = (ctypes.c_double * OUT_LEN)()
+        lat = ctypes.c_double()
+        _check(lib().sre2_server_poll(self._p, ctypes.c_uint64(ticket), ctypes.byref(st), res,
+                                      ctypes.byref(lat)), "sre2_server_poll")
+        if st.value in (REQ_DONE, REQ_CANCELLED, REQ_FAILED):
+            return st.value, Result(m2=res[0], S=res[1], n=res[2], status=int(res[3])), lat.value
+        return st.value, None, None
+
+    def cancel(self, ticket: int):
+        _check(lib().sre2_server_cancel(self._p, ctypes.c_uint64(ticket)), "sre2_server_cancel")
+
+    def drain(self, timeout: float = 600.0):
+        _check(lib().sre2_server_drain(self._p, float(timeout)), "sre2_server_drain")
+
+    def stats(self) -> dict:
+        v = (ctypes.c_int64 * len(SERVER_STATS))()
+        _check(lib().sre2_server_stats(self._p, v, len(SERVER_STATS)), "sre2_server_stats")
+        return dict(zip(SERVER_STATS, list(v)))
+
+    def close(self):
+        if self._p:
+            rc = lib().sre2_server_destroy(self._p)
+            self._p = ctypes.c_void_p()
+            _check(rc, "sre2_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

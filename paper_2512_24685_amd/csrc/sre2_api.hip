@@ -18,31 +18,14 @@
 
 #include "../../include/sre2.h"
 #include "sre2_internal.h"
+#include "sre2_ctx.h"
 
 using namespace sre2;
 
-struct sre2_ctx {
-    int device = 0;
-    size_t scratch_limit = size_t(4) << 30;
-    void* psi_work = nullptr;
-    size_t psi_work_bytes = 0;
-    double* sx = nullptr;  // S_x when the caller passes no partials buffer
-    size_t sx_bytes = 0;
-    void* scratch = nullptr;  // two-pass slab
-    size_t scratch_bytes = 0;
-    double* part = nullptr;  // two-pass column-group partials of one chunk
-    size_t part_bytes = 0;
-    double* red = nullptr;  // norm partials, flags, S partials
-    size_t red_bytes = 0;
-    // optional per-launch timing (sre2_set_timing)
-    bool timing = false;
-    std::vector<hipEvent_t> events;       // pool, reused between reads
-    std::vector<int> pending;             // kind of each recorded (start, stop) pair
-};
+
 
 namespace {
 
-constexpr int kMaxRed = 1024;  // upper bound of reduction blocks
 
 struct DeviceGuard {
     int prev = -1;
@@ -115,9 +98,12 @@ Chunking chunking(int N, int form, bool herm, int64_t x_count, size_t limit) {
     while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << L))
         cs *= 2;
     c.cs = cs;
+    // Column groups per shift depend on (N, form) only - never on the chunk
+    // size - so the order of the FP64 partial sums, and hence every result
+    // bit, is independent of the scratch limit.
     const int64_t tiles = col_tiles(N, form, herm);
     int P = 1;
-    while (cs * P < 2048 && P * 2 <= tiles) P *= 2;
+    while (P < 64 && P * 2 <= tiles) P *= 2;
     c.P = P;
     return c;
 }
@@ -226,17 +212,19 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
         if (split > x0) {
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
-                f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se, st)
-                    : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se, st);
+                f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se,
+                                                  Pack{}, st)
+                    : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se,
+                                                 Pack{}, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         if (x1 > split) {
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
                 f64 ? launch_shift_kernel<double>(work, N, true, false, split, x1 - split,
-                                                  Sx + (split - x0), se, st)
+                                                  Sx + (split - x0), se, Pack{}, st)
                     : launch_shift_kernel<float>(work, N, true, false, split, x1 - split,
-                                                 Sx + (split - x0), se, st);
+                                                 Sx + (split - x0), se, Pack{}, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         return SRE2_OK;
@@ -294,8 +282,10 @@ int red_buffers(sre2_ctx* ctx, Red* r) {
 int norm_stage(sre2_ctx* ctx, const void* work, int N, int form, const Red& r, int nb,
                hipStream_t st) {
     Timed tm(ctx, st, SRE2_KIND_AUX);
-    int rc = hip_status(launch_norm(work, work_dtype(form), int64_t(1) << N, nb, r.npart, r.nflag, st));
-    if (!rc && is_split(form)) rc = hip_status(launch_split_scale(r.npart, nb, r.se, st));
+    int rc = hip_status(launch_norm(work, work_dtype(form), int64_t(1) << N, nb, r.npart, r.nflag,
+                                    Pack{}, st));
+    if (!rc && is_split(form))
+        rc = hip_status(launch_split_scale(r.npart, nb, r.se, Pack{}, st));
     return rc;
 }
 
@@ -321,14 +311,99 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
     if (rc) return rc;
     {
         Timed tm(ctx, st, SRE2_KIND_AUX);
-        rc = hip_status(launch_sum(Sx, n, 1, nb, r.spart, nullptr, st));
+        rc = hip_status(launch_sum(Sx, n, 1, nb, r.spart, nullptr, Pack{}, st));
     }
     if (rc) return rc;
     Timed tm(ctx, st, SRE2_KIND_AUX);
-    return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, st));
+    return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, Pack{}, st));
+}
+
+// Up to kMaxPack states of one N <= fused_max(form) in packed launches: the
+// same kernels, grids and reduction ranges as m2_one, with the grid's y index
+// selecting the state, so every result is bitwise identical to a single call.
+int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, int form,
+            double* const* outs, hipStream_t st) {
+    const int wd = work_dtype(form);
+    const int64_t n = int64_t(1) << N;
+    Pack pk;
+    pk.count = count;
+    pk.N = N;
+    int rc = ensure((void**)&ctx->pack_ws, &ctx->pack_ws_bytes,
+                    (size_t)kMaxPack * pack_ws_doubles(N) * sizeof(double));
+    if (rc) return rc;
+    if (wd != dtype) {
+        rc = ensure(&ctx->pack_work, &ctx->pack_work_bytes, (size_t)kMaxPack * n * elem_bytes(wd));
+        if (rc) return rc;
+    }
+    for (int i = 0; i < count; ++i) {
+        pk.ws[i] = ctx->pack_ws + (size_t)i * pack_ws_doubles(N);
+        pk.out[i] = outs[i];
+        if (wd == dtype) {
+            pk.psi[i] = psi[i];
+        } else {
+            void* dst = (char*)ctx->pack_work + (size_t)i * n * elem_bytes(wd);
+            Timed tm(ctx, st, SRE2_KIND_AUX);
+            if (launch_convert(psi[i], dtype, dst, wd, n, st) != hipSuccess) return SRE2_EHIP;
+            pk.psi[i] = dst;
+        }
+    }
+    const bool f64 = is_f64(form), sp = is_split(form);
+    const bool herm = is_herm(form) && N >= herm_min(form);
+    const int nb = red_blocks(n);
+    {
+        Timed tm(ctx, st, SRE2_KIND_AUX);
+        if (launch_norm(nullptr, wd, n, nb, nullptr, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
+        if (sp && launch_split_scale(nullptr, nb, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
+    }
+    {
+        Timed tm(ctx, st, SRE2_KIND_SHIFT);
+        const int64_t plain_end = herm ? 1 : n;
+        hipError_t e = f64 ? launch_shift_kernel<double>(nullptr, N, false, false, 0, plain_end,
+                                                         nullptr, nullptr, pk, st)
+                           : launch_shift_kernel<float>(nullptr, N, false, sp, 0, plain_end,
+                                                        nullptr, nullptr, pk, st);
+        if (e == hipSuccess && herm)
+            e = f64 ? launch_shift_kernel<double>(nullptr, N, true, false, 1, n - 1, nullptr,
+                                                  nullptr, pk, st)
+                    : launch_shift_kernel<float>(nullptr, N, true, false, 1, n - 1, nullptr,
+                                                 nullptr, pk, st);
+        if (e != hipSuccess) return SRE2_EHIP;
+    }
+    Timed tm(ctx, st, SRE2_KIND_AUX);
+    if (launch_sum(nullptr, n, 1, nb, nullptr, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
+    if (launch_final(nullptr, nb, nullptr, nullptr, nb, N, nullptr, pk, st) != hipSuccess)
+        return SRE2_EHIP;
+    return SRE2_OK;
 }
 
 }  // namespace
+
+namespace sre2 {
+int ctx_m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
+               double* out) {
+    return m2_one(ctx, psi, N, dtype, form, st, out, nullptr);
+}
+int ctx_m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, int form,
+                double* const* outs, hipStream_t st) {
+    return m2_pack(ctx, psi, count, N, dtype, form, outs, st);
+}
+int ctx_fused_max(int form) { return fused_max(form); }
+int ctx_reserve_pack(sre2_ctx* ctx, int N, int form) {
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    int rc = ensure((void**)&ctx->pack_ws, &ctx->pack_ws_bytes,
+                    (size_t)kMaxPack * pack_ws_doubles(N) * sizeof(double));
+    if (!rc)
+        rc = ensure(&ctx->pack_work, &ctx->pack_work_bytes,
+                    (size_t)kMaxPack * (size_t(1) << N) * elem_bytes(work_dtype(form)));
+    return rc;
+}
+int ctx_validate_form(int N, int dtype, int form) {
+    static const char kDummy = 0;
+    sre2_ctx probe;
+    return validate(&probe, &kDummy, N, dtype, form);
+}
+}  // namespace sre2
 
 extern "C" {
 
@@ -362,11 +437,13 @@ int sre2_create(sre2_ctx** out, int hip_device) {
 int sre2_destroy(sre2_ctx* ctx) {
     if (!ctx) return SRE2_OK;
     int rc = SRE2_OK;
-    if (ctx->psi_work || ctx->sx || ctx->scratch || ctx->part || ctx->red) {
+    if (ctx->psi_work || ctx->sx || ctx->scratch || ctx->part || ctx->red || ctx->pack_ws ||
+        ctx->pack_work) {
         DeviceGuard g(ctx->device);
         if (g.err != hipSuccess) rc = SRE2_EHIP;
         (void)hipDeviceSynchronize();
-        void* bufs[] = {ctx->psi_work, ctx->sx, ctx->scratch, ctx->part, ctx->red};
+        void* bufs[] = {ctx->psi_work, ctx->sx,      ctx->scratch,  ctx->part,
+                        ctx->red,      ctx->pack_ws, ctx->pack_work};
         for (void* b : bufs)
             if (b && hipFree(b) != hipSuccess) rc = SRE2_EHIP;
     }
@@ -436,8 +513,28 @@ int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_lis
     }
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return SRE2_EHIP;
+    const hipStream_t st = (hipStream_t)stream;
+    // states of one small N share packed launches; larger N run one by one
+    for (int N = 1; N <= fused_max(form); ++N) {
+        const void* psis[kMaxPack];
+        double* outs[kMaxPack];
+        int k = 0;
+        for (int i = 0; i <= count; ++i) {
+            if (i < count && N_list[i] == N) {
+                psis[k] = psi_list[i];
+                outs[k] = out + (size_t)SRE2_OUT_LEN * i;
+                ++k;
+            }
+            if (k == kMaxPack || (i == count && k > 0)) {
+                const int rc = m2_pack(ctx, psis, k, N, dtype, form, outs, st);
+                if (rc) return rc;
+                k = 0;
+            }
+        }
+    }
     for (int i = 0; i < count; ++i) {
-        const int rc = m2_one(ctx, psi_list[i], N_list[i], dtype, form, (hipStream_t)stream,
+        if (N_list[i] <= fused_max(form)) continue;
+        const int rc = m2_one(ctx, psi_list[i], N_list[i], dtype, form, st,
                               out + (size_t)SRE2_OUT_LEN * i, nullptr);
         if (rc) return rc;
     }

@@ -1,0 +1,46 @@
+// sre2_ctx.h - the library context (workspace owned per device and stream)
+// and the internal entry points the serving loop builds on.  Not public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+struct sre2_ctx {
+    int device = 0;
+    size_t scratch_limit = size_t(4) << 30;
+    void* psi_work = nullptr;
+    size_t psi_work_bytes = 0;
+    double* sx = nullptr;  // S_x when the caller passes no partials buffer
+    size_t sx_bytes = 0;
+    void* scratch = nullptr;  // two-pass slab
+    size_t scratch_bytes = 0;
+    double* part = nullptr;  // two-pass column-group partials of one chunk
+    size_t part_bytes = 0;
+    double* red = nullptr;  // norm partials, flags, S partials
+    size_t red_bytes = 0;
+    double* pack_ws = nullptr;  // packed launches: per-state workspace blocks
+    size_t pack_ws_bytes = 0;
+    void* pack_work = nullptr;  // packed launches: converted inputs
+    size_t pack_work_bytes = 0;
+    // optional per-launch timing (sre2_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;       // pool, reused between reads
+    std::vector<int> pending;             // kind of each recorded (start, stop) pair
+};
+
+namespace sre2 {
+// One full evaluation of one state (sre2_m2 without partials).
+int ctx_m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
+               double* out);
+// Up to kMaxPack states of one N <= ctx_fused_max(form) in packed launches.
+int ctx_m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, int form,
+                double* const* outs, hipStream_t st);
+int ctx_fused_max(int form);
+// Grow the packed-launch workspace for every N up to `N` (so that it never
+// has to be reallocated while packed work is in flight).
+int ctx_reserve_pack(sre2_ctx* ctx, int N, int form);
+// Host-side argument check of (N, dtype, form), as sre2_m2 does it.
+int ctx_validate_form(int N, int dtype, int form);
+}  // namespace sre2

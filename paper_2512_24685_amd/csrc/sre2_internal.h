@@ -8,6 +8,37 @@
 namespace sre2 {
 
 constexpr int kMaxN = 26;
+
+constexpr int kMaxRed = 1024;  // upper bound of reduction blocks per state
+constexpr int kMaxPack = 64;   // states per packed launch
+
+// States of one packed launch: several states of the same N in one grid, the
+// grid's y index selecting the state.  Passed to the kernels by value.  Each
+// state owns a workspace block ws of pack_ws_doubles(N) doubles laid out as
+// S_x (2^N) | norm partials | non-finite flags | S partials (kMaxRed each) |
+// split scale exponent (one int in the last double).
+struct Pack {
+    int count = 0;  // 0: an ordinary single-state launch
+    int N = 0;
+    const void* psi[kMaxPack] = {};
+    double* ws[kMaxPack] = {};
+    double* out[kMaxPack] = {};
+};
+
+__host__ __device__ inline int64_t pack_ws_doubles(int N) {
+    return ((int64_t)1 << N) + 3 * kMaxRed + 1;
+}
+__host__ __device__ inline double* pk_sx(double* ws, int) { return ws; }
+__host__ __device__ inline double* pk_npart(double* ws, int N) { return ws + ((int64_t)1 << N); }
+__host__ __device__ inline double* pk_nflag(double* ws, int N) {
+    return ws + ((int64_t)1 << N) + kMaxRed;
+}
+__host__ __device__ inline double* pk_spart(double* ws, int N) {
+    return ws + ((int64_t)1 << N) + 2 * kMaxRed;
+}
+__host__ __device__ inline int* pk_se(double* ws, int N) {
+    return reinterpret_cast<int*>(ws + ((int64_t)1 << N) + 3 * kMaxRed);
+}
 constexpr int kC64 = 0;
 constexpr int kC128 = 1;
 
@@ -25,9 +56,11 @@ template <typename Real> int64_t pass2_col_tiles(int N, bool herm);
 // S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (plain, N < RB) or
 // fused kernel (N <= fused_max_n).  `split` selects the split-FP16 MFMA
 // transform (FP32 only, not with herm); it reads the scale exponent *se.
+// With pk.count > 0 the launch covers pk.count states of the same N (grid
+// y = state); psi / S / se then come from the pack (S = S_x of state y + x0).
 template <typename Real>
 hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
-                               int64_t xc, double* S, const int* se, hipStream_t st);
+                               int64_t xc, double* S, const int* se, const Pack& pk, hipStream_t st);
 // Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
 // row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
 // pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
@@ -38,16 +71,18 @@ template <typename Real>
 hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
                         double* part, const int* se, hipStream_t st);
 // Scale exponent of the split form from the norm partials.
-hipError_t launch_split_scale(const double* npart, int nb, int* se, hipStream_t st);
+hipError_t launch_split_scale(const double* npart, int nb, int* se, const Pack& pk, hipStream_t st);
 
 hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                           hipStream_t st);
+// The reduction launchers also accept a packed launch (pk.count > 0).
 hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, double* part,
-                       double* flag, hipStream_t st);
+                       double* flag, const Pack& pk, hipStream_t st);
 hipError_t launch_sum(const double* v, int64_t nshift, int P, int nblocks, double* part,
-                      double* Sx, hipStream_t st);
+                      double* Sx, const Pack& pk, hipStream_t st);
 hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, hipStream_t st);
 hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
-                        int nn, int N, double* out, hipStream_t st);
+                        int nn, int N, double* out, const Pack& pk,
+                        hipStream_t st);
 
 }  // namespace sre2

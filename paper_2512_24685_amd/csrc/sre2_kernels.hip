@@ -330,9 +330,14 @@ __device__ __forceinline__ void seg_tree(double* red, int seg) {
 template <typename Real, int N>
 __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restrict__ psi,
                                              int64_t x_begin, int64_t x_count,
-                                             double* __restrict__ S_out) {
+                                             double* __restrict__ S_out,
+                                             const Pack pk) {
     using C = typename CT<Real>::T;
     constexpr int D = 1 << N;
+    if (pk.count) {
+        psi = (const C*)pk.psi[blockIdx.y];
+        S_out = pk_sx(pk.ws[blockIdx.y], N) + x_begin;
+    }
     const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (idx >= x_count) return;
     const uint32_t x = (uint32_t)(x_begin + idx);
@@ -359,7 +364,8 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
-             double* __restrict__ S_out, const int* __restrict__ scale_exp) {
+             double* __restrict__ S_out, const int* __restrict__ scale_exp,
+             const Pack pk) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 1000 + NT;
@@ -370,6 +376,11 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     constexpr uint32_t KMASK = (1u << NT) - 1u;
     __shared__ C lds[1 << TB];
     double* red = reinterpret_cast<double*>(lds);
+    if (pk.count) {
+        psi = (const C*)pk.psi[blockIdx.y];
+        S_out = pk_sx(pk.ws[blockIdx.y], pk.N) + x_begin;
+        scale_exp = pk_se(pk.ws[blockIdx.y], pk.N);
+    }
 
     const int se = SPLIT ? *scale_exp : 0;
     const Real sc = SPLIT ? ldexpf(1.0f, se) : Real(1);
@@ -536,14 +547,21 @@ __global__ void k_convert(const Src* __restrict__ in, Dst* __restrict__ out, int
 }
 
 constexpr int kRedThreads = 256;
+static_assert(kRedThreads <= kMaxRed, "reduction blocks");
 
 // part[b] = sum of |psi|^2 over block b's fixed range; flag[b] = non-finite seen.
 template <typename C>
 __global__ __launch_bounds__(kRedThreads) void k_norm_part(const C* __restrict__ psi, int64_t n,
                                                            int64_t per_block,
                                                            double* __restrict__ part,
-                                                           double* __restrict__ flag) {
+                                                           double* __restrict__ flag,
+                                                           const Pack pk) {
     __shared__ double red[kRedThreads];
+    if (pk.count) {
+        psi = (const C*)pk.psi[blockIdx.y];
+        part = pk_npart(pk.ws[blockIdx.y], pk.N);
+        flag = pk_nflag(pk.ws[blockIdx.y], pk.N);
+    }
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = lo + per_block < n ? lo + per_block : n;
     double s = 0.0;
@@ -572,8 +590,14 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_part(const double* __restri
                                                           int64_t nshift, int P,
                                                           int64_t per_block,
                                                           double* __restrict__ part,
-                                                          double* __restrict__ Sx) {
+                                                          double* __restrict__ Sx,
+                                                          const Pack pk) {
     __shared__ double red[kRedThreads];
+    if (pk.count) {
+        v = pk_sx(pk.ws[blockIdx.y], pk.N);
+        part = pk_spart(pk.ws[blockIdx.y], pk.N);
+        Sx = nullptr;
+    }
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = lo + per_block < nshift ? lo + per_block : nshift;
     double s = 0.0;
@@ -602,8 +626,15 @@ __global__ __launch_bounds__(256) void k_group_sum(const double* __restrict__ pa
 __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ spart, int ns,
                                                        const double* __restrict__ npart,
                                                        const double* __restrict__ nflag, int nn,
-                                                       int N, double* __restrict__ out) {
+                                                       int N, double* __restrict__ out,
+                                                       const Pack pk) {
     __shared__ double red[kRedThreads];
+    if (pk.count) {
+        spart = pk_spart(pk.ws[blockIdx.y], pk.N);
+        npart = pk_npart(pk.ws[blockIdx.y], pk.N);
+        nflag = pk_nflag(pk.ws[blockIdx.y], pk.N);
+        out = pk.out[blockIdx.y];
+    }
     double a = 0.0, b = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < ns; i += kRedThreads) a += spart[i];
     for (int i = threadIdx.x; i < nn; i += kRedThreads) {
@@ -637,24 +668,25 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
 namespace {
 
 template <typename Real, int N>
-hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st) {
+hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S,
+                         const Pack& pk, hipStream_t st) {
     using C = typename CT<Real>::T;
     const int64_t blocks = (xc + 63) / 64;
-    hipLaunchKernelGGL((k_tiny<Real, N>), dim3((unsigned)blocks), dim3(64), 0, st,
-                       (const C*)psi, x0, xc, S);
+    hipLaunchKernelGGL((k_tiny<Real, N>), dim3((unsigned)blocks, (unsigned)(pk.count ? pk.count : 1)), dim3(64), 0, st,
+                       (const C*)psi, x0, xc, S, pk);
     return hipGetLastError();
 }
 
 template <typename Real, int NT, bool HERM, bool SPLIT>
 hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, const int* se,
-                           hipStream_t st) {
+                           const Pack& pk, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = fused_tb<Real>(NT), RB = Tune<Real>::RBF;
     constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT>), dim3((unsigned)grid),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se);
+    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT>), dim3((unsigned)grid, (unsigned)(pk.count ? pk.count : 1)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se, pk);
     return hipGetLastError();
 }
 
@@ -669,20 +701,24 @@ hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* p
 }
 
 template <typename Real, int... Ns>
-hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double* S, hipStream_t st,
+hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double* S,
+                         const Pack& pk, hipStream_t st,
                          std::integer_sequence<int, Ns...>) {
     hipError_t e = hipErrorInvalidValue;
-    ((N == Ns + 1 ? (e = launch_tiny_n<Real, Ns + 1>(psi, x0, xc, S, st), 0) : 0), ...);
+    ((N == Ns + 1 ? (e = launch_tiny_n<Real, Ns + 1>(psi, x0, xc, S, pk, st), 0) : 0),
+     ...);
     return e;
 }
 
 template <typename Real, bool HERM, bool SPLIT, int... Ns>
 hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, double* S,
-                          const int* se, hipStream_t st, std::integer_sequence<int, Ns...>) {
+                          const int* se, const Pack& pk, hipStream_t st,
+                          std::integer_sequence<int, Ns...>) {
     constexpr int RB = Tune<Real>::RBF;
     hipError_t e = hipErrorInvalidValue;
-    ((NT == Ns + RB ? (e = launch_fused_nt<Real, Ns + RB, HERM, SPLIT>(psi, x0, xc, S, se, st), 0)
-                    : 0),
+    ((NT == Ns + RB
+          ? (e = launch_fused_nt<Real, Ns + RB, HERM, SPLIT>(psi, x0, xc, S, se, pk, st), 0)
+          : 0),
      ...);
     return e;
 }
@@ -743,22 +779,24 @@ template int64_t pass2_col_tiles<double>(int, bool);
 
 template <typename Real>
 hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
-                               int64_t xc, double* S, const int* se, hipStream_t st) {
+                               int64_t xc, double* S, const int* se, const Pack& pk, hipStream_t st) {
     constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
-    if (N > FMAX || (split && (herm || sizeof(Real) != 4))) return hipErrorInvalidValue;
+    if (N > FMAX || (split && (herm || sizeof(Real) != 4)) || pk.count > kMaxPack)
+        return hipErrorInvalidValue;
     if (herm) {
         if (x0 < 1 || N - 1 < RB) return hipErrorInvalidValue;
-        return dispatch_fused<Real, true, false>(N - 1, psi, x0, xc, S, se, st,
+        return dispatch_fused<Real, true, false>(N - 1, psi, x0, xc, S, se, pk, st,
                                                  std::make_integer_sequence<int, FMAX - RB>{});
     }
     if (N < RB)
-        return dispatch_tiny<Real>(N, psi, x0, xc, S, st, std::make_integer_sequence<int, RB - 1>{});
+        return dispatch_tiny<Real>(N, psi, x0, xc, S, pk, st,
+                                   std::make_integer_sequence<int, RB - 1>{});
     if constexpr (sizeof(Real) == 4) {
         if (split)
-            return dispatch_fused<Real, false, true>(N, psi, x0, xc, S, se, st,
+            return dispatch_fused<Real, false, true>(N, psi, x0, xc, S, se, pk, st,
                                                      std::make_integer_sequence<int, FMAX - RB + 1>{});
     }
-    return dispatch_fused<Real, false, false>(N, psi, x0, xc, S, se, st,
+    return dispatch_fused<Real, false, false>(N, psi, x0, xc, S, se, pk, st,
                                               std::make_integer_sequence<int, FMAX - RB + 1>{});
 }
 
@@ -807,9 +845,11 @@ hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int c
 }
 
 template hipError_t launch_shift_kernel<float>(const void*, int, bool, bool, int64_t, int64_t,
-                                               double*, const int*, hipStream_t);
+                                               double*, const int*, const Pack&,
+                                               hipStream_t);
 template hipError_t launch_shift_kernel<double>(const void*, int, bool, bool, int64_t, int64_t,
-                                                double*, const int*, hipStream_t);
+                                                double*, const int*, const Pack&,
+                                                hipStream_t);
 template hipError_t launch_pass1<float>(const void*, int, bool, bool, int64_t, int, void*,
                                         const int*, hipStream_t);
 template hipError_t launch_pass1<double>(const void*, int, bool, bool, int64_t, int, void*,
@@ -822,8 +862,13 @@ template hipError_t launch_pass2<double>(const void*, int, bool, bool, int, int,
 // s = 14 - ceil(log2 n) from the norm partials (0 when n is not positive and
 // finite): with every |value| of a transform bounded by n, the scaled values
 // of the split form stay below 2^14, inside FP16's range.
-__global__ void k_split_scale(const double* __restrict__ npart, int nb, int* __restrict__ se) {
+__global__ void k_split_scale(const double* __restrict__ npart, int nb, int* __restrict__ se,
+                              const Pack pk) {
     if (threadIdx.x != 0) return;
+    if (pk.count) {
+        npart = pk_npart(pk.ws[blockIdx.y], pk.N);
+        se = pk_se(pk.ws[blockIdx.y], pk.N);
+    }
     double n = 0.0;
     for (int i = 0; i < nb; ++i) n += npart[i];
     int s = 0;
@@ -834,8 +879,9 @@ __global__ void k_split_scale(const double* __restrict__ npart, int nb, int* __r
     *se = s;
 }
 
-hipError_t launch_split_scale(const double* npart, int nb, int* se, hipStream_t st) {
-    hipLaunchKernelGGL(k_split_scale, dim3(1), dim3(64), 0, st, npart, nb, se);
+hipError_t launch_split_scale(const double* npart, int nb, int* se, const Pack& pk, hipStream_t st) {
+    hipLaunchKernelGGL(k_split_scale, dim3(1, (unsigned)(pk.count ? pk.count : 1)), dim3(64), 0, st, npart, nb, se,
+                       pk);
     return hipGetLastError();
 }
 
@@ -854,22 +900,23 @@ hipError_t launch_convert(const void* in, int in_dtype, void* out, int out_dtype
 }
 
 hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, double* part,
-                       double* flag, hipStream_t st) {
+                       double* flag, const Pack& pk, hipStream_t st) {
     const int64_t per = (n + nblocks - 1) / nblocks;
+    const dim3 grid(nblocks, pk.count ? pk.count : 1);
     if (dtype == kC64)
-        hipLaunchKernelGGL((k_norm_part<float2>), dim3(nblocks), dim3(kRedThreads), 0, st,
-                           (const float2*)psi, n, per, part, flag);
+        hipLaunchKernelGGL((k_norm_part<float2>), grid, dim3(kRedThreads), 0, st,
+                           (const float2*)psi, n, per, part, flag, pk);
     else
-        hipLaunchKernelGGL((k_norm_part<double2>), dim3(nblocks), dim3(kRedThreads), 0, st,
-                           (const double2*)psi, n, per, part, flag);
+        hipLaunchKernelGGL((k_norm_part<double2>), grid, dim3(kRedThreads), 0, st,
+                           (const double2*)psi, n, per, part, flag, pk);
     return hipGetLastError();
 }
 
 hipError_t launch_sum(const double* v, int64_t nshift, int P, int nblocks, double* part,
-                      double* Sx, hipStream_t st) {
+                      double* Sx, const Pack& pk, hipStream_t st) {
     const int64_t per = (nshift + nblocks - 1) / nblocks;
-    hipLaunchKernelGGL(k_sum_part, dim3(nblocks), dim3(kRedThreads), 0, st, v, nshift, P, per,
-                       part, Sx);
+    hipLaunchKernelGGL(k_sum_part, dim3(nblocks, pk.count ? pk.count : 1), dim3(kRedThreads), 0, st, v, nshift, P,
+                       per, part, Sx, pk);
     return hipGetLastError();
 }
 
@@ -880,9 +927,10 @@ hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, h
 }
 
 hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
-                        int nn, int N, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, spart, ns, npart, nflag, nn, N,
-                       out);
+                        int nn, int N, double* out, const Pack& pk,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_final, dim3(1, pk.count ? pk.count : 1), dim3(kRedThreads), 0, st, spart, ns, npart, nflag,
+                       nn, N, out, pk);
     return hipGetLastError();
 }
 

@@ -96,3 +96,20 @@ def test_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         sre2.m2(torch.zeros(16, dtype=torch.complex64))
+
+
+def test_server_argument_validation(L):
+    p = ctypes.c_void_p()
+    assert L.sre2_server_create(None, 0, 0, 1 << 30, 8) == sre2.EINVAL
+    assert L.sre2_server_create(ctypes.byref(p), -1, 0, 1 << 30, 8) == sre2.EINVAL
+    assert L.sre2_server_create(ctypes.byref(p), 0, 0, 1 << 30, 0) == sre2.EINVAL
+    assert L.sre2_server_create(ctypes.byref(p), 0, 0, 1024, 8) == sre2.EINVAL
+    assert L.sre2_server_create(ctypes.byref(p), 0, 99, 1 << 30, 8) == sre2.EFORM
+    t = ctypes.c_uint64()
+    st = ctypes.c_int()
+    assert L.sre2_server_submit(None, FAKE, 8, 0, 0, ctypes.byref(t)) == sre2.EINVAL
+    assert L.sre2_server_poll(None, 1, ctypes.byref(st), None, None) == sre2.EINVAL
+    assert L.sre2_server_cancel(None, 1) == sre2.EINVAL
+    assert L.sre2_server_drain(None, 1.0) == sre2.EINVAL
+    assert L.sre2_server_stats(None, None, 0) == sre2.EINVAL
+    assert L.sre2_server_destroy(None) == sre2.OK

@@ -169,7 +169,7 @@ def test_scratch_limit_does_not_change_result():
     ctx.set_scratch_limit(1 << 20)  # one slab at a time
     b = sre2.m2(psi, ctx=ctx)
     ctx.close()
-    assert abs(a.m2 - b.m2) <= 1e-12
+    assert a.m2 == b.m2 and a.S == b.S  # chunking never changes the summation order
 
 
 def _golden():
