@@ -228,30 +228,45 @@ __device__ __forceinline__ half8 split4(float a, float b, float c, float d) {
 
 // H_16 along the four tile bits of F on a complex FP32 tile held in LDS
 // (swizzled addresses).  Columns: the lowest four tile bits outside F; the
-// other TB - 8 bits enumerate 16 x 16 blocks, shared round-robin by the waves.
+// other TB - 8 bits enumerate 16 x 16 blocks, split evenly between the waves.
 // Every lane reads and rewrites the same four elements of a block.
 template <int TB, int SB, uint32_t F, int NWAVES>
 __device__ __forceinline__ void mfma_h16(float2* lds, const half8 amat) {
     constexpr uint32_t FULL = (1u << TB) - 1u;
     constexpr uint32_t CM = low_bits(FULL & ~F, 4);
     constexpr uint32_t BM = FULL & ~F & ~CM;
+    constexpr int NB = 1 << (TB - 8);               // blocks per tile
+    constexpr int PER = NB / NWAVES;                // blocks per wave
+    constexpr int UB = 1;  // wider unrolling costs occupancy (measured slower)
+    static_assert(NB % NWAVES == 0 && PER % UB == 0, "block split");
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t ecol = pdep((uint32_t)(l & 15), CM);
     uint32_t erow[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) erow[j] = pdep((uint32_t)(4 * (l >> 4) + j), F) | ecol;
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-    for (int b = w; b < (1 << (TB - 8)); b += NWAVES) {
-        const uint32_t eb = pdep((uint32_t)b, BM);
-        float2 x[4];
+    for (int b0 = w * PER; b0 < (w + 1) * PER; b0 += UB) {
+        float2 x[UB][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = lds[swz<SB>(eb | erow[j])];
-        const half8 br = split4(x[0].x, x[1].x, x[2].x, x[3].x);
-        const half8 bi = split4(x[0].y, x[1].y, x[2].y, x[3].y);
-        const floatx4 dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
-        const floatx4 di = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
+        for (int u = 0; u < UB; ++u) {
+            const uint32_t eb = pdep((uint32_t)(b0 + u), BM);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) lds[swz<SB>(eb | erow[j])] = make_float2(dr[j], di[j]);
+            for (int j = 0; j < 4; ++j) x[u][j] = lds[swz<SB>(eb | erow[j])];
+        }
+        floatx4 dr[UB], di[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const half8 br = split4(x[u][0].x, x[u][1].x, x[u][2].x, x[u][3].x);
+            const half8 bi = split4(x[u][0].y, x[u][1].y, x[u][2].y, x[u][3].y);
+            dr[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
+            di[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const uint32_t eb = pdep((uint32_t)(b0 + u), BM);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lds[swz<SB>(eb | erow[j])] = make_float2(dr[u][j], di[u][j]);
+        }
     }
 }
 

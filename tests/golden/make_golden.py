@@ -56,11 +56,11 @@ def cases():
     for i in range(32):
         out.append((f"haar16_cfg2_{i}",
                     (lambda i=i: W.haar(16, s2 * 1000 + i, np.complex64)), "full"))
+    out.append(("haar20_cfg3", lambda: W.haar(20, s3, np.complex64), "full"))
     J = W.snapshot_couplings(20)
     for t in (5, 21):
         out.append((f"ising20_cfg5_t{t}",
                     (lambda t=t: W.ising_snapshot(20, t, J, dtype=np.complex64)), "full"))
-    out.append(("haar20_cfg3", lambda: W.haar(20, s3, np.complex64), "full"))
     return out
 
 
