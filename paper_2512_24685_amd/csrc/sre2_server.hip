@@ -47,22 +47,26 @@ double now_s() {
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
 }
 
-// First-fit allocator over one device allocation (256-byte granules), with
-// coalescing of neighbouring free blocks.
+// First-fit allocator over one device (or pinned host) allocation,
+// 256-byte granules, with coalescing of neighbouring free blocks.
 class Arena {
    public:
-    int init(size_t bytes) {
+    int init(size_t bytes, bool pinned_host = false) {
+        host_ = pinned_host;
         cap_ = bytes & ~size_t(255);
-        if (hipMalloc(&base_, cap_) != hipSuccess) {
+        const hipError_t e = host_ ? hipHostMalloc((void**)&base_, cap_, hipHostMallocDefault)
+                                   : hipMalloc((void**)&base_, cap_);
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             base_ = nullptr;
+            cap_ = 0;
             return SRE2_ENOMEM;
         }
         free_[0] = cap_;
         return SRE2_OK;
     }
     void release() {
-        if (base_) (void)hipFree(base_);
+        if (base_) (void)(host_ ? hipHostFree(base_) : hipFree(base_));
         base_ = nullptr;
     }
     void* alloc(size_t bytes) {
@@ -107,6 +111,7 @@ class Arena {
     size_t peak() const { return peak_; }
 
    private:
+    bool host_ = false;
     char* base_ = nullptr;
     size_t cap_ = 0, in_use_ = 0, peak_ = 0;
     std::map<size_t, size_t> free_;  // offset -> length
@@ -118,6 +123,7 @@ struct Req {
     int N = 0, dtype = 0;
     size_t bytes = 0;
     std::vector<unsigned char> host;  // state copied from host memory at submit
+    void* staged = nullptr;           // ... or into the pinned staging arena
     const void* src_dev = nullptr;    // caller's device state (copied at admission)
     void* d_psi = nullptr;            // arena block
     int slot = -1;
@@ -139,6 +145,7 @@ struct sre2_server {
     int device = 0, form = 0;
     int max_slots = 0;
     Arena arena;
+    Arena staging;  // pinned host copies of host-submitted states
     sre2_ctx* ctx_small = nullptr;
     sre2_ctx* ctx_large = nullptr;
     hipStream_t s_small = nullptr, s_large = nullptr;
@@ -180,6 +187,8 @@ struct sre2_server {
             hipError_t e;
             if (r->src_dev)
                 e = hipMemcpyAsync(r->d_psi, r->src_dev, r->bytes, hipMemcpyDeviceToDevice, st);
+            else if (r->staged)
+                e = hipMemcpyAsync(r->d_psi, r->staged, r->bytes, hipMemcpyHostToDevice, st);
             else
                 e = hipMemcpyAsync(r->d_psi, r->host.data(), r->bytes, hipMemcpyHostToDevice, st);
             if (e != hipSuccess) sticky = SRE2_EHIP;
@@ -251,6 +260,8 @@ struct sre2_server {
                 free_slots.push_back(r->slot);
                 r->host.clear();
                 r->host.shrink_to_fit();
+                if (r->staged) staging.free(r->staged);
+                r->staged = nullptr;
                 stat[SRE2_SERVER_STAT_COMPLETED] += 1;
                 --inflight;
             }
@@ -272,6 +283,8 @@ struct sre2_server {
                 if (r->cancel) {
                     r->state = SRE2_REQ_CANCELLED;
                     r->t_done = now_s();
+                    if (r->staged) staging.free(r->staged);
+                    r->staged = nullptr;
                     queue.pop_front();
                     continue;
                 }
@@ -331,9 +344,12 @@ int sre2_server_create(sre2_server** out, int hip_device, int form, size_t hbm_b
     s->form = form;
     s->max_slots = max_slots;
     int rc = s->arena.init(hbm_budget_bytes);
+    // pinned staging for host inputs (best effort: without it, host inputs
+    // are copied from pageable memory)
+    if (!rc) (void)s->staging.init(std::min(hbm_budget_bytes, size_t(1) << 30), true);
     if (!rc) rc = sre2_create(&s->ctx_small, hip_device);
     if (!rc) rc = sre2_create(&s->ctx_large, hip_device);
-    if (!rc) rc = sre2_set_scratch_limit(s->ctx_large, size_t(512) << 20);
+    if (!rc) rc = sre2_set_scratch_limit(s->ctx_large, size_t(2) << 30);
     if (!rc) rc = ctx_reserve_pack(s->ctx_small, ctx_fused_max(form), form);
     if (!rc && (hipStreamCreateWithFlags(&s->s_small, hipStreamNonBlocking) != hipSuccess ||
                 hipStreamCreateWithFlags(&s->s_large, hipStreamNonBlocking) != hipSuccess))
@@ -361,6 +377,7 @@ int sre2_server_submit(sre2_server* s, const void* psi, int N, int dtype, int ps
     int rc = ctx_validate_form(N, dtype, s->form);
     if (rc) return rc;
     auto r = std::make_shared<Req>();
+    r->t_submit = now_s();  // latency includes the host-side copy
     r->N = N;
     r->dtype = dtype;
     r->bytes = (size_t(1) << N) * (dtype == SRE2_C64 ? 8 : 16);
@@ -379,12 +396,23 @@ int sre2_server_submit(sre2_server* s, const void* psi, int N, int dtype, int ps
             for (size_t i = 0; i < nreal; ++i)
                 if (!(f[i] - f[i] == 0.0)) return SRE2_ENORM;
         }
-        r->host.assign((const unsigned char*)psi, (const unsigned char*)psi + r->bytes);
+    }
+    if (!psi_on_device) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            r->staged = s->staging.capacity() ? s->staging.alloc(r->bytes) : nullptr;
+        }
+        if (r->staged)  // the copy itself runs outside the lock
+            memcpy(r->staged, psi, r->bytes);
+        else
+            r->host.assign((const unsigned char*)psi, (const unsigned char*)psi + r->bytes);
     }
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return SRE2_EBUSY;
+    if (s->stop) {
+        if (r->staged) s->staging.free(r->staged);
+        return SRE2_EBUSY;
+    }
     r->ticket = s->next_ticket++;
-    r->t_submit = now_s();
     s->queue.push_back(r);
     s->live[r->ticket] = r;
     s->stat[SRE2_SERVER_STAT_SUBMITTED] += 1;
@@ -460,6 +488,7 @@ int sre2_server_destroy(sre2_server* s) {
     if (s->d_out) (void)hipFree(s->d_out);
     if (s->h_out) (void)hipHostFree(s->h_out);
     s->arena.release();
+    s->staging.release();
     sre2_destroy(s->ctx_small);
     sre2_destroy(s->ctx_large);
     (void)hipSetDevice(prev);

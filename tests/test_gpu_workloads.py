@@ -1,0 +1,94 @@
+"""GPU checks on the benchmark workloads beyond the N=20 single state.
+
+* N=16 batch: 32 Haar states against stored oracle M2 values (each stored
+  value keeps the SHA-256 of its input bytes) and 8 graph+T states against
+  m log2(4/3), through the packed batched path.
+* N=20 Ising snapshot sequence psi_t = diag(exp(i pi t/64 h)) H^N |0>: M2 = 0
+  at the Clifford angles t = 0, 16, 32, 48; M2(t) = M2(t + 32) = M2(32 - t);
+  stored oracle values at t = 5 and 21 when present.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2512_24685_amd as sre2  # noqa: E402
+
+LOG43 = np.log2(4.0 / 3.0)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sre2.lib()
+
+
+def golden():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def sha(psi):
+    return hashlib.sha256(np.ascontiguousarray(psi).tobytes()).hexdigest()
+
+
+def dev(psi):
+    return torch.from_numpy(np.ascontiguousarray(psi)).to("cuda")
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+def test_n16_batch(form):
+    print("CASE n16-batch", form, flush=True)
+    inputs = W.config_inputs(2)
+    g = golden()
+    res = sre2.m2_batched([dev(p) for _, p, _ in inputs], form=form)
+    checked = 0
+    for i, ((name, psi, closed), r) in enumerate(zip(inputs, res)):
+        assert r.status == 0
+        if closed is not None:
+            tol = 1e-5 if form == "split16" else 1e-6
+            assert abs(r.m2 - closed) <= tol, name
+            checked += 1
+        else:
+            rec = g.get(f"haar16_cfg2_{i}")
+            if rec and rec["sha256"] == sha(psi):
+                assert abs(r.m2 - rec["m2"]) <= 1e-5, name
+                checked += 1
+            else:
+                assert abs(r.m2 - (np.log2(2 ** 16 + 3) - 2)) < 2e-3  # Haar law
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("form", ["fp32h", "fp32"])
+def test_n20_snapshot_sequence(form):
+    print("CASE snapshots", form, flush=True)
+    N = 20
+    J = W.snapshot_couplings(N)
+    h = W.ising_energy(N, J)
+    g = golden()
+    ts = [0, 5, 16, 21, 27, 32, 37, 48, 53]
+    m = {}
+    for t in ts:
+        psi = W.ising_snapshot(N, t, J, dtype=np.complex64, energy=h)
+        r = sre2.m2(dev(psi), form=form)
+        assert r.status == 0
+        m[t] = r.m2
+        rec = g.get(f"ising20_cfg5_t{t}")
+        if rec and rec["sha256"] == sha(psi):
+            assert abs(r.m2 - rec["m2"]) <= 1e-5, t
+    for t in (0, 16, 32, 48):
+        assert abs(m[t]) <= 1e-6, (t, m[t])
+    for a, b in ((5, 37), (5, 27), (21, 53), (27, 37)):
+        assert abs(m[a] - m[b]) <= 1e-5, (a, b, m[a], m[b])
+    assert m[5] > 1.0 and m[21] > 1.0  # non-trivial between Clifford angles
