@@ -125,22 +125,27 @@ __device__ __forceinline__ void butterflies(C (&v)[1 << RB]) {
     }
 }
 
-template <uint32_t LANE, uint32_t WAVE>
+// Tile bits of this thread's elements outside the registers: lane-id bit i
+// goes to tile bit (LPERM >> 5i) & 31, the wave id to the bits of WAVE.
+template <uint32_t LPERM, uint32_t WAVE>
 __device__ __forceinline__ uint32_t thread_base() {
     const uint32_t t = threadIdx.x;
-    return pdep(t & 63u, LANE) | pdep(t >> 6, WAVE);
+    uint32_t b = pdep(t >> 6, WAVE);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b |= ((t >> i) & 1u) << ((LPERM >> (5 * i)) & 31u);
+    return b;
 }
 
-template <int SB, int RB, uint32_t REG, uint32_t LANE, uint32_t WAVE, typename C>
+template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
 __device__ __forceinline__ void lds_put(C* lds, const C (&v)[1 << RB]) {
-    const uint32_t pb = swz<SB>(thread_base<LANE, WAVE>());
+    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>());
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i) lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))] = v[i];
 }
 
-template <int SB, int RB, uint32_t REG, uint32_t LANE, uint32_t WAVE, typename C>
+template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
 __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
-    const uint32_t pb = swz<SB>(thread_base<LANE, WAVE>());
+    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>());
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i) v[i] = lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))];
 }
@@ -149,33 +154,30 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
 //   PK = 1000 + N : whole transform over tile bits [0, N)        (fused)
 //   PK = 2000     : row transform over all TB tile bits          (pass 1)
 //   PK = 3000 + H : column transform over the top H tile bits    (pass 2)
+//   PK + 10000    : the same transform in the split-FP16 form, with H_16
+//                   factors on the matrix cores (pass 1 ends with a round
+//                   whose lanes run over the lowest bits, for the stores)
 template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
     constexpr int SB = Prec<Real>::SB;
+    if (PK >= 10000) {
+        constexpr int K = PK - 10000;
+        if (K >= 3000) return make_split_plan(TB, RB, SB, TB - (K - 3000), TB, 0);
+        if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, 1);
+        return make_split_plan(TB, RB, SB, 0, K - 1000, 2);
+    }
     if (PK >= 3000) return make_plan(TB, RB, SB, TB - (PK - 3000), TB);
     if (PK >= 2000) return make_plan(TB, RB, SB, 0, TB);
     return make_plan(TB, RB, SB, 0, PK - 1000);
 }
 
-// Rounds J .. nrounds-1 of a plan: LDS transpose, then butterflies.
-template <typename Real, int TB, int RB, int PK, int J>
-struct RoundRunner {
-    using C = typename CT<Real>::T;
-    static constexpr Plan P = plan_of<Real, TB, RB, PK>();
-    static constexpr int SB = Prec<Real>::SB;
-    __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB]) {
-        if constexpr (J < P.nrounds) {
-            constexpr Round prev = P.r[J - 1];
-            constexpr Round cur = P.r[J];
-            __syncthreads();  // previous readers of the LDS tile are done
-            lds_put<SB, RB, prev.reg, prev.lane, prev.wave>(lds, v);
-            __syncthreads();
-            lds_get<SB, RB, cur.reg, cur.lane, cur.wave>(lds, v);
-            butterflies<RB, cur.reg, cur.bfly>(v);
-            RoundRunner<Real, TB, RB, PK, J + 1>::run(lds, v);
-        }
-    }
-};
+template <int TB, int RB, int PK>
+__host__ __device__ constexpr bool plan_has_mf() {
+    constexpr Plan P = plan_of<float, TB, RB, PK>();
+    bool any = false;
+    for (int j = 0; j < P.nrounds; ++j) any = any || P.r[j].mf != 0;
+    return any;
+}
 
 // ---------------------------------------------------------------------------
 // Split-FP16 MFMA form.  H_16 = H_2^{(x)4} applied along four tile bits is a
@@ -226,104 +228,67 @@ __device__ __forceinline__ half8 split4(float a, float b, float c, float d) {
     return r;
 }
 
-// H_16 along the four tile bits of F on a complex FP32 tile held in LDS
-// (swizzled addresses).  Columns: the lowest four tile bits outside F; the
-// other TB - 8 bits enumerate 16 x 16 blocks, split evenly between the waves.
-// Every lane reads and rewrites the same four elements of a block.
-template <int TB, int SB, uint32_t F, int NWAVES>
-__device__ __forceinline__ void mfma_h16(float2* lds, const half8 amat) {
-    constexpr uint32_t FULL = (1u << TB) - 1u;
-    constexpr uint32_t CM = low_bits(FULL & ~F, 4);
-    constexpr uint32_t BM = FULL & ~F & ~CM;
-    constexpr int NB = 1 << (TB - 8);               // blocks per tile
-    constexpr int PER = NB / NWAVES;                // blocks per wave
-    constexpr int UB = 1;  // wider unrolling costs occupancy (measured slower)
-    static_assert(NB % NWAVES == 0 && PER % UB == 0, "block split");
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t ecol = pdep((uint32_t)(l & 15), CM);
-    uint32_t erow[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) erow[j] = pdep((uint32_t)(4 * (l >> 4) + j), F) | ecol;
+// One round's H_16 factor in registers.  The factor's tile bits are the
+// register-index bits A, A + 1 (j) and the lane-id bits 4, 5 (g): for every
+// setting q of the other register-index bits, lane 16g + c holds rows 4g + j
+// of column c, which is the B operand layout, and receives rows 4g + r of the
+// product in the same registers.
+template <int RB, int A>
+__device__ __forceinline__ void mf_apply(float2 (&v)[1 << RB], const half8 amat) {
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-    for (int b0 = w * PER; b0 < (w + 1) * PER; b0 += UB) {
-        float2 x[UB][4];
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            const uint32_t eb = pdep((uint32_t)(b0 + u), BM);
+    for (int q = 0; q < (1 << (RB - 2)); ++q) {
+        const int b = (q & ((1 << A) - 1)) | ((q >> A) << (A + 2));
+        constexpr int s = 1 << A;
+        const half8 br = split4(v[b].x, v[b + s].x, v[b + 2 * s].x, v[b + 3 * s].x);
+        const half8 bi = split4(v[b].y, v[b + s].y, v[b + 2 * s].y, v[b + 3 * s].y);
+        const floatx4 dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
+        const floatx4 di = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) x[u][j] = lds[swz<SB>(eb | erow[j])];
-        }
-        floatx4 dr[UB], di[UB];
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            const half8 br = split4(x[u][0].x, x[u][1].x, x[u][2].x, x[u][3].x);
-            const half8 bi = split4(x[u][0].y, x[u][1].y, x[u][2].y, x[u][3].y);
-            dr[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
-            di[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            const uint32_t eb = pdep((uint32_t)(b0 + u), BM);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) lds[swz<SB>(eb | erow[j])] = make_float2(dr[u][j], di[u][j]);
-        }
+        for (int r = 0; r < 4; ++r) v[b + r * s] = make_float2(dr[r], di[r]);
     }
 }
 
-// Successive H_16 factors over the bits of FB, four at a time from the bottom.
-template <int TB, int SB, uint32_t FB, int NWAVES>
-__device__ __forceinline__ void mfma_factors(float2* lds, const half8 amat) {
-    if constexpr (FB != 0) {
-        constexpr uint32_t F = low_bits(FB, 4);
-        mfma_h16<TB, SB, F, NWAVES>(lds, amat);
-        __syncthreads();
-        mfma_factors<TB, SB, FB & ~F, NWAVES>(lds, amat);
+// The arithmetic of round J: butterflies on its FP32 bits, then its H_16
+// factor (split form).
+template <typename Real, int TB, int RB, int PK, int J>
+__device__ __forceinline__ void round_math(typename CT<Real>::T (&v)[1 << RB], const half8 amat) {
+    constexpr Round rd = plan_of<Real, TB, RB, PK>().r[J];
+    butterflies<RB, rd.reg, rd.bfly>(v);
+    if constexpr (rd.mf != 0) {
+        static_assert(sizeof(Real) == 4, "H_16 factors act on FP32 values");
+        mf_apply<RB, mf_reg_index(rd)>(v, amat);
     }
 }
 
-template <int TB, int RB, int PK>
-__host__ __device__ constexpr uint32_t transform_mask() {
-    constexpr Plan P = plan_of<float, TB, RB, PK>();
-    uint32_t m = 0;
-    for (int j = 0; j < P.nrounds; ++j) m |= P.r[j].bfly;
-    return m;
-}
-
-// Bits of the split form done by VALU butterflies in the first round (the
-// transform bit count modulo 4, taken from the top of round 0's registers);
-// the rest go through H_16 factors.
-template <int TB, int RB, int PK>
-__host__ __device__ constexpr uint32_t split_rem_mask() {
-    constexpr Plan P = plan_of<float, TB, RB, PK>();
-    constexpr uint32_t T = transform_mask<TB, RB, PK>();
-    return top_bits(P.r[0].reg & T, popc(T) % 4);
-}
+// Rounds J .. nrounds-1 of a plan: LDS transpose, then the round's arithmetic.
+template <typename Real, int TB, int RB, int PK, int J>
+struct RoundRunner {
+    using C = typename CT<Real>::T;
+    static constexpr Plan P = plan_of<Real, TB, RB, PK>();
+    static constexpr int SB = Prec<Real>::SB;
+    __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB], const half8 amat) {
+        if constexpr (J < P.nrounds) {
+            constexpr Round prev = P.r[J - 1];
+            constexpr Round cur = P.r[J];
+            __syncthreads();  // previous readers of the LDS tile are done
+            lds_put<SB, RB, prev.reg, prev.lperm, prev.wave>(lds, v);
+            __syncthreads();
+            lds_get<SB, RB, cur.reg, cur.lperm, cur.wave>(lds, v);
+            round_math<Real, TB, RB, PK, J>(v, amat);
+            RoundRunner<Real, TB, RB, PK, J + 1>::run(lds, v, amat);
+        }
+    }
+};
 
 // Whole transform from round 0's register layout to the last round's.
-template <typename Real, int TB, int RB, int PK, bool SPLIT>
+template <typename Real, int TB, int RB, int PK>
 __device__ __forceinline__ void run_transform(typename CT<Real>::T* lds,
                                               typename CT<Real>::T (&v)[1 << RB]) {
-    constexpr Plan P = plan_of<Real, TB, RB, PK>();
-    constexpr Round r0 = P.r[0];
-    if constexpr (!SPLIT) {
-        butterflies<RB, r0.reg, r0.bfly>(v);
-        RoundRunner<Real, TB, RB, PK, 1>::run(lds, v);
-    } else {
-        static_assert(sizeof(Real) == 4, "the split form works on FP32 values");
-        constexpr int SB = Prec<Real>::SB;
-        constexpr Round rl = P.r[P.nrounds - 1];
-        constexpr uint32_t REM = split_rem_mask<TB, RB, PK>();
-        constexpr uint32_t FB = transform_mask<TB, RB, PK>() & ~REM;
-        butterflies<RB, r0.reg, REM>(v);
-        if constexpr (FB != 0) {
-            const half8 amat = h16_operand();
-            __syncthreads();
-            lds_put<SB, RB, r0.reg, r0.lane, r0.wave>(lds, v);
-            __syncthreads();
-            mfma_factors<TB, SB, FB, (1 << (TB - RB)) / 64>(lds, amat);
-            lds_get<SB, RB, rl.reg, rl.lane, rl.wave>(lds, v);
-        }
-    }
+    half8 amat = {};
+    if constexpr (PK >= 10000) amat = h16_operand();
+    round_math<Real, TB, RB, PK, 0>(v, amat);
+    RoundRunner<Real, TB, RB, PK, 1>::run(lds, v, amat);
 }
 
 // Fixed-shape tree over T doubles in LDS; segments of `seg` consecutive entries
@@ -383,7 +348,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
              const Pack pk) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 1000 + NT;
+    constexpr int PK = 1000 + NT + (SPLIT ? 10000 : 0);
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
@@ -405,7 +370,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
         const int64_t x0 = x_begin + tile * SPT;  // first shift of the tile
         C v[1 << RB];
         {
-            const uint32_t base = thread_base<r0.lane, r0.wave>();
+            const uint32_t base = thread_base<r0.lperm, r0.wave>();
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) {
                 const uint32_t e = base | pdep((uint32_t)i, r0.reg);
@@ -425,7 +390,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
                 }
             }
         }
-        run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
+        run_transform<Real, TB, RB, PK>(lds, v);
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) s += HERM ? abs4h(v[i]) : abs4(v[i]);
@@ -433,7 +398,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
         if constexpr (SPLIT) s *= unscale;
         // thread order index: tile bits outside the last round's registers,
         // compressed; its top TB-NT bits are the shift slot.
-        const uint32_t q = pext(thread_base<rl.lane, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
+        const uint32_t q = pext(thread_base<rl.lperm, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
         __syncthreads();
         red[q] = s;
         seg_tree<T>(red, T / SPT);
@@ -456,7 +421,7 @@ __global__ __launch_bounds__(1 << (TB - RB))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
-    constexpr int PK = 2000;
+    constexpr int PK = 2000 + (SPLIT ? 10000 : 0);
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
@@ -475,7 +440,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     const C* __restrict__ pb = psi + prow;
     C v[1 << RB];
     {
-        const uint32_t base = thread_base<r0.lane, r0.wave>();
+        const uint32_t base = thread_base<r0.lperm, r0.wave>();
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t e = base | pdep((uint32_t)i, r0.reg);
@@ -490,9 +455,9 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
             }
         }
     }
-    run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
+    run_transform<Real, TB, RB, PK>(lds, v);
     C* __restrict__ out = scratch + ((uint64_t)s << NS) + ((uint64_t)srow << TB);
-    const uint32_t base = thread_base<rl.lane, rl.wave>();
+    const uint32_t base = thread_base<rl.lperm, rl.wave>();
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i) slab_store(out + (base | pdep((uint32_t)i, rl.reg)), v[i]);
 }
@@ -509,14 +474,12 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 3000 + HT;
+    constexpr int PK = 3000 + HT + (SPLIT ? 10000 : 0);
     constexpr Plan PL = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = PL.r[0];
     constexpr int CB = TB - HT;  // column bits per tile
     constexpr uint32_t CMASK = (1u << CB) - 1u;
-    constexpr bool NEED_LDS =
-        PL.nrounds > 1 || (SPLIT && (transform_mask<TB, RB, PK>() & ~split_rem_mask<TB, RB, PK>()));
-    __shared__ C lds[NEED_LDS ? (1 << TB) : 1];
+    __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
     __shared__ double red[T];
 
     const int64_t b = blockIdx.x;
@@ -530,13 +493,13 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     for (int ct = g * per; ct < (g + 1) * per; ++ct) {
         const C* __restrict__ src = slab + ((uint64_t)ct << CB);
         C v[1 << RB];
-        const uint32_t base = thread_base<r0.lane, r0.wave>();
+        const uint32_t base = thread_base<r0.lperm, r0.wave>();
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t e = base | pdep((uint32_t)i, r0.reg);
             v[i] = slab_load(src + ((uint64_t)(e >> CB) << L) + (e & CMASK));
         }
-        run_transform<Real, TB, RB, PK, SPLIT>(lds, v);
+        run_transform<Real, TB, RB, PK>(lds, v);
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
     }

@@ -20,11 +20,37 @@
 namespace sre2 {
 
 struct Round {
-    uint32_t reg;   // tile bits held in registers (RB bits)
-    uint32_t bfly;  // register bits that receive butterflies in this round
-    uint32_t lane;  // tile bits indexed by the lane id (6 bits)
-    uint32_t wave;  // tile bits indexed by the wave id
+    uint32_t reg;    // tile bits held in registers (RB bits)
+    uint32_t bfly;   // register bits that receive butterflies in this round
+    uint32_t lane;   // tile bits indexed by the lane id (6 bits)
+    uint32_t wave;   // tile bits indexed by the wave id
+    uint32_t lperm;  // tile bit of lane-id bit i, 5 bits each (i = 0..5)
+    uint32_t mf;     // split form: the four tile bits of this round's H_16
+                     // factor (two neighbouring register-index bits and
+                     // lane-id bits 4, 5)
 };
+
+// Register-index bit of the lower of a factor's two register bits.
+__host__ __device__ constexpr int mf_reg_index(const Round& rd) {
+    uint32_t below = 0;
+    for (int b = 0; b < 32; ++b)
+        if (((rd.mf & rd.reg) >> b) & 1u) {
+            below = rd.reg & ((1u << b) - 1u);
+            break;
+        }
+    int n = 0;
+    for (int b = 0; b < 32; ++b) n += (below >> b) & 1u;
+    return n;
+}
+
+// Lane permutation packing: lane-id bit i -> tile bit (lperm >> 5i) & 31.
+__host__ __device__ constexpr uint32_t lperm_of_mask(uint32_t lane) {
+    uint32_t p = 0;
+    int i = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((lane >> b) & 1u) p |= (uint32_t)b << (5 * i++);
+    return p;
+}
 
 constexpr int kMaxRounds = 8;
 
@@ -104,27 +130,24 @@ __host__ __device__ constexpr Round make_round(int tb, int sb, uint32_t reg, uin
     rd.reg = reg;
     rd.bfly = bfly;
     uint32_t free_bits = bits_range(0, tb) & ~reg;
-    uint32_t lane = 0;
-    int nl = 0;
+    uint32_t matched = 0;
     for (int i = 0; i < sb && i < 6; ++i) {  // residue-matched lanes
         for (int b = 0; b < tb; ++b) {
             if (((free_bits >> b) & 1u) && (b % sb) == i) {
-                lane |= 1u << b;
+                matched |= 1u << b;
                 free_bits &= ~(1u << b);
-                ++nl;
                 break;
             }
         }
     }
-    while (nl < 6) {  // fill with the lowest remaining bits
-        uint32_t b = low_bits(free_bits, 1);
-        if (!b) break;
-        lane |= b;
-        free_bits &= ~b;
-        ++nl;
-    }
-    rd.lane = lane;
-    rd.wave = free_bits;
+    // the matched bits take the low lane-id bits (ascending), the lowest
+    // remaining bits fill the rest
+    const uint32_t fill = low_bits(free_bits, 6 - popc(matched));
+    const int nm = popc(matched);
+    rd.lane = matched | fill;
+    rd.wave = free_bits & ~fill;
+    rd.lperm = lperm_of_mask(matched) | (lperm_of_mask(fill) << (5 * nm));
+    rd.mf = 0;
     return rd;
 }
 
@@ -178,6 +201,209 @@ __host__ __device__ constexpr Plan make_plan(int tb, int rb, int sb, int lo, int
         todo &= ~b;
         done |= b;
     }
+    p.nrounds = k;
+    return p;
+}
+
+__host__ __device__ constexpr int high_bit(uint32_t m) {
+    int h = -1;
+    for (int b = 0; b < 32; ++b)
+        if ((m >> b) & 1u) h = b;
+    return h;
+}
+
+// Pads `reg` up to RB bits with bits of `pool`, from the top, taking only
+// bits whose removal leaves a non-register bit of every bank residue mod SB.
+__host__ __device__ constexpr uint32_t pad_keeping_residues(uint32_t reg, uint32_t pool, int rb,
+                                                           int tb, int sb) {
+    for (int b = tb - 1; b >= 0 && popc(reg) < rb; --b) {
+        if (!((pool >> b) & 1u) || ((reg >> b) & 1u)) continue;
+        const uint32_t rest = bits_range(0, tb) & ~reg & ~(1u << b);
+        bool covers = true;
+        for (int r = 0; r < sb; ++r) {
+            bool any = false;
+            for (int c = r; c < tb; c += sb) any = any || ((rest >> c) & 1u);
+            covers = covers && any;
+        }
+        if (covers) reg |= 1u << b;
+    }
+    return reg;
+}
+
+// Round with an H_16 factor on the matrix cores.  MF = {two bits MREG held
+// in registers at neighbouring register-index bits, and two bits on lane-id
+// bits 4 (L4) and 5}; V = register bits butterflied in FP32.  The other
+// RB - 2 - |V| register bits are padding (done bits first, never between the
+// factor's register bits); lane-id bits 0..3 (the MFMA's 16 columns) take the
+// lowest free bits in the first round (coalesced loads), else bits whose bank
+// slots are distinct from each other's and from L4's.
+__host__ __device__ constexpr Round make_mf_round_as(int tb, int rb, int sb, uint32_t mf,
+                                                     uint32_t mreg, int l4, uint32_t v,
+                                                     uint32_t pad_pool, bool first) {
+    Round rd{};
+    const uint32_t mlane = mf & ~mreg;
+    const int l5 = high_bit(mlane & ~(1u << l4));
+    const int m0 = high_bit(low_bits(mreg, 1)), m1 = high_bit(mreg);
+    const uint32_t between = bits_range(m0 + 1, m1);
+    const uint32_t avail = bits_range(0, tb) & ~mreg & ~v & ~mlane & ~between;
+    uint32_t reg = pad_keeping_residues(mreg | v, avail & pad_pool, rb, tb, sb);
+    reg = pad_keeping_residues(reg, avail, rb, tb, sb);
+    reg |= top_bits(avail & ~reg, rb - popc(reg));
+    rd.reg = reg;
+    rd.bfly = v;
+    rd.mf = mf;
+    uint32_t free_bits = bits_range(0, tb) & ~reg & ~mlane;
+    int cols[4] = {0, 0, 0, 0};
+    int nc = 0;
+    if (first) {
+        for (int b = 0; b < tb && nc < 4; ++b)
+            if ((free_bits >> b) & 1u) cols[nc++] = b;
+    } else {
+        uint32_t used_res = 1u << (l4 % sb);
+        for (int b = 0; b < tb && nc < 4; ++b)
+            if (((free_bits >> b) & 1u) && !((used_res >> (b % sb)) & 1u)) {
+                cols[nc++] = b;
+                used_res |= 1u << (b % sb);
+            }
+        for (int b = 0; b < tb && nc < 4; ++b) {
+            bool taken = false;
+            for (int j = 0; j < nc; ++j) taken = taken || cols[j] == b;
+            if (((free_bits >> b) & 1u) && !taken) cols[nc++] = b;
+        }
+    }
+    uint32_t lane = mlane;
+    uint32_t lp = 0;
+    for (int j = 0; j < 4; ++j) {
+        lane |= 1u << cols[j];
+        lp |= (uint32_t)cols[j] << (5 * j);
+    }
+    lp |= (uint32_t)l4 << 20;
+    lp |= (uint32_t)l5 << 25;
+    rd.lane = lane;
+    rd.lperm = lp;
+    rd.wave = bits_range(0, tb) & ~reg & ~lane;
+    return rd;
+}
+
+// True when lane-id bits 0..4 of a round have distinct bank-slot residues.
+__host__ __device__ constexpr bool lanes_conflict_free(const Round& rd, int sb) {
+    uint32_t used = 0;
+    for (int i = 0; i < 5; ++i) {
+        const uint32_t r = 1u << (((rd.lperm >> (5 * i)) & 31u) % sb);
+        if (used & r) return false;
+        used |= r;
+    }
+    return true;
+}
+
+// The factor's register bits are its two lowest bits and L4 the lower of
+// the other two, unless another of the twelve assignments is free of bank
+// conflicts where that one is not: in the first round with the lowest-bit
+// columns if one allows it, else (every round) with columns chosen by bank
+// slot.
+__host__ __device__ constexpr Round make_mf_round(int tb, int rb, int sb, uint32_t mf, uint32_t v,
+                                                  uint32_t pad_pool, bool first) {
+    const uint32_t mreg0 = low_bits(mf, 2);
+    const int l40 = high_bit(low_bits(mf & ~mreg0, 1));
+    const Round dflt = make_mf_round_as(tb, rb, sb, mf, mreg0, l40, v, pad_pool, first);
+    if (lanes_conflict_free(dflt, sb)) return dflt;
+    int fb[4] = {0, 0, 0, 0};
+    int n = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((mf >> b) & 1u) fb[n++] = b;
+    for (int pass = first ? 0 : 1; pass < 2; ++pass)
+        for (int a = 0; a < 4; ++a)
+            for (int c = a + 1; c < 4; ++c) {
+                const uint32_t mreg = (1u << fb[a]) | (1u << fb[c]);
+                for (int k = 0; k < 4; ++k) {
+                    if (k == a || k == c) continue;
+                    const Round rd =
+                        make_mf_round_as(tb, rb, sb, mf, mreg, fb[k], v, pad_pool, pass == 0);
+                    if (lanes_conflict_free(rd, sb)) return rd;
+                }
+            }
+    return first ? make_mf_round_as(tb, rb, sb, mf, mreg0, l40, v, pad_pool, false) : dflt;
+}
+
+// A first round whose lane-id bits 0..3 run over the four lowest tile bits
+// outside its registers and factor, with conflict-free bank slots.
+__host__ __device__ constexpr bool first_round_ok(const Round& rd, int tb, int sb) {
+    const uint32_t free_bits = bits_range(0, tb) & ~rd.reg & ~rd.mf;
+    int j = 0;
+    for (int b = 0; b < tb && j < 4; ++b)
+        if ((free_bits >> b) & 1u) {
+            if (((rd.lperm >> (5 * j)) & 31u) != (uint32_t)b) return false;
+            ++j;
+        }
+    return lanes_conflict_free(rd, sb);
+}
+
+// Plan of the split form over tile bits [lo, hi): rounds with an H_16 factor
+// plus up to RB - 2 FP32 butterfly bits while at least four bits remain, then
+// FP32-only rounds.  A round without arithmetic may close the plan: tail = 1
+// puts the lanes on the lowest tile bits (coalesced stores); tail = 2 brings
+// the registers inside [0, hi) when they are not (one shift per thread).
+__host__ __device__ constexpr Plan make_split_plan(int tb, int rb, int sb, int lo, int hi,
+                                                   int tail) {
+    Plan p{};
+    p.tb = tb;
+    p.rb = rb;
+    const uint32_t tmask = bits_range(lo, hi);
+    uint32_t todo = tmask, done = 0;
+    int k = 0;
+    bool first = true;
+    while (todo && k < kMaxRounds - 1) {
+        const int n = popc(todo);
+        if (n >= 4 && rb >= 2) {
+            const int nv = (rb - 2) < (n - 4) ? (rb - 2) : (n - 4);
+            uint32_t mf = 0, v = 0;
+            if (first) {
+                // the top 4 + nv bits, the factor on the lowest four of them,
+                // unless another four (or, failing that, fewer FP32 bits) give
+                // conflict-free lanes on the lowest free bits
+                const uint32_t u0 = top_bits(todo, nv + 4);
+                mf = low_bits(u0, 4);
+                v = u0 & ~mf;
+                bool found = first_round_ok(make_mf_round(tb, rb, sb, mf, v, done, true), tb, sb);
+                for (int w = nv; w >= 0 && !found; --w) {
+                    const uint32_t u = top_bits(todo, w + 4);
+                    int ub[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    int nu = 0;
+                    for (int b = 0; b < 32; ++b)
+                        if ((u >> b) & 1u) ub[nu++] = b;
+                    for (uint32_t sel = 0; sel < (1u << nu) && !found; ++sel) {
+                        if (popc(sel) != 4) continue;
+                        uint32_t m = 0;
+                        for (int i = 0; i < nu; ++i)
+                            if ((sel >> i) & 1u) m |= 1u << ub[i];
+                        if (first_round_ok(make_mf_round(tb, rb, sb, m, u & ~m, done, true), tb, sb)) {
+                            mf = m;
+                            v = u & ~m;
+                            found = true;
+                        }
+                    }
+                }
+            } else {
+                mf = low_bits(todo, 4);
+                v = top_bits(todo & ~mf, nv);
+            }
+            p.r[k++] = make_mf_round(tb, rb, sb, mf, v, done, first);
+            todo &= ~(mf | v);
+            done |= mf | v;
+        } else {
+            // FP32-only round over the remaining bits, padded with done bits
+            // (from the top, keeping a free bit of every bank residue)
+            uint32_t reg = pad_keeping_residues(todo, done, rb, tb, sb);
+            reg |= top_bits(bits_range(0, tb) & ~reg, rb - popc(reg));
+            p.r[k++] = make_round(tb, sb, reg, todo);
+            done |= todo;
+            todo = 0;
+        }
+        first = false;
+    }
+    if (tail == 1) p.r[k++] = make_round(tb, sb, top_bits(bits_range(0, tb), rb), 0);
+    if (tail == 2 && (p.r[k - 1].reg & ~bits_range(0, hi)))
+        p.r[k++] = make_round(tb, sb, top_bits(bits_range(0, hi), rb), 0);
     p.nrounds = k;
     return p;
 }

@@ -43,13 +43,19 @@ int probe_geometry(int precision, int kind, int param, int* tb, int* rb, int* sb
                           : geometry<double>(kind, param, tb, rb, sb);
 }
 
-int probe_plan(int tb, int rb, int sb, int lo, int hi, unsigned* out) {
-    const sre2::Plan p = sre2::make_plan(tb, rb, sb, lo, hi);
+// Rounds of a plan, six words each: reg, bfly, lane, wave, lperm, mf.
+// split = 0: FP32 plan; otherwise the split-FP16 plan with tail split - 1
+// (0 none, 1 store round, 2 registers inside [0, hi) at the end).
+int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, unsigned* out) {
+    const sre2::Plan p = split ? sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1)
+                               : sre2::make_plan(tb, rb, sb, lo, hi);
     for (int j = 0; j < p.nrounds; ++j) {
-        out[4 * j + 0] = p.r[j].reg;
-        out[4 * j + 1] = p.r[j].bfly;
-        out[4 * j + 2] = p.r[j].lane;
-        out[4 * j + 3] = p.r[j].wave;
+        out[6 * j + 0] = p.r[j].reg;
+        out[6 * j + 1] = p.r[j].bfly;
+        out[6 * j + 2] = p.r[j].lane;
+        out[6 * j + 3] = p.r[j].wave;
+        out[6 * j + 4] = p.r[j].lperm;
+        out[6 * j + 5] = p.r[j].mf;
     }
     return p.nrounds;
 }
