@@ -121,17 +121,17 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
 
     N = psi.size.bit_length() - 1
     cores = len(os.sched_getaffinity(0))
-    rng = np.random.default_rng(1)
-    probe = rng.choice(1 << N, size=cores, replace=False)
-    t0 = time.perf_counter()
-    oracle.partials(psi, probe, threads=cores)
-    per_shift = (time.perf_counter() - t0) / len(probe)
-    count = int(max(cores, min(1 << N, target_s / max(per_shift, 1e-9))))
-    count = max(cores, (count // cores) * cores)
-    xs = rng.choice(1 << N, size=count, replace=False)
-    t0 = time.perf_counter()
-    oracle.partials(psi, xs, threads=cores)
-    dt = time.perf_counter() - t0
+    order = np.random.default_rng(1).permutation(1 << N)
+    oracle.partials(psi, order[:cores], threads=cores)  # warm-up, not timed
+    batch = 4 * cores
+    count, dt, pos = 0, 0.0, cores
+    while dt < target_s and pos < (1 << N):
+        xs = order[pos:pos + batch]
+        t0 = time.perf_counter()
+        oracle.partials(psi, xs, threads=cores)
+        dt += time.perf_counter() - t0
+        count += len(xs)
+        pos += len(xs)
     return {"value": count * float(1 << N) / dt, "unit": "Pauli strings/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{count} random shifts x of the N={N} state, each a full FP64 FWHT over "
@@ -197,7 +197,7 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
         t_n[N] = best
     mean_service = float(np.mean([t_n[r["N"]] for r in reqs]))
     lam = load / mean_service
-    arrivals = np.cumsum(np.random.default_rng(W.config_seed(4) + 1).exponential(1 / lam, count))
+    arrivals = np.cumsum(np.random.default_rng(W.SEED_SERVING + 1).exponential(1 / lam, count))
     work = float(sum(4.0 ** r["N"] for r in reqs))
 
     def wait_until(t):
@@ -307,7 +307,7 @@ def main():
 
     N = args.N
     log(f"bench: N={N} form={args.form} also={args.also} steps={args.steps} warmup={args.warmup}")
-    psi = W.haar(N, W.config_seed(3), np.complex64)
+    psi = W.haar(N, W.SEED_N20, np.complex64)
     d_psi = torch.from_numpy(psi).to("cuda:0")
     if args.profile_chunks:
         ctx = sre2.Context(0)

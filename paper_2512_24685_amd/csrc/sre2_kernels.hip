@@ -59,6 +59,31 @@ __device__ __forceinline__ double abs4h(C w) {
     return a * a + b * b;
 }
 
+#ifndef SRE2_SPLIT_P1_TAIL
+#define SRE2_SPLIT_P1_TAIL 1  // split-form pass 1 ends in a store-layout round
+#endif
+// Minimum waves per SIMD asked of the compiler (register budget 512 / waves).
+// The split-form kernels keep their MFMA results in VGPRs at 3 (with fewer,
+// the compiler moves them through AGPRs, which costs pass 1 about half its
+// speed); LDS limits every TB = 12 kernel to 2.5 waves per SIMD anyway.
+#ifndef SRE2_P1_WAVES
+#define SRE2_P1_WAVES 1
+#endif
+#ifndef SRE2_P1S_WAVES
+#define SRE2_P1S_WAVES 3  // split form
+#endif
+#ifndef SRE2_P2_WAVES
+#define SRE2_P2_WAVES 1
+#endif
+#ifndef SRE2_P2S_WAVES
+#define SRE2_P2S_WAVES 3
+#endif
+#ifndef SRE2_FUSED_WAVES
+#define SRE2_FUSED_WAVES 1
+#endif
+#ifndef SRE2_FUSEDS_WAVES
+#define SRE2_FUSEDS_WAVES 2
+#endif
 // Slab traffic: streamed through the caches (no reuse until the other pass).
 #ifndef SRE2_NT_SLAB
 #define SRE2_NT_SLAB 1
@@ -163,7 +188,7 @@ __host__ __device__ constexpr Plan plan_of() {
     if (PK >= 10000) {
         constexpr int K = PK - 10000;
         if (K >= 3000) return make_split_plan(TB, RB, SB, TB - (K - 3000), TB, 0);
-        if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, 1);
+        if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, SRE2_SPLIT_P1_TAIL);
         return make_split_plan(TB, RB, SB, 0, K - 1000, 2);
     }
     if (PK >= 3000) return make_plan(TB, RB, SB, TB - (PK - 3000), TB);
@@ -343,6 +368,7 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 // ---------------------------------------------------------------------------
 template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
+__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES : SRE2_FUSED_WAVES)))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out, const int* __restrict__ scale_exp,
              const Pack pk) {
@@ -418,6 +444,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // ---------------------------------------------------------------------------
 template <typename Real, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
+__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P1S_WAVES : SRE2_P1_WAVES)))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
@@ -470,6 +497,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // ---------------------------------------------------------------------------
 template <typename Real, int HT, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
+__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES)))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;

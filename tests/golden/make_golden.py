@@ -47,19 +47,18 @@ def sample_shifts(N: int, count: int = 256, seed: int = 7) -> list[int]:
 def cases():
     """(name, builder) for every stored case; builders are cheap."""
     out = []
-    s3 = W.config_seed(3)
-    out.append(("haar20_cfg3_sampled", lambda: W.haar(20, s3, np.complex64), "sampled"))
-    s5 = W.config_seed(5)
-    out.append(("haar22_cfg5_sampled", lambda: W.haar(22, s5, np.complex64), "sampled"))
-    out.append(("haar24_cfg5_sampled", lambda: W.haar(24, s5 + 1, np.complex64), "sampled"))
-    s2 = W.config_seed(2)
+    s20, sl = W.SEED_N20, W.SEED_LARGE
+    out.append(("haar20_sampled", lambda: W.haar(20, s20, np.complex64), "sampled"))
+    out.append(("haar22_sampled", lambda: W.haar(22, sl, np.complex64), "sampled"))
+    out.append(("haar24_sampled", lambda: W.haar(24, sl + 1, np.complex64), "sampled"))
+    s16 = W.SEED_N16_BATCH
     for i in range(32):
-        out.append((f"haar16_cfg2_{i}",
-                    (lambda i=i: W.haar(16, s2 * 1000 + i, np.complex64)), "full"))
-    out.append(("haar20_cfg3", lambda: W.haar(20, s3, np.complex64), "full"))
+        out.append((f"haar16_batch_{i}",
+                    (lambda i=i: W.haar(16, s16 * 1000 + i, np.complex64)), "full"))
+    out.append(("haar20", lambda: W.haar(20, s20, np.complex64), "full"))
     J = W.snapshot_couplings(20)
     for t in (5, 21):
-        out.append((f"ising20_cfg5_t{t}",
+        out.append((f"ising20_t{t}",
                     (lambda t=t: W.ising_snapshot(20, t, J, dtype=np.complex64)), "full"))
     return out
 

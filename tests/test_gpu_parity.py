@@ -187,23 +187,23 @@ def _sha(psi):
 def test_n20_full_size(oracle_mod, form):
     """Benchmark shape (N=20, complex64, default launch configuration)."""
     g = _golden()
-    psi = W.haar(20, W.config_seed(3), np.complex64)
+    psi = W.haar(20, W.SEED_N20, np.complex64)
     d = dev(psi)
     case_id("n20", form)
     r = sre2.m2(d, form=form, partials=True)
     assert r.status == 0
-    rec = g.get("haar20_cfg3_sampled")
+    rec = g.get("haar20_sampled")
     xs = rec["shifts"] if rec and rec["sha256"] == _sha(psi) else [0, 1, 12345, (1 << 20) - 1]
     ref = np.array(rec["partials"]) if rec and rec["sha256"] == _sha(psi) else \
         oracle_mod.partials(psi, xs)
     got = r.partials.cpu().numpy()[xs]
     assert np.max(np.abs(got - ref) / ref) <= TOL_SX[form]
-    full = g.get("haar20_cfg3")
+    full = g.get("haar20")
     if full and full["sha256"] == _sha(psi):
         assert abs(r.m2 - full["m2"]) <= TOL_M2[form], (r.m2, full["m2"])
     else:
         assert abs(r.m2 - (np.log2(2 ** 20 + 3) - 2)) < 1e-3  # Haar law (sanity)
-    psi_t, _ = W.graph_t(20, 10, W.config_seed(3) + 1, dtype=np.complex64)
+    psi_t, _ = W.graph_t(20, 10, W.SEED_N20 + 1, dtype=np.complex64)
     rt = sre2.m2(dev(psi_t), form=form)
     assert abs(rt.m2 - 10 * LOG43) <= closed_tol(form)
 
@@ -212,8 +212,8 @@ def test_n20_full_size(oracle_mod, form):
 @pytest.mark.parametrize("N", [22, 24])
 def test_large_n_sampled_shifts(N, form):
     g = _golden()
-    name = f"haar{N}_cfg5_sampled"
-    seed = W.config_seed(5) + (0 if N == 22 else 1)
+    name = f"haar{N}_sampled"
+    seed = W.SEED_LARGE + (0 if N == 22 else 1)
     psi = W.haar(N, seed, np.complex64)
     rec = g.get(name)
     if not rec or rec["sha256"] != _sha(psi):

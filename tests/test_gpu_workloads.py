@@ -50,7 +50,7 @@ def dev(psi):
 @pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
 def test_n16_batch(form):
     print("CASE n16-batch", form, flush=True)
-    inputs = W.config_inputs(2)
+    inputs = W.workload_inputs("n16_batch")
     g = golden()
     res = sre2.m2_batched([dev(p) for _, p, _ in inputs], form=form)
     checked = 0
@@ -61,7 +61,7 @@ def test_n16_batch(form):
             assert abs(r.m2 - closed) <= tol, name
             checked += 1
         else:
-            rec = g.get(f"haar16_cfg2_{i}")
+            rec = g.get(f"haar16_batch_{i}")
             if rec and rec["sha256"] == sha(psi):
                 assert abs(r.m2 - rec["m2"]) <= 1e-5, name
                 checked += 1
@@ -84,7 +84,7 @@ def test_n20_snapshot_sequence(form):
         r = sre2.m2(dev(psi), form=form)
         assert r.status == 0
         m[t] = r.m2
-        rec = g.get(f"ising20_cfg5_t{t}")
+        rec = g.get(f"ising20_t{t}")
         if rec and rec["sha256"] == sha(psi):
             assert abs(r.m2 - rec["m2"]) <= 1e-5, t
     for t in (0, 16, 32, 48):

@@ -2,12 +2,17 @@
 
 This package holds no part of the method's arithmetic: it only builds state
 vectors (and request streams) of the shapes the paper and its benchmark
-configurations use.  Both the CPU oracle and the GPU path consume its output;
+workloads use.  Both the CPU oracle and the GPU path consume its output;
 neither is imported from here.
 """
 from .states import (  # noqa: F401
     BASE_SEED,
-    config_seed,
+    SEED_N10,
+    SEED_N16_BATCH,
+    SEED_N20,
+    SEED_SERVING,
+    SEED_LARGE,
+    WORKLOADS,
     haar,
     t_product,
     graph,
@@ -18,7 +23,7 @@ from .states import (  # noqa: F401
     plus_state,
     apply_random_clifford,
     to_dtype,
-    config_inputs,
+    workload_inputs,
     serving_requests,
     build_request,
     ising_energy,

@@ -9,18 +9,19 @@ Conventions
 * Every generator builds the state in float64 / complex128, normalises it in
   float64, and only then casts (``to_dtype``).  The oracle receives exactly the
   cast bytes, upcast to complex128.
-* Random draws use ``numpy.random.default_rng`` (PCG64) with explicit seeds.
-  ``config_seed(i)`` = 2512_24685 + i is the seed of benchmark configuration i.
+* Random draws use ``numpy.random.default_rng`` (PCG64) with explicit seeds,
+  one base seed per workload (``SEED_*``).
 """
 from __future__ import annotations
 
 import numpy as np
 
 BASE_SEED = 2512_24685
-
-
-def config_seed(index: int) -> int:
-    return BASE_SEED + int(index)
+SEED_N10 = BASE_SEED + 1        # small single states, N = 10 (complex128)
+SEED_N16_BATCH = BASE_SEED + 2  # batch of 40 states, N = 16
+SEED_N20 = BASE_SEED + 3        # single state, N = 20 (the throughput workload)
+SEED_SERVING = BASE_SEED + 4    # serving request stream, N = 8..18
+SEED_LARGE = BASE_SEED + 5      # N = 22 / 24 states and the N = 20 Ising snapshots
 
 
 def _indices(N: int) -> np.ndarray:
@@ -193,20 +194,24 @@ def apply_random_clifford(psi: np.ndarray, seed: int, layers: int = 4) -> np.nda
 
 
 # ---------------------------------------------------------------------------
-# Benchmark configurations as concrete inputs.
+# Workloads as concrete inputs.
 # ---------------------------------------------------------------------------
 
-def config_inputs(index: int):
-    """Inputs of benchmark configuration `index` (1-based) as a list of
-    (name, psi, expected_closed_form_or_None).  Configuration 4 (serving) is
-    produced by `serving_requests`."""
-    seed = config_seed(index)
+WORKLOADS = ("n10_small", "n16_batch", "n20_single", "n22_n24_large")
+
+
+def workload_inputs(name: str):
+    """Inputs of a named workload as a list of (name, psi,
+    expected_closed_form_or_None).  The serving stream is produced by
+    `serving_requests`."""
     out = []
-    if index == 1:
+    if name == "n10_small":
+        seed = SEED_N10
         out.append(("haar10", haar(10, seed), None))
         out.append(("t10", t_product(10), 10 * np.log2(4.0 / 3.0)))
         out.append(("graph10", graph(10, seed + 100), 0.0))
-    elif index == 2:
+    elif name == "n16_batch":
+        seed = SEED_N16_BATCH
         rng = np.random.default_rng(seed)
         for i in range(32):
             out.append((f"haar16_{i}", haar(16, seed * 1000 + i, np.complex64), None))
@@ -214,15 +219,17 @@ def config_inputs(index: int):
             m = int(rng.integers(1, 9))
             psi, _ = graph_t(16, m, seed * 1000 + 500 + i, dtype=np.complex64)
             out.append((f"graphT16_{i}_m{m}", psi, m * np.log2(4.0 / 3.0)))
-    elif index == 3:
+    elif name == "n20_single":
+        seed = SEED_N20
         out.append(("haar20", haar(20, seed, np.complex64), None))
         psi, _ = graph_t(20, 10, seed + 1, dtype=np.complex64)
         out.append(("graphT20_m10", psi, 10 * np.log2(4.0 / 3.0)))
-    elif index == 5:
+    elif name == "n22_n24_large":
+        seed = SEED_LARGE
         out.append(("haar22", haar(22, seed, np.complex64), None))
         out.append(("haar24", haar(24, seed + 1, np.complex64), None))
     else:
-        raise ValueError(f"no static inputs for configuration {index}")
+        raise ValueError(f"unknown workload {name!r}")
     return out
 
 
@@ -231,7 +238,7 @@ def serving_requests(count: int = 4096, seed: int | None = None,
     """Serving stream: N ~ U{n_min..n_max}; kind 50/50 Haar or graph+T with
     m ~ U{1..8}; complex64.  Returns a list of dicts with the request's N,
     kind, seed and m (states are built lazily with `build_request`)."""
-    rng = np.random.default_rng(config_seed(4) if seed is None else seed)
+    rng = np.random.default_rng(SEED_SERVING if seed is None else seed)
     reqs = []
     for i in range(count):
         N = int(rng.integers(n_min, n_max + 1))
@@ -251,5 +258,5 @@ def build_request(req) -> np.ndarray:
 
 
 def snapshot_couplings(N: int = 20) -> np.ndarray:
-    """Couplings of the 64-snapshot Ising sequence (benchmark configuration 5)."""
-    return ising_couplings(N, config_seed(5) + 2)
+    """Couplings of the 64-snapshot Ising sequence."""
+    return ising_couplings(N, SEED_LARGE + 2)
