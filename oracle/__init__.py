@@ -17,6 +17,10 @@ brute_sum(psi)           sum over all 4^N Pauli strings of |<P>|^4, O(8^N).
 pauli_expect(psi, x, z)  <psi|X^x Z^z|psi> by the direct sum (Eq. Pauli_expect).
 shift_transform(psi, x)  W_x(z) for all z (one FWHT).
 fwht(a)                  unnormalised FWHT of a complex vector.
+sre(psi, alpha)          M_alpha of Eq. 1 for any alpha > 0 (alpha = 1: the limit).
+alpha_sum(psi, alpha)    sum over Pauli strings of w^alpha (w log2 w at alpha = 1).
+brute_alpha_sum(...)     the same by the direct expectation values, O(8^N).
+spectrum(psi, nbins)     Pauli-spectrum histogram of q = |<P>|^2 (bins round(-log2 q)).
 """
 from __future__ import annotations
 
@@ -64,6 +68,9 @@ def _load():
         "sre2o_norm2": [dp, c_int, dp],
         "sre2o_m2": [dp, c_int, c_int, dp, dp, dp],
         "sre2o_max_threads": [],
+        "sre2o_alpha_sum": [dp, c_int, ctypes.c_double, c_int, c_int, dp],
+        "sre2o_brute_alpha_sum": [dp, c_int, ctypes.c_double, c_int, c_int, dp],
+        "sre2o_spectrum": [dp, c_int, c_int, ctypes.c_double, c_int, i64p, i64p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -175,3 +182,51 @@ def fwht(v) -> np.ndarray:
     out = a.copy()
     _check(_load().sre2o_fwht(_dp(out), N), "fwht")
     return out
+
+
+def _kind(alpha: float) -> int:
+    if not alpha > 0:
+        raise ValueError("alpha must be positive")
+    return 2 if alpha == 1 else 1
+
+
+def alpha_sum(psi, alpha: float, threads: int = 0) -> float:
+    """sum_{x,z} w^alpha (alpha != 1) or sum w log2 w (alpha = 1), w = |W_x(z)|^2."""
+    a, N = _as_c128(psi)
+    out = ctypes.c_double()
+    _check(_load().sre2o_alpha_sum(_dp(a), N, float(alpha), _kind(alpha), threads,
+                                   ctypes.byref(out)), "alpha_sum")
+    return float(out.value)
+
+
+def brute_alpha_sum(psi, alpha: float, threads: int = 0) -> float:
+    a, N = _as_c128(psi)
+    out = ctypes.c_double()
+    _check(_load().sre2o_brute_alpha_sum(_dp(a), N, float(alpha), _kind(alpha), threads,
+                                         ctypes.byref(out)), "brute_alpha_sum")
+    return float(out.value)
+
+
+def sre_from_sum(S: float, n: float, N: int, alpha: float) -> float:
+    """M_alpha (Eq. 1) from the Pauli sum and n = sum |psi|^2."""
+    if alpha == 1:
+        return float(np.log2(n * n) - S / (2.0 ** N * n * n))
+    return float((np.log2(S) - N - alpha * np.log2(n * n)) / (1.0 - alpha))
+
+
+def sre(psi, alpha: float, threads: int = 0) -> float:
+    a, N = _as_c128(psi)
+    return sre_from_sum(alpha_sum(a, alpha, threads), norm2(a), N, alpha)
+
+
+def spectrum(psi, nbins: int, eps: float = 1e-3, threads: int = 0):
+    """(counts, near_edge): counts[b] = number of Pauli strings with
+    round(-log2(|<P>|^2)) = b (last bin: everything beyond, and zeros);
+    near_edge = strings within eps of a bin edge in -log2 units."""
+    a, N = _as_c128(psi)
+    counts = np.zeros(nbins, dtype=np.int64)
+    near = ctypes.c_int64()
+    _check(_load().sre2o_spectrum(_dp(a), N, nbins, float(eps), threads,
+                                  counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  ctypes.byref(near)), "spectrum")
+    return counts, int(near.value)

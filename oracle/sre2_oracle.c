@@ -25,6 +25,14 @@
  * oracle returns M2 = -log2( S / (2^N n^4) ), which is the paper's value when
  * n = 1 and is invariant under psi -> c psi.
  *
+ * General Renyi index (Eq. 1), w = |<X^x Z^z>|^2 before normalisation:
+ *   alpha != 1        M_alpha = log2( sum w^alpha / (2^N n^(2 alpha)) ) / (1 - alpha)
+ *   alpha -> 1        M_1 = -sum_P Xi_P log2 Xi_P - N,  Xi_P = w / (2^N n^2);
+ *                     with sum_P w = 2^N n^2 (purity of a pure state) this is
+ *                     M_1 = log2(n^2) - (sum w log2 w) / (2^N n^2)
+ *   Pauli spectrum    counts of q = w / n^2 in bins b = round(-log2 q), the
+ *                     last bin also taking q = 0 and everything beyond it.
+ *
  * Arrays are interleaved (re, im) doubles of length 2 * 2^N.  Every function
  * returns 0 on success and a negative value on a bad argument.
  */
@@ -302,5 +310,150 @@ int sre2o_m2(const double *psi, int N, int nthreads, double *m2, double *total,
         *total = s;
     if (norm2)
         *norm2 = n;
+    return 0;
+}
+
+/* Term of the generalised Pauli sum for one w = |W|^2: kind 1 -> w^alpha,
+ * kind 2 -> w log2 w (0 at w = 0). */
+static double alpha_term(double w, double alpha, int kind)
+{
+    if (!(w > 0.0))
+        return 0.0;
+    return kind == 1 ? pow(w, alpha) : w * log2(w);
+}
+
+/* Generalised sums of Eq. 1 by the per-shift FWHT of Algorithm 1, with the
+ * quartic replaced by alpha_term: per-shift compensated sums over z, then a
+ * compensated sum over x in ascending order. */
+int sre2o_alpha_sum(const double *psi, int N, double alpha, int kind, int nthreads,
+                    double *out)
+{
+    if (!psi || !out || N < 0 || N > ORACLE_MAX_N || (kind != 1 && kind != 2) ||
+        !(alpha > 0.0))
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *per_x = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!per_x)
+        return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel
+    {
+        double *W = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        double *q = (double *)malloc(sizeof(double) * (size_t)d);
+        if (!W || !q) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t x = 0; x < d; ++x) {
+                sre2o_shift_transform(psi, N, (uint64_t)x, W);
+                for (int64_t z = 0; z < d; ++z)
+                    q[z] = alpha_term(W[2 * z] * W[2 * z] + W[2 * z + 1] * W[2 * z + 1], alpha,
+                                      kind);
+                per_x[x] = compensated_sum(q, d);
+            }
+        }
+        free(W);
+        free(q);
+    }
+    if (!err)
+        *out = compensated_sum(per_x, d);
+    free(per_x);
+    return err;
+}
+
+/* The same sums over all 4^N Pauli strings by the direct expectation values,
+ * O(8^N), N <= 12. */
+int sre2o_brute_alpha_sum(const double *psi, int N, double alpha, int kind, int nthreads,
+                          double *out)
+{
+    if (!psi || !out || N < 0 || N > 12 || (kind != 1 && kind != 2) || !(alpha > 0.0))
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *per_x = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!per_x)
+        return -2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t x = 0; x < d; ++x) {
+        double *q = (double *)malloc(sizeof(double) * (size_t)d);
+        for (int64_t z = 0; z < d; ++z) {
+            double re, im;
+            sre2o_pauli_expect(psi, N, (uint64_t)x, (uint64_t)z, &re, &im);
+            q[z] = alpha_term(re * re + im * im, alpha, kind);
+        }
+        per_x[x] = compensated_sum(q, d);
+        free(q);
+    }
+    *out = compensated_sum(per_x, d);
+    free(per_x);
+    return 0;
+}
+
+/* Pauli-spectrum histogram: for every Pauli string, q = |W|^2 / n^2 goes to
+ * bin round(-log2 q) (clamped to [0, nbins - 1]; q = 0 to the last bin).
+ * near_edge counts the strings whose -log2 q lies within eps of an edge
+ * between two bins (b + 1/2, b = 0 .. nbins - 2), where a rounding of the
+ * expectation value can change the bin. */
+int sre2o_spectrum(const double *psi, int N, int nbins, double eps, int nthreads,
+                   int64_t *counts, int64_t *near_edge)
+{
+    if (!psi || !counts || !near_edge || N < 0 || N > ORACLE_MAX_N || nbins < 2 ||
+        nbins > 64 || !(eps >= 0.0))
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double n;
+    int rc = sre2o_norm2(psi, N, &n);
+    if (rc)
+        return rc;
+    if (!(n > 0.0) || !isfinite(n))
+        return -3;
+    int64_t total[64] = {0};
+    int64_t near = 0;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel
+    {
+        int64_t mine[64] = {0};
+        int64_t mnear = 0;
+        double *W = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        if (!W) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t x = 0; x < d; ++x) {
+                sre2o_shift_transform(psi, N, (uint64_t)x, W);
+                for (int64_t z = 0; z < d; ++z) {
+                    const double q = (W[2 * z] * W[2 * z] + W[2 * z + 1] * W[2 * z + 1]) / (n * n);
+                    int b = nbins - 1;
+                    if (q > 0.0) {
+                        const double t = -log2(q);
+                        const double f = floor(t + 0.5);
+                        b = f < 0.0 ? 0 : (f > nbins - 1 ? nbins - 1 : (int)f);
+                        /* nearest edge e + 1/2 between bins e and e + 1 */
+                        const double r = t - 0.5;
+                        const double e = floor(r + 0.5);
+                        if (e >= 0.0 && e <= nbins - 2 && fabs(r - e) <= eps)
+                            ++mnear;
+                    }
+                    ++mine[b];
+                }
+            }
+        }
+        free(W);
+#pragma omp critical
+        {
+            for (int b = 0; b < nbins; ++b)
+                total[b] += mine[b];
+            near += mnear;
+        }
+    }
+    if (err)
+        return err;
+    for (int b = 0; b < nbins; ++b)
+        counts[b] = total[b];
+    *near_edge = near;
     return 0;
 }

@@ -206,3 +206,110 @@ def test_partials_match_full_and_sum(oracle_mod):
     # S_0 = sum_z |FWHT(|psi|^2)(z)|^4
     F = oracle_mod.fwht(abs(psi) ** 2)
     assert abs(S_all[0] - np.sum(abs(F) ** 4)) < 1e-13 * S_all[0]
+
+
+# ---------------------------------------------------------------------------
+# General Renyi index (Eq. 1) and the Pauli spectrum.
+# ---------------------------------------------------------------------------
+
+ALPHAS = [0.5, 1.0, 1.5, 2.0, 3.0]
+
+
+def _t_single(alpha):
+    """M_alpha of one |T> qubit from Eq. 1: the four expectation values are
+    1 (identity), 1/sqrt2 (X, Y) and 0 (Z), so (1/2) sum |<P>|^(2 alpha) =
+    (1 + 2^(1 - alpha)) / 2; the alpha -> 1 limit is the Shannon form with
+    Xi = (1/2, 1/4, 1/4, 0): H = 3/2 bits, minus N = 1."""
+    if alpha == 1:
+        return 0.5
+    return np.log2((1.0 + 2.0 ** (1.0 - alpha)) / 2.0) / (1.0 - alpha)
+
+
+def _brute_spectrum(psi, nbins):
+    """Histogram straight from the textbook Pauli matrices (N <= 4)."""
+    N = psi.size.bit_length() - 1
+    n = np.vdot(psi, psi).real
+    counts = np.zeros(nbins, dtype=np.int64)
+    for x in range(1 << N):
+        for z in range(1 << N):
+            q = abs(np.vdot(psi, _pauli_matrix(N, x, z) @ psi)) ** 2 / n ** 2
+            if q < 1e-24:
+                counts[-1] += 1
+            else:
+                counts[min(nbins - 1, max(0, int(np.floor(-np.log2(q) + 0.5))))] += 1
+    return counts
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_alpha_sum_equals_brute_force(oracle_mod, N, alpha):
+    psi = W.haar(N, 700 + N)
+    a = oracle_mod.alpha_sum(psi, alpha)
+    b = oracle_mod.brute_alpha_sum(psi, alpha)
+    assert abs(a - b) <= 1e-12 * max(1.0, abs(b))
+    # against the textbook matrices for the smallest case
+    if N == 1:
+        ws = [abs(np.vdot(psi, _pauli_matrix(1, x, z) @ psi)) ** 2 for x in (0, 1) for z in (0, 1)]
+        ref = sum(w * np.log2(w) if alpha == 1 else w ** alpha for w in ws if w > 0)
+        assert abs(a - ref) <= 1e-13
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_alpha_closed_forms(oracle_mod, alpha):
+    for N in (1, 2, 4, 6):
+        assert abs(oracle_mod.sre(W.t_product(N), alpha) - N * _t_single(alpha)) < 1e-12
+    # faithfulness: stabilizer states give 0 for every index
+    for psi in (W.graph(6, 3), W.computational_basis(5, 9), W.plus_state(4)):
+        assert abs(oracle_mod.sre(psi, alpha)) < 1e-12
+    # alpha = 2 is M2
+    psi = W.haar(6, 71)
+    if alpha == 2:
+        assert abs(oracle_mod.sre(psi, 2.0) - oracle_mod.m2(psi)) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_alpha_invariants(oracle_mod, alpha):
+    a, b = W.haar(3, 81), W.haar(4, 82)
+    ab = np.kron(b, a)  # qubits of a are the low bits
+    assert abs(oracle_mod.sre(ab, alpha) - oracle_mod.sre(a, alpha)
+               - oracle_mod.sre(b, alpha)) < 1e-11  # additivity
+    psi = W.haar(6, 83)
+    m = oracle_mod.sre(psi, alpha)
+    assert abs(oracle_mod.sre(W.apply_random_clifford(psi, 5), alpha) - m) < 1e-11
+    assert abs(oracle_mod.sre((2.5 - 1j) * psi, alpha) - m) < 1e-11  # scale invariance
+    assert 0.0 <= m <= 6.0 + 1e-12
+
+
+def test_alpha_limit_and_monotonicity(oracle_mod):
+    psi = W.haar(6, 91)
+    m1 = oracle_mod.sre(psi, 1.0)
+    for h in (1e-3, 1e-4):
+        assert abs(oracle_mod.sre(psi, 1.0 + h) - m1) < 10 * h
+        assert abs(oracle_mod.sre(psi, 1.0 - h) - m1) < 10 * h
+    ms = [oracle_mod.sre(psi, a) for a in (0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)]
+    assert all(x >= y - 1e-12 for x, y in zip(ms, ms[1:]))  # Renyi order
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_spectrum_equals_textbook(oracle_mod, N):
+    for psi in (W.haar(N, 300 + N), W.t_product(N), W.graph(N, 4)):
+        counts, _ = oracle_mod.spectrum(psi, 12)
+        assert np.array_equal(counts, _brute_spectrum(psi, 12))
+        assert counts.sum() == 4 ** N
+
+
+def test_spectrum_closed_forms(oracle_mod):
+    from math import comb
+    for N in (3, 5):
+        d = 1 << N
+        counts, near = oracle_mod.spectrum(W.graph(N, 12), 10)
+        assert counts[0] == d and counts[-1] == d * d - d and counts[1:-1].sum() == 0
+        assert near == 0
+        counts, near = oracle_mod.spectrum(W.t_product(N), N + 2)
+        for k in range(N + 1):  # q = 2^-k for C(N, k) 2^k strings
+            assert counts[k] == comb(N, k) * 2 ** k
+        assert counts[-1] == 4 ** N - 3 ** N and near == 0
+    # scale invariance
+    psi = W.haar(5, 13)
+    assert np.array_equal(oracle_mod.spectrum(psi, 20)[0],
+                          oracle_mod.spectrum(3.0 * psi, 20)[0])
