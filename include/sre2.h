@@ -131,6 +131,37 @@ size_t sre2_workspace_bytes(int N, int dtype, int form);
 int sre2_m2(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, void* stream,
             double* out, double* partials);
 
+/* Stabilizer Renyi entropy of any index alpha > 0 (Eq. 1):
+ *   M_alpha = log2( sum_P |<P>|^(2 alpha) / 2^N ) / (1 - alpha),
+ * and for alpha = 1 its limit M_1 = -sum_P Xi_P log2 Xi_P - N with
+ * Xi_P = |<P>|^2 / 2^N (using sum_P |<P>|^2 = 2^N for a pure state).  The
+ * same shift transforms as sre2_m2 feed sum w^alpha (or sum w log2 w),
+ * w = |W_x(z)|^2, each term evaluated in the form's precision and summed in
+ * FP64; the input need not be normalised (<P> = W / n).
+ *   out  device, SRE2_OUT_LEN doubles: M_alpha, the Pauli sum (of w^alpha,
+ *        or of w log2 w at alpha = 1, before normalisation), n, status
+ * alpha = 2 runs exactly sre2_m2 (bitwise equal results).  The split form
+ * supports alpha = 2 only.
+ * Errors: as sre2_m2; SRE2_EINVAL for alpha not positive and finite;
+ * SRE2_EFORM for the split form with alpha != 2. */
+int sre2_sre(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, double alpha,
+             void* stream, double* out);
+
+/* Pauli spectrum: histogram of q_P = |<P>|^2 over all 4^N Pauli strings.
+ * String P goes to bin round(-log2 q_P) clamped to [0, nbins - 1]; q_P = 0
+ * goes to the last bin, which thus holds everything below 2^-(nbins - 1.5).
+ * Bin edges sit halfway (in log2) between powers of two, so the values
+ * 2^-k of stabilizer and |T>-product states land at bin centres.  Values
+ * within rounding of an edge may fall on either side; below the form's
+ * precision floor (FP32: q ~ 1e-12) bins hold rounding noise.
+ *   nbins   2 .. 64
+ *   counts  device, nbins uint64 counters (cleared by the call)
+ *   out     device, SRE2_OUT_LEN doubles: NaN, 0, n, status
+ * Errors: as sre2_m2; SRE2_EINVAL for a bad nbins or null pointers;
+ * SRE2_EFORM for the split form. */
+int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int nbins,
+                        void* stream, uint64_t* counts, double* out);
+
 /* Per-shift sums S_x for x in [x_begin, x_begin + x_count) only - the unit a
  * multi-GPU shard computes (shifts are independent; each GPU takes a range and
  * the totals add).  partials (device, x_count doubles) receives S_x in order.

@@ -9,6 +9,8 @@ fallback: if the library is not built, loading fails with an error.
     import torch, paper_2512_24685_amd as sre2
     psi = torch.randn(1 << 16, dtype=torch.complex64, device="cuda")
     r = sre2.m2(psi)            # r.m2, r.S, r.n
+    r3 = sre2.sre(psi, 3.0)     # any Renyi index: r3.m2 holds M_3
+    counts, r = sre2.pauli_spectrum(psi, 32)
 """
 from __future__ import annotations
 
@@ -60,6 +62,8 @@ def lib():
         "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_partials": ([vp, vp, c_int, c_int, c_int, i64, i64, vp, vp], c_int),
+        "sre2_sre": ([vp, vp, c_int, c_int, c_int, ctypes.c_double, vp, vp], c_int),
+        "sre2_pauli_spectrum": ([vp, vp, c_int, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_m2_batched": ([vp, ctypes.POINTER(vp), ctypes.POINTER(c_int), c_int, c_int, c_int,
                              vp, vp], c_int),
         "sre2_set_timing": ([vp, c_int], c_int),
@@ -222,6 +226,43 @@ def m2(psi, form: str = "fp32", partials: bool = False, ctx: Context | None = No
     """M2 of one device-resident state (synchronises to read the result)."""
     out, part = m2_async(psi, form, partials, ctx, stream)
     return _result(out.cpu(), part)
+
+
+def sre(psi, alpha: float = 2.0, form: str = "fp32", ctx: Context | None = None,
+        stream=None) -> Result:
+    """Stabilizer Renyi entropy M_alpha (Eq. 1) of one device state, any
+    alpha > 0 (alpha = 1: the limit); Result.m2 holds M_alpha and Result.S
+    the Pauli sum.  alpha = 2 is exactly m2()."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    ctx = ctx or context(psi.device.index or 0)
+    out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
+    rc = lib().sre2_sre(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
+                        FORMS[form], float(alpha), ctypes.c_void_p(_stream_ptr(psi, stream)),
+                        ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_sre")
+    return _result(out.cpu())
+
+
+def pauli_spectrum(psi, nbins: int = 32, form: str = "fp32", ctx: Context | None = None,
+                   stream=None):
+    """Histogram of |<P>|^2 over all 4^N Pauli strings in bins round(-log2 q)
+    (last bin: everything beyond, and zeros).  Returns (counts as a numpy
+    int64 array, Result with n and status)."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    ctx = ctx or context(psi.device.index or 0)
+    out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
+    counts = torch.empty(int(nbins), dtype=torch.int64, device=psi.device)
+    rc = lib().sre2_pauli_spectrum(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N,
+                                   _dtype_code(psi), FORMS[form], int(nbins),
+                                   ctypes.c_void_p(_stream_ptr(psi, stream)),
+                                   ctypes.c_void_p(counts.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_pauli_spectrum")
+    return counts.cpu().numpy(), _result(out.cpu())
 
 
 def shift_partials(psi, x_begin: int = 0, x_count: int | None = None, form: str = "fp32",

@@ -13,6 +13,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -171,7 +172,7 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
 
 // Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
 int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
-             double* Sx, const int* se, hipStream_t st) {
+             double* Sx, const int* se, const Spec* spec, hipStream_t st) {
     const bool f64 = is_f64(form), split = is_split(form);
     const Chunking ch = chunking(N, form, herm, xc, ctx->scratch_limit);
     for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
@@ -186,8 +187,10 @@ int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_
         if (e != hipSuccess) return SRE2_EHIP;
         {
             Timed tm(ctx, st, SRE2_KIND_PASS2);
-            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se, st)
-                    : launch_pass2<float>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se, st);
+            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se,
+                                           spec, st)
+                    : launch_pass2<float>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se,
+                                          spec, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
@@ -203,7 +206,7 @@ int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_
 // forms route the shifts they cannot take (x = 0 fused, x < 2^L two-pass,
 // or N too small) through the plain kernels of the same precision.
 int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
-               double* Sx, const int* se, hipStream_t st) {
+               double* Sx, const int* se, const Spec* spec, hipStream_t st) {
     const bool f64 = is_f64(form), sp = is_split(form);
     const int64_t x1 = x0 + xc;
     if (N <= fused_max(form)) {
@@ -213,18 +216,18 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
                 f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se,
-                                                  Pack{}, st)
+                                                  Pack{}, spec, st)
                     : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se,
-                                                 Pack{}, st);
+                                                 Pack{}, spec, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         if (x1 > split) {
             Timed tm(ctx, st, SRE2_KIND_SHIFT);
             const hipError_t e =
                 f64 ? launch_shift_kernel<double>(work, N, true, false, split, x1 - split,
-                                                  Sx + (split - x0), se, Pack{}, st)
+                                                  Sx + (split - x0), se, Pack{}, spec, st)
                     : launch_shift_kernel<float>(work, N, true, false, split, x1 - split,
-                                                 Sx + (split - x0), se, Pack{}, st);
+                                                 Sx + (split - x0), se, Pack{}, spec, st);
             if (e != hipSuccess) return SRE2_EHIP;
         }
         return SRE2_OK;
@@ -251,30 +254,34 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
     rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
     if (rc) return rc;
     if (split > x0) {
-        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, st);
+        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, spec, st);
         if (rc) return rc;
     }
     if (x1 > split)
-        rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), se, st);
+        rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), se, spec,
+                      st);
     return rc;
 }
 
 // Workspace layout of ctx->red: norm partials, non-finite flags, S partials
-// (kMaxRed doubles each), then one int: the split form's scale exponent.
+// (kMaxRed doubles each), one int (the split form's scale exponent) in a
+// double, then n (the histogram's normalisation).
 struct Red {
     double* npart;
     double* nflag;
     double* spart;
     int* se;
+    double* nrm;
 };
 
 int red_buffers(sre2_ctx* ctx, Red* r) {
-    const int rc = ensure((void**)&ctx->red, &ctx->red_bytes, (3 * kMaxRed + 1) * sizeof(double));
+    const int rc = ensure((void**)&ctx->red, &ctx->red_bytes, (3 * kMaxRed + 2) * sizeof(double));
     if (rc) return rc;
     r->npart = ctx->red;
     r->nflag = ctx->red + kMaxRed;
     r->spart = ctx->red + 2 * kMaxRed;
     r->se = reinterpret_cast<int*>(ctx->red + 3 * kMaxRed);
+    r->nrm = ctx->red + 3 * kMaxRed + 1;
     return SRE2_OK;
 }
 
@@ -289,8 +296,10 @@ int norm_stage(sre2_ctx* ctx, const void* work, int N, int form, const Red& r, i
     return rc;
 }
 
+// M2 (spec == nullptr), or the general reduction of spec: M_alpha / M_1 in
+// out, or the Pauli-spectrum counts in spec->hist (cleared here first).
 int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st, double* out,
-           double* partials) {
+           double* partials, const Spec* spec = nullptr) {
     const void* work = nullptr;
     int rc = stage_input(ctx, psi, N, dtype, form, st, &work);
     if (rc) return rc;
@@ -307,7 +316,18 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
         if (rc) return rc;
         Sx = ctx->sx;
     }
-    rc = shift_sums(ctx, work, N, form, 0, n, Sx, r.se, st);
+    Spec sp{};
+    if (spec) {
+        sp = *spec;
+        if (sp.kind == kRedHist) {
+            Timed tm(ctx, st, SRE2_KIND_AUX);
+            rc = hip_status(launch_norm_total(r.npart, nb, r.nrm, st));
+            if (!rc) rc = hip_status(launch_zero_u64(sp.hist, sp.nbins, st));
+            if (rc) return rc;
+            sp.nrm = r.nrm;
+        }
+    }
+    rc = shift_sums(ctx, work, N, form, 0, n, Sx, r.se, spec ? &sp : nullptr, st);
     if (rc) return rc;
     {
         Timed tm(ctx, st, SRE2_KIND_AUX);
@@ -315,7 +335,8 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
     }
     if (rc) return rc;
     Timed tm(ctx, st, SRE2_KIND_AUX);
-    return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, Pack{}, st));
+    return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, Pack{},
+                                   spec ? sp.kind : kRedQuartic, spec ? sp.alpha : 2.0, st));
 }
 
 // Up to kMaxPack states of one N <= fused_max(form) in packed launches: the
@@ -359,19 +380,20 @@ int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, 
         Timed tm(ctx, st, SRE2_KIND_SHIFT);
         const int64_t plain_end = herm ? 1 : n;
         hipError_t e = f64 ? launch_shift_kernel<double>(nullptr, N, false, false, 0, plain_end,
-                                                         nullptr, nullptr, pk, st)
+                                                         nullptr, nullptr, pk, nullptr, st)
                            : launch_shift_kernel<float>(nullptr, N, false, sp, 0, plain_end,
-                                                        nullptr, nullptr, pk, st);
+                                                        nullptr, nullptr, pk, nullptr, st);
         if (e == hipSuccess && herm)
             e = f64 ? launch_shift_kernel<double>(nullptr, N, true, false, 1, n - 1, nullptr,
-                                                  nullptr, pk, st)
+                                                  nullptr, pk, nullptr, st)
                     : launch_shift_kernel<float>(nullptr, N, true, false, 1, n - 1, nullptr,
-                                                 nullptr, pk, st);
+                                                 nullptr, pk, nullptr, st);
         if (e != hipSuccess) return SRE2_EHIP;
     }
     Timed tm(ctx, st, SRE2_KIND_AUX);
     if (launch_sum(nullptr, n, 1, nb, nullptr, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
-    if (launch_final(nullptr, nb, nullptr, nullptr, nb, N, nullptr, pk, st) != hipSuccess)
+    if (launch_final(nullptr, nb, nullptr, nullptr, nb, N, nullptr, pk, kRedQuartic, 2.0, st) !=
+        hipSuccess)
         return SRE2_EHIP;
     return SRE2_OK;
 }
@@ -461,7 +483,7 @@ int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes) {
 size_t sre2_workspace_bytes(int N, int dtype, int form) {
     if (N < 1 || N > SRE2_MAX_N || !dtype_ok(dtype) || !form_ok(form)) return 0;
     const size_t n = size_t(1) << N;
-    size_t b = (3 * kMaxRed + 1) * sizeof(double) + n * sizeof(double);
+    size_t b = (3 * kMaxRed + 2) * sizeof(double) + n * sizeof(double);
     if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
     const Chunking ch = chunking(N, form, false, (int64_t)n, size_t(4) << 30);
     if (ch.cs) {
@@ -479,6 +501,36 @@ int sre2_m2(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, void* st
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return SRE2_EHIP;
     return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, partials);
+}
+
+int sre2_sre(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, double alpha,
+             void* stream, double* out) {
+    int rc = validate(ctx, psi, N, dtype, form);
+    if (rc) return rc;
+    if (!out || !(alpha > 0.0) || !std::isfinite(alpha)) return SRE2_EINVAL;
+    if (alpha != 2.0 && is_split(form)) return SRE2_EFORM;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    if (alpha == 2.0) return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, nullptr);
+    Spec sp{};
+    sp.kind = alpha == 1.0 ? kRedShannon : kRedPow;
+    sp.alpha = alpha;
+    return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, nullptr, &sp);
+}
+
+int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int nbins,
+                        void* stream, uint64_t* counts, double* out) {
+    int rc = validate(ctx, psi, N, dtype, form);
+    if (rc) return rc;
+    if (!counts || !out || nbins < 2 || nbins > kMaxBins) return SRE2_EINVAL;
+    if (is_split(form)) return SRE2_EFORM;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    Spec sp{};
+    sp.kind = kRedHist;
+    sp.nbins = nbins;
+    sp.hist = reinterpret_cast<unsigned long long*>(counts);
+    return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, nullptr, &sp);
 }
 
 int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
@@ -501,7 +553,7 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
         rc = norm_stage(ctx, work, N, form, r, red_blocks(n), st);
         if (rc) return rc;
     }
-    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, r.se, st);
+    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, r.se, nullptr, st);
 }
 
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,

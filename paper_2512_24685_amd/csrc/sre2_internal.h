@@ -42,6 +42,26 @@ __host__ __device__ inline int* pk_se(double* ws, int N) {
 constexpr int kC64 = 0;
 constexpr int kC128 = 1;
 
+// Reduction of the transformed values (step a5) other than the default sum of
+// |W|^4: w = |W_x(z)|^2 of every Pauli string feeds
+//   kRedPow      sum w^alpha          (Renyi index alpha of Eq. 1)
+//   kRedShannon  sum w log2 w         (the alpha -> 1 limit)
+//   kRedHist     hist[b] += 1, b = round(-log2(w / n^2)) clamped to
+//                [0, nbins - 1], w = 0 in the last bin (Pauli spectrum)
+// Passed to the kernels by value; a null Spec* selects the default path.
+constexpr int kRedQuartic = 0;
+constexpr int kRedPow = 1;
+constexpr int kRedShannon = 2;
+constexpr int kRedHist = 3;
+constexpr int kMaxBins = 64;
+struct Spec {
+    int kind = kRedQuartic;
+    int nbins = 0;
+    double alpha = 2.0;
+    const double* nrm = nullptr;         // device: n = sum |psi|^2 (histogram)
+    unsigned long long* hist = nullptr;  // device: nbins counters (histogram)
+};
+
 // Geometry queries.  Two-pass is used for N > fused_max_n; pass 1 transforms
 // the low L = pass1_row_bits bits.  The Hermitian-pair forms need
 // N >= herm_min_n (fused) and shifts x >= 1 (fused) or x >= 2^L (two-pass);
@@ -58,9 +78,11 @@ template <typename Real> int64_t pass2_col_tiles(int N, bool herm);
 // transform (FP32 only, not with herm); it reads the scale exponent *se.
 // With pk.count > 0 the launch covers pk.count states of the same N (grid
 // y = state); psi / S / se then come from the pack (S = S_x of state y + x0).
+// sp != nullptr selects the general reduction (not with split or packs).
 template <typename Real>
 hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
-                               int64_t xc, double* S, const int* se, const Pack& pk, hipStream_t st);
+                               int64_t xc, double* S, const int* se, const Pack& pk,
+                               const Spec* sp, hipStream_t st);
 // Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
 // row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
 // pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
@@ -69,7 +91,11 @@ hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x
                         void* scratch, const int* se, hipStream_t st);
 template <typename Real>
 hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
-                        double* part, const int* se, hipStream_t st);
+                        double* part, const int* se, const Spec* sp, hipStream_t st);
+// *nrm = sum of the norm partials (for the histogram's normalisation).
+hipError_t launch_norm_total(const double* npart, int nb, double* nrm, hipStream_t st);
+// p[0 .. count) = 0 (a kernel, so that callers may capture it in a graph).
+hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
 // Scale exponent of the split form from the norm partials.
 hipError_t launch_split_scale(const double* npart, int nb, int* se, const Pack& pk, hipStream_t st);
 
@@ -81,8 +107,10 @@ hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, doubl
 hipError_t launch_sum(const double* v, int64_t nshift, int P, int nblocks, double* part,
                       double* Sx, const Pack& pk, hipStream_t st);
 hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, hipStream_t st);
+// out = {M, S, n, status}: M2 for kind kRedQuartic, M_alpha for kRedPow,
+// M_1 for kRedShannon, NaN for kRedHist.
 hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
-                        int nn, int N, double* out, const Pack& pk,
+                        int nn, int N, double* out, const Pack& pk, int kind, double alpha,
                         hipStream_t st);
 
 }  // namespace sre2

@@ -59,13 +59,66 @@ __device__ __forceinline__ double abs4h(C w) {
     return a * a + b * b;
 }
 
+// General reduction of one w = |W|^2 (Spec kinds): the term of the sum in
+// FP64, or (histogram) a count in the block's LDS bins.  lnorm2 = log2(n^2).
+template <typename Real>
+__device__ __forceinline__ double gen_term(Real w, const Spec& sp, Real lnorm2,
+                                           unsigned* __restrict__ lh) {
+    if (sp.kind == kRedHist) {
+        int b = sp.nbins - 1;
+        if (w > Real(0)) {  // NaN-safe: every comparison with NaN selects bin 0
+            const Real f = floor(lnorm2 - log2(w) + Real(0.5));
+            b = !(f >= Real(0)) ? 0 : (f >= Real(sp.nbins - 1) ? sp.nbins - 1 : (int)f);
+        }
+        atomicAdd(&lh[b], 1u);
+        return 0.0;
+    }
+    if (!(w > Real(0))) return 0.0;
+    if (sp.kind == kRedShannon) return (double)(w * log2(w));
+    return (double)exp2((Real)sp.alpha * log2(w));
+}
+
+// Terms of one transformed value: |W|^2 in the plain form; in the Hermitian
+// pair the real and imaginary parts stand for two Pauli strings with
+// |W| = 2 |Re| and 2 |Im|.
+template <typename Real, bool HERM, typename C>
+__device__ __forceinline__ double gen_terms(C v, const Spec& sp, Real lnorm2,
+                                            unsigned* __restrict__ lh) {
+    if constexpr (HERM)
+        return gen_term<Real>(Real(4) * v.x * v.x, sp, lnorm2, lh) +
+               gen_term<Real>(Real(4) * v.y * v.y, sp, lnorm2, lh);
+    else
+        return gen_term<Real>(v.x * v.x + v.y * v.y, sp, lnorm2, lh);
+}
+
+// Block-level histogram bins: cleared at kernel start, added to the global
+// counters at the end (GEN kernels with a histogram Spec only).
+__device__ __forceinline__ void hist_clear(unsigned* lh, const Spec& sp) {
+    if (sp.kind == kRedHist) {
+        for (int i = threadIdx.x; i < kMaxBins; i += blockDim.x) lh[i] = 0u;
+        __syncthreads();
+    }
+}
+__device__ __forceinline__ void hist_flush(unsigned* lh, const Spec& sp) {
+    if (sp.kind == kRedHist) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < sp.nbins; i += blockDim.x)
+            if (lh[i]) atomicAdd(&sp.hist[i], (unsigned long long)lh[i]);
+    }
+}
+template <typename Real>
+__device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
+    return sp.kind == kRedHist ? (Real)(2.0 * log2(*sp.nrm)) : Real(0);
+}
+
 #ifndef SRE2_SPLIT_P1_TAIL
 #define SRE2_SPLIT_P1_TAIL 1  // split-form pass 1 ends in a store-layout round
 #endif
 // Minimum waves per SIMD asked of the compiler (register budget 512 / waves).
-// The split-form kernels keep their MFMA results in VGPRs at 3 (with fewer,
-// the compiler moves them through AGPRs, which costs pass 1 about half its
-// speed); LDS limits every TB = 12 kernel to 2.5 waves per SIMD anyway.
+// Split-form pass 1 keeps its MFMA results in VGPRs at 3 (with fewer, the
+// compiler moves them through AGPRs, which costs it about half its speed);
+// LDS limits every TB = 12 kernel to 2.5 waves per SIMD anyway.  Split-form
+// pass 2 cannot reach 3 without spilling and is left alone.
 #ifndef SRE2_P1_WAVES
 #define SRE2_P1_WAVES 1
 #endif
@@ -76,7 +129,7 @@ __device__ __forceinline__ double abs4h(C w) {
 #define SRE2_P2_WAVES 1
 #endif
 #ifndef SRE2_P2S_WAVES
-#define SRE2_P2S_WAVES 3
+#define SRE2_P2S_WAVES 1
 #endif
 #ifndef SRE2_FUSED_WAVES
 #define SRE2_FUSED_WAVES 1
@@ -332,13 +385,32 @@ __device__ __forceinline__ void seg_tree(double* red, int seg) {
 // ---------------------------------------------------------------------------
 // Tiny N (N < RB): one thread per shift.
 // ---------------------------------------------------------------------------
-template <typename Real, int N>
+template <typename Real, int N, bool GEN>
 __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restrict__ psi,
                                              int64_t x_begin, int64_t x_count,
                                              double* __restrict__ S_out,
-                                             const Pack pk) {
+                                             const Pack pk, const Spec sp) {
     using C = typename CT<Real>::T;
     constexpr int D = 1 << N;
+    __shared__ unsigned lh[GEN ? kMaxBins : 1];
+    if constexpr (GEN) {
+        hist_clear(lh, sp);
+        const Real lnorm2 = hist_lnorm2<Real>(sp);
+        const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+        if (idx < x_count) {
+            const uint32_t x = (uint32_t)(x_begin + idx);
+            C v[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = cmul_conj_a(psi[k ^ x], psi[k]);
+            butterflies<N, (1u << N) - 1u, (1u << N) - 1u>(v);
+            double s = 0.0;
+#pragma unroll
+            for (int z = 0; z < D; ++z) s += gen_terms<Real, false>(v[z], sp, lnorm2, lh);
+            S_out[idx] = s;
+        }
+        hist_flush(lh, sp);
+        return;
+    }
     if (pk.count) {
         psi = (const C*)pk.psi[blockIdx.y];
         S_out = pk_sx(pk.ws[blockIdx.y], N) + x_begin;
@@ -366,12 +438,12 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 //                Re or twice i Im of this half transform, so
 //                S_x = 16 sum_z' (Re^4 + Im^4).
 // ---------------------------------------------------------------------------
-template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT>
+template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES : SRE2_FUSED_WAVES)))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out, const int* __restrict__ scale_exp,
-             const Pack pk) {
+             const Pack pk, const Spec sp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 1000 + NT + (SPLIT ? 10000 : 0);
@@ -380,12 +452,19 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     constexpr Round rl = P.r[P.nrounds - 1];
     constexpr int SPT = 1 << (TB - NT);
     constexpr uint32_t KMASK = (1u << NT) - 1u;
+    static_assert((rl.reg & ~KMASK) == 0, "last round: one shift per thread");
     __shared__ C lds[1 << TB];
+    __shared__ unsigned lh[GEN ? kMaxBins : 1];
     double* red = reinterpret_cast<double*>(lds);
     if (pk.count) {
         psi = (const C*)pk.psi[blockIdx.y];
         S_out = pk_sx(pk.ws[blockIdx.y], pk.N) + x_begin;
         scale_exp = pk_se(pk.ws[blockIdx.y], pk.N);
+    }
+    Real lnorm2 = Real(0);
+    if constexpr (GEN) {
+        hist_clear(lh, sp);
+        lnorm2 = hist_lnorm2<Real>(sp);
     }
 
     const int se = SPLIT ? *scale_exp : 0;
@@ -418,10 +497,22 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
         }
         run_transform<Real, TB, RB, PK>(lds, v);
         double s = 0.0;
+        if constexpr (GEN) {
+            // this thread's values belong to one shift slot (the last round's
+            // registers lie inside the transform bits); empty slots of the
+            // last tile hold zeros that must not enter the histogram
+            const int64_t slot = thread_base<rl.lperm, rl.wave>() >> NT;
+            if (tile * SPT + slot < x_count) {
 #pragma unroll
-        for (int i = 0; i < (1 << RB); ++i) s += HERM ? abs4h(v[i]) : abs4(v[i]);
-        if constexpr (HERM) s *= 16.0;
-        if constexpr (SPLIT) s *= unscale;
+                for (int i = 0; i < (1 << RB); ++i)
+                    s += gen_terms<Real, HERM>(v[i], sp, lnorm2, lh);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) s += HERM ? abs4h(v[i]) : abs4(v[i]);
+            if constexpr (HERM) s *= 16.0;
+            if constexpr (SPLIT) s *= unscale;
+        }
         // thread order index: tile bits outside the last round's registers,
         // compressed; its top TB-NT bits are the shift slot.
         const uint32_t q = pext(thread_base<rl.lperm, rl.wave>(), ((1u << TB) - 1u) & ~rl.reg);
@@ -433,6 +524,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
             if (tile * SPT + j < x_count) S_out[tile * SPT + j] = red[j * (T / SPT)];
         }
     }
+    if constexpr (GEN) hist_flush(lh, sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,11 +587,11 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // columns.  Block b -> shift slot b / P, column group b % P; the group loops
 // over its column tiles and writes one FP64 partial of S_x.
 // ---------------------------------------------------------------------------
-template <typename Real, int HT, int TB, int RB, bool HERM, bool SPLIT>
+template <typename Real, int HT, int TB, int RB, bool HERM, bool SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES)))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
-             double* __restrict__ part, const int* __restrict__ scale_exp) {
+             double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 3000 + HT + (SPLIT ? 10000 : 0);
@@ -509,6 +601,12 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     constexpr uint32_t CMASK = (1u << CB) - 1u;
     __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
     __shared__ double red[T];
+    __shared__ unsigned lh[GEN ? kMaxBins : 1];
+    Real lnorm2 = Real(0);
+    if constexpr (GEN) {
+        hist_clear(lh, sp);
+        lnorm2 = hist_lnorm2<Real>(sp);
+    }
 
     const int64_t b = blockIdx.x;
     const int64_t s = b / P;
@@ -528,14 +626,22 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
             v[i] = slab_load(src + ((uint64_t)(e >> CB) << L) + (e & CMASK));
         }
         run_transform<Real, TB, RB, PK>(lds, v);
+        if constexpr (GEN) {
 #pragma unroll
-        for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
+            for (int i = 0; i < (1 << RB); ++i) acc += gen_terms<Real, HERM>(v[i], sp, lnorm2, lh);
+        } else {
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
+        }
     }
-    if constexpr (HERM) acc *= 16.0;
-    if constexpr (SPLIT) acc *= ldexp(1.0, -4 * *scale_exp);
+    if constexpr (!GEN) {
+        if constexpr (HERM) acc *= 16.0;
+        if constexpr (SPLIT) acc *= ldexp(1.0, -4 * *scale_exp);
+    }
     red[threadIdx.x] = acc;
     seg_tree<T>(red, T);
     if (threadIdx.x == 0) part[b] = red[0];
+    if constexpr (GEN) hist_flush(lh, sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,7 +739,7 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
                                                        const double* __restrict__ npart,
                                                        const double* __restrict__ nflag, int nn,
                                                        int N, double* __restrict__ out,
-                                                       const Pack pk) {
+                                                       const Pack pk, int kind, double alpha) {
     __shared__ double red[kRedThreads];
     if (pk.count) {
         spart = pk_spart(pk.ws[blockIdx.y], pk.N);
@@ -661,7 +767,14 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
     if (threadIdx.x == 0) {
         const bool ok = bad == 0.0 && n > 0.0 && isfinite(n) && isfinite(S);
         const double n2 = n * n;
-        out[0] = ok ? -log2(S / (ldexp(1.0, N) * n2 * n2)) : NAN;
+        double m = NAN;
+        if (kind == kRedQuartic)
+            m = -log2(S / (ldexp(1.0, N) * n2 * n2));
+        else if (kind == kRedPow)  // Eq. 1: log2(S / (2^N n^(2 alpha))) / (1 - alpha)
+            m = (log2(S) - (double)N - alpha * log2(n2)) / (1.0 - alpha);
+        else if (kind == kRedShannon)  // alpha -> 1, with sum_P w = 2^N n^2
+            m = log2(n2) - S / (ldexp(1.0, N) * n2);
+        out[0] = ok ? m : NAN;
         out[1] = S;
         out[2] = n;
         out[3] = ok ? 0.0 : 1.0;
@@ -673,68 +786,72 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename Real, int N>
+template <typename Real, int N, bool GEN>
 hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S,
-                         const Pack& pk, hipStream_t st) {
+                         const Pack& pk, const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
     const int64_t blocks = (xc + 63) / 64;
-    hipLaunchKernelGGL((k_tiny<Real, N>), dim3((unsigned)blocks, (unsigned)(pk.count ? pk.count : 1)), dim3(64), 0, st,
-                       (const C*)psi, x0, xc, S, pk);
+    hipLaunchKernelGGL((k_tiny<Real, N, GEN>), dim3((unsigned)blocks, (unsigned)(pk.count ? pk.count : 1)), dim3(64), 0, st,
+                       (const C*)psi, x0, xc, S, pk, sp);
     return hipGetLastError();
 }
 
-template <typename Real, int NT, bool HERM, bool SPLIT>
+template <typename Real, int NT, bool HERM, bool SPLIT, bool GEN>
 hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, const int* se,
-                           const Pack& pk, hipStream_t st) {
+                           const Pack& pk, const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = fused_tb<Real>(NT), RB = Tune<Real>::RBF;
     constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT>), dim3((unsigned)grid, (unsigned)(pk.count ? pk.count : 1)),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se, pk);
+    hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT, GEN>), dim3((unsigned)grid, (unsigned)(pk.count ? pk.count : 1)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se, pk, sp);
     return hipGetLastError();
 }
 
-template <typename Real, int HT, bool HERM, bool SPLIT>
+template <typename Real, int HT, bool HERM, bool SPLIT, bool GEN>
 hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part, const int* se,
-                           hipStream_t st) {
+                           const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
-    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM, SPLIT>), dim3((unsigned)((int64_t)cs * P)),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part, se);
+    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM, SPLIT, GEN>), dim3((unsigned)((int64_t)cs * P)),
+                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part, se, sp);
     return hipGetLastError();
 }
 
-template <typename Real, int... Ns>
+template <typename Real, bool GEN, int... Ns>
 hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double* S,
-                         const Pack& pk, hipStream_t st,
+                         const Pack& pk, const Spec& sp, hipStream_t st,
                          std::integer_sequence<int, Ns...>) {
     hipError_t e = hipErrorInvalidValue;
-    ((N == Ns + 1 ? (e = launch_tiny_n<Real, Ns + 1>(psi, x0, xc, S, pk, st), 0) : 0),
+    ((N == Ns + 1 ? (e = launch_tiny_n<Real, Ns + 1, GEN>(psi, x0, xc, S, pk, sp, st), 0) : 0),
      ...);
     return e;
 }
 
-template <typename Real, bool HERM, bool SPLIT, int... Ns>
+template <typename Real, bool HERM, bool SPLIT, bool GEN, int... Ns>
 hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, double* S,
-                          const int* se, const Pack& pk, hipStream_t st,
+                          const int* se, const Pack& pk, const Spec& sp, hipStream_t st,
                           std::integer_sequence<int, Ns...>) {
     constexpr int RB = Tune<Real>::RBF;
     hipError_t e = hipErrorInvalidValue;
     ((NT == Ns + RB
-          ? (e = launch_fused_nt<Real, Ns + RB, HERM, SPLIT>(psi, x0, xc, S, se, pk, st), 0)
+          ? (e = launch_fused_nt<Real, Ns + RB, HERM, SPLIT, GEN>(psi, x0, xc, S, se, pk, sp, st),
+             0)
           : 0),
      ...);
     return e;
 }
 
-template <typename Real, bool HERM, bool SPLIT, int... Hs>
+template <typename Real, bool HERM, bool SPLIT, bool GEN, int... Hs>
 hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, double* part,
-                          const int* se, hipStream_t st, std::integer_sequence<int, Hs...>) {
+                          const int* se, const Spec& sp, hipStream_t st,
+                          std::integer_sequence<int, Hs...>) {
     hipError_t e = hipErrorInvalidValue;
     ((HT == Hs + 1
-          ? (e = launch_pass2_ht<Real, Hs + 1, HERM, SPLIT>(scratch, NS, cs, P, part, se, st), 0)
+          ? (e = launch_pass2_ht<Real, Hs + 1, HERM, SPLIT, GEN>(scratch, NS, cs, P, part, se, sp,
+                                                                 st),
+             0)
           : 0),
      ...);
     return e;
@@ -783,27 +900,43 @@ template int herm_min_n<double>();
 template int64_t pass2_col_tiles<float>(int, bool);
 template int64_t pass2_col_tiles<double>(int, bool);
 
-template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
-                               int64_t xc, double* S, const int* se, const Pack& pk, hipStream_t st) {
+template <typename Real, bool GEN>
+hipError_t shift_kernel_gen(const void* psi, int N, bool herm, bool split, int64_t x0,
+                            int64_t xc, double* S, const int* se, const Pack& pk, const Spec& sp,
+                            hipStream_t st) {
     constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
-    if (N > FMAX || (split && (herm || sizeof(Real) != 4)) || pk.count > kMaxPack)
-        return hipErrorInvalidValue;
     if (herm) {
         if (x0 < 1 || N - 1 < RB) return hipErrorInvalidValue;
-        return dispatch_fused<Real, true, false>(N - 1, psi, x0, xc, S, se, pk, st,
-                                                 std::make_integer_sequence<int, FMAX - RB>{});
+        return dispatch_fused<Real, true, false, GEN>(N - 1, psi, x0, xc, S, se, pk, sp, st,
+                                                      std::make_integer_sequence<int, FMAX - RB>{});
     }
     if (N < RB)
-        return dispatch_tiny<Real>(N, psi, x0, xc, S, pk, st,
-                                   std::make_integer_sequence<int, RB - 1>{});
-    if constexpr (sizeof(Real) == 4) {
+        return dispatch_tiny<Real, GEN>(N, psi, x0, xc, S, pk, sp, st,
+                                        std::make_integer_sequence<int, RB - 1>{});
+    if constexpr (sizeof(Real) == 4 && !GEN) {
         if (split)
-            return dispatch_fused<Real, false, true>(N, psi, x0, xc, S, se, pk, st,
-                                                     std::make_integer_sequence<int, FMAX - RB + 1>{});
+            return dispatch_fused<Real, false, true, false>(
+                N, psi, x0, xc, S, se, pk, sp, st, std::make_integer_sequence<int, FMAX - RB + 1>{});
     }
-    return dispatch_fused<Real, false, false>(N, psi, x0, xc, S, se, pk, st,
-                                              std::make_integer_sequence<int, FMAX - RB + 1>{});
+    return dispatch_fused<Real, false, false, GEN>(N, psi, x0, xc, S, se, pk, sp, st,
+                                                   std::make_integer_sequence<int, FMAX - RB + 1>{});
+}
+
+template <typename Real>
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
+                               int64_t xc, double* S, const int* se, const Pack& pk,
+                               const Spec* sp, hipStream_t st) {
+    constexpr int FMAX = Tune<Real>::FMAX;
+    if (N > FMAX || (split && (herm || sizeof(Real) != 4)) || pk.count > kMaxPack)
+        return hipErrorInvalidValue;
+    if (sp) {
+        if (split || pk.count || sp->kind < kRedPow || sp->kind > kRedHist ||
+            (sp->kind == kRedHist && (!sp->hist || !sp->nrm || sp->nbins < 2 ||
+                                      sp->nbins > kMaxBins)))
+            return hipErrorInvalidValue;
+        return shift_kernel_gen<Real, true>(psi, N, herm, split, x0, xc, S, se, pk, *sp, st);
+    }
+    return shift_kernel_gen<Real, false>(psi, N, herm, split, x0, xc, S, se, pk, Spec{}, st);
 }
 
 template <typename Real>
@@ -832,38 +965,54 @@ hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x
 
 template <typename Real>
 hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
-                        double* part, const int* se, hipStream_t st) {
+                        double* part, const int* se, const Spec* sp, hipStream_t st) {
     constexpr int ROW = Tune<Real>::ROW;
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
     if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
     constexpr int HMAX = max_n_of<Real>() - ROW;
+    if (sp) {
+        if (split || sp->kind < kRedPow || sp->kind > kRedHist ||
+            (sp->kind == kRedHist && (!sp->hist || !sp->nrm || sp->nbins < 2 ||
+                                      sp->nbins > kMaxBins)))
+            return hipErrorInvalidValue;
+        if (herm)
+            return dispatch_pass2<Real, true, false, true>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                           *sp, st,
+                                                           std::make_integer_sequence<int, HMAX>{});
+        return dispatch_pass2<Real, false, false, true>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                        *sp, st,
+                                                        std::make_integer_sequence<int, HMAX>{});
+    }
+    const Spec none{};
     if (herm)
-        return dispatch_pass2<Real, true, false>(NS - ROW, scratch, NS, cs, P, part, se, st,
-                                                 std::make_integer_sequence<int, HMAX>{});
+        return dispatch_pass2<Real, true, false, false>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                        none, st,
+                                                        std::make_integer_sequence<int, HMAX>{});
     if constexpr (sizeof(Real) == 4) {
         if (split)
-            return dispatch_pass2<Real, false, true>(NS - ROW, scratch, NS, cs, P, part, se, st,
-                                                     std::make_integer_sequence<int, HMAX>{});
+            return dispatch_pass2<Real, false, true, false>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                            none, st,
+                                                            std::make_integer_sequence<int, HMAX>{});
     }
-    return dispatch_pass2<Real, false, false>(NS - ROW, scratch, NS, cs, P, part, se, st,
-                                              std::make_integer_sequence<int, HMAX>{});
+    return dispatch_pass2<Real, false, false, false>(NS - ROW, scratch, NS, cs, P, part, se, none,
+                                                     st, std::make_integer_sequence<int, HMAX>{});
 }
 
 template hipError_t launch_shift_kernel<float>(const void*, int, bool, bool, int64_t, int64_t,
-                                               double*, const int*, const Pack&,
+                                               double*, const int*, const Pack&, const Spec*,
                                                hipStream_t);
 template hipError_t launch_shift_kernel<double>(const void*, int, bool, bool, int64_t, int64_t,
-                                                double*, const int*, const Pack&,
+                                                double*, const int*, const Pack&, const Spec*,
                                                 hipStream_t);
 template hipError_t launch_pass1<float>(const void*, int, bool, bool, int64_t, int, void*,
                                         const int*, hipStream_t);
 template hipError_t launch_pass1<double>(const void*, int, bool, bool, int64_t, int, void*,
                                          const int*, hipStream_t);
 template hipError_t launch_pass2<float>(const void*, int, bool, bool, int, int, double*,
-                                        const int*, hipStream_t);
+                                        const int*, const Spec*, hipStream_t);
 template hipError_t launch_pass2<double>(const void*, int, bool, bool, int, int, double*,
-                                         const int*, hipStream_t);
+                                         const int*, const Spec*, hipStream_t);
 
 // s = 14 - ceil(log2 n) from the norm partials (0 when n is not positive and
 // finite): with every |value| of a transform bounded by n, the scaled values
@@ -933,10 +1082,32 @@ hipError_t launch_group_sum(const double* part, int64_t ns, int P, double* Sx, h
 }
 
 hipError_t launch_final(const double* spart, int ns, const double* npart, const double* nflag,
-                        int nn, int N, double* out, const Pack& pk,
+                        int nn, int N, double* out, const Pack& pk, int kind, double alpha,
                         hipStream_t st) {
     hipLaunchKernelGGL(k_final, dim3(1, pk.count ? pk.count : 1), dim3(kRedThreads), 0, st, spart, ns, npart, nflag,
-                       nn, N, out, pk);
+                       nn, N, out, pk, kind, alpha);
+    return hipGetLastError();
+}
+
+__global__ void k_norm_total(const double* __restrict__ npart, int nb, double* __restrict__ nrm) {
+    if (threadIdx.x != 0) return;
+    double n = 0.0;
+    for (int i = 0; i < nb; ++i) n += npart[i];
+    *nrm = n;
+}
+
+hipError_t launch_norm_total(const double* npart, int nb, double* nrm, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm_total, dim3(1), dim3(64), 0, st, npart, nb, nrm);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u64, dim3((count + 63) / 64), dim3(64), 0, st, p, count);
     return hipGetLastError();
 }
 

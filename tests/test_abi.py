@@ -60,6 +60,25 @@ def test_m2_argument_validation(L, ctx):
     assert L.sre2_m2(h, FAKE, 10, 0, 0, None, None, None) == sre2.EINVAL
 
 
+def test_sre_and_spectrum_argument_validation(L, ctx):
+    h = ctx.handle
+    nan, inf = float("nan"), float("inf")
+    assert L.sre2_sre(None, FAKE, 10, 0, 0, 3.0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_sre(h, FAKE, 10, 0, 0, 3.0, None, None) == sre2.EINVAL
+    for a in (0.0, -1.0, nan, inf):
+        assert L.sre2_sre(h, FAKE, 10, 0, 0, a, None, FAKE) == sre2.EINVAL
+    assert L.sre2_sre(h, FAKE, 10, 7, 0, 3.0, None, FAKE) == sre2.EDTYPE
+    assert L.sre2_sre(h, FAKE, 10, 0, sre2.FORMS["split16"], 3.0, None, FAKE) == sre2.EFORM
+    assert L.sre2_sre(h, FAKE, 10, 0, sre2.FORMS["split16"], 1.0, None, FAKE) == sre2.EFORM
+    sp = L.sre2_pauli_spectrum
+    assert sp(h, FAKE, 10, 0, 0, 1, None, FAKE, FAKE) == sre2.EINVAL
+    assert sp(h, FAKE, 10, 0, 0, 65, None, FAKE, FAKE) == sre2.EINVAL
+    assert sp(h, FAKE, 10, 0, 0, 16, None, None, FAKE) == sre2.EINVAL
+    assert sp(h, FAKE, 10, 0, 0, 16, None, FAKE, None) == sre2.EINVAL
+    assert sp(h, FAKE, 0, 0, 0, 16, None, FAKE, FAKE) == sre2.EINVAL
+    assert sp(h, FAKE, 10, 0, sre2.FORMS["split16"], 16, None, FAKE, FAKE) == sre2.EFORM
+
+
 def test_partials_argument_validation(L, ctx):
     h = ctx.handle
     assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 17, None, FAKE) == sre2.EINVAL
