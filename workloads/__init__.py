@@ -29,4 +29,9 @@ from .states import (  # noqa: F401
     ising_energy,
     snapshot_couplings,
     random_adjacency,
+    TFIM_PARAMS,
+    product_angles,
+    haar_u4,
+    brickwork_pairs,
+    brickwork_gates,
 )

@@ -260,3 +260,45 @@ def build_request(req) -> np.ndarray:
 def snapshot_couplings(N: int = 20) -> np.ndarray:
     """Couplings of the 64-snapshot Ising sequence."""
     return ising_couplings(N, SEED_LARGE + 2)
+
+
+# ---------------------------------------------------------------------------
+# Dynamics workloads (quench dynamics of the paper's examples): random
+# product initial states, TFIM parameters, brickwork circuits of Haar U(4).
+# ---------------------------------------------------------------------------
+
+TFIM_PARAMS = {"J": 1.0, "hx": 1.5, "hz": 1.5, "dt": 0.2}
+
+
+def product_angles(N: int, seed: int):
+    """Angles of the random product state prod_i (cos(theta_i/2)|0> +
+    e^{i phi_i} sin(theta_i/2)|1>): theta_i ~ U[0, pi], phi_i ~ U[0, 2 pi),
+    independent (qubit i = bit i)."""
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, np.pi, N)
+    phi = rng.uniform(0.0, 2.0 * np.pi, N)
+    return theta, phi
+
+
+def haar_u4(rng: np.random.Generator) -> np.ndarray:
+    """One Haar-random 4x4 unitary: QR of a complex Ginibre matrix with the
+    phases of R's diagonal moved into Q (Mezzadri's construction)."""
+    Z = (rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(Z)
+    d = np.diag(R)
+    return Q * (d / np.abs(d))[None, :]
+
+
+def brickwork_pairs(N: int):
+    """Bonds of one brickwork time step on an open chain: even bonds
+    (0,1), (2,3), ..., then odd bonds (1,2), (3,4), ..."""
+    return [(q, q + 1) for q in range(0, N - 1, 2)] + [(q, q + 1) for q in range(1, N - 1, 2)]
+
+
+def brickwork_gates(N: int, steps: int, seed: int):
+    """(gates, pairs): gates[t][g] is the Haar U(4) of step t on bond
+    pairs[g]; a gate acts on the index j = bit(q0) + 2 bit(q1) of its pair."""
+    rng = np.random.default_rng(seed)
+    pairs = brickwork_pairs(N)
+    gates = np.array([[haar_u4(rng) for _ in pairs] for _ in range(steps)], dtype=np.complex128)
+    return gates, pairs
