@@ -273,6 +273,54 @@ int sre2_server_stats(sre2_server* s, int64_t* stats, int count);
  * accepted.  Returns SRE2_EHIP if device work failed. */
 int sre2_server_destroy(sre2_server* s);
 
+/* ---- quench-dynamics simulator and snapshot pipeline ------------------
+ * A complex128 state vector of N qubits (2 <= N <= 26) on one device, with
+ * its own HIP stream, for the paper's two quench examples.  Qubit i is bit i
+ * of the basis index, |0> = spin up (Z = +1).  All calls are asynchronous on
+ * the simulator's stream except sre2_sim_state and the pipeline runs. */
+typedef struct sre2_sim sre2_sim;
+
+/* Creates the simulator in |0...0>.  Errors: SRE2_EINVAL, SRE2_ENOMEM,
+ * SRE2_EHIP. */
+int sre2_sim_create(sre2_sim** out, int hip_device, int N);
+int sre2_sim_destroy(sre2_sim* s);
+
+/* psi = prod_i (cos(theta_i/2)|0> + e^{i phi_i} sin(theta_i/2)|1>), the random
+ * product initial state of the Hamiltonian-quench example.  theta, phi: host,
+ * N doubles each.  Errors: SRE2_EINVAL (null or non-finite), SRE2_EHIP. */
+int sre2_sim_product_state(sre2_sim* s, const double* theta, const double* phi);
+
+/* Applies `count` two-qubit gates in order (the brickwork random-circuit
+ * example).  gates: host, count x 16 complex (row-major 4x4 U[i][j],
+ * interleaved re, im); the gate acts on the index j = bit(q0) + 2 bit(q1) of
+ * its pair.  pairs: host, count x 2 distinct qubits (q0, q1).
+ * Errors: SRE2_EINVAL (null, bad qubits), SRE2_EHIP. */
+int sre2_sim_apply_gates(sre2_sim* s, const double* gates, const int* pairs, int count);
+
+/* psi <- exp(-i H dt) psi for the TFIM with a longitudinal field on an open
+ * chain, H = -J sum_{i=0}^{N-2} Z_i Z_{i+1} - hx sum_i X_i - hz sum_i Z_i,
+ * by a Chebyshev expansion of the propagator cut below 1e-17 (FP64).
+ * Errors: SRE2_EINVAL (non-finite parameters), SRE2_EHIP. */
+int sre2_sim_tfim_step(sre2_sim* s, double J, double hx, double hz, double dt);
+
+/* Copies the current state to dst (device, 2^N values of dtype; complex64 is
+ * rounded from complex128) and waits for the simulator's stream. */
+int sre2_sim_state(sre2_sim* s, int dtype, void* dst);
+
+/* Snapshot pipelines: evolve `steps` steps and evaluate M2 (the server's
+ * form) of the state before the first step and after every step, each
+ * snapshot streamed to `srv` as a device input while the next step runs.
+ * results: host, (steps + 1) x SRE2_OUT_LEN doubles, snapshot t at 4 t.
+ * Blocks until every result is in.  The server must be owned by the caller
+ * and be on the simulator's device.
+ * Errors: SRE2_EINVAL, SRE2_ENOMEM, SRE2_EHIP, and any server error. */
+int sre2_sim_run_tfim(sre2_sim* s, sre2_server* srv, double J, double hx, double hz, double dt,
+                      int steps, int dtype, double* results);
+/* gates: host, steps x gates_per_step x 16 complex (step t uses block t - 1);
+ * pairs: host, gates_per_step x 2, the same bonds every step. */
+int sre2_sim_run_circuit(sre2_sim* s, sre2_server* srv, const double* gates, const int* pairs,
+                         int gates_per_step, int steps, int dtype, double* results);
+
 #ifdef __cplusplus
 }
 #endif

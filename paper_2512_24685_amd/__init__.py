@@ -77,6 +77,17 @@ def lib():
         "sre2_server_drain": ([vp, ctypes.c_double], c_int),
         "sre2_server_stats": ([vp, ctypes.POINTER(i64), c_int], c_int),
         "sre2_server_destroy": ([vp], c_int),
+        "sre2_sim_create": ([ctypes.POINTER(vp), c_int, c_int], c_int),
+        "sre2_sim_destroy": ([vp], c_int),
+        "sre2_sim_product_state": ([vp, dp, dp], c_int),
+        "sre2_sim_apply_gates": ([vp, dp, ctypes.POINTER(c_int), c_int], c_int),
+        "sre2_sim_tfim_step": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double], c_int),
+        "sre2_sim_state": ([vp, c_int, vp], c_int),
+        "sre2_sim_run_tfim": ([vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, c_int, c_int, dp], c_int),
+        "sre2_sim_run_circuit": ([vp, vp, dp, ctypes.POINTER(c_int), c_int, c_int, c_int, dp],
+                                 c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -371,6 +382,105 @@ class Server:
             rc = lib().sre2_server_destroy(self._p)
             self._p = ctypes.c_void_p()
             _check(rc, "sre2_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _f64(a):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _gates_arg(gates):
+    """complex (..., 4, 4) -> interleaved float64 buffer."""
+    import numpy as np
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.complex128))
+    return _f64(g.view(np.float64).reshape(-1))
+
+
+def _pairs_arg(pairs):
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    return p, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), p.size // 2
+
+
+class Simulator:
+    """Quench-dynamics state-vector simulator (sre2_sim_* in include/sre2.h):
+    a complex128 state of N qubits on one device, qubit i = bit i."""
+
+    def __init__(self, N: int, device: int = 0):
+        self._p = ctypes.c_void_p()
+        _check(lib().sre2_sim_create(ctypes.byref(self._p), int(device), int(N)),
+               "sre2_sim_create")
+        self.N = int(N)
+        self.device = int(device)
+
+    def product_state(self, theta, phi):
+        th, thp = _f64(theta)
+        ph, php = _f64(phi)
+        if th.size != self.N or ph.size != self.N:
+            raise ValueError("theta and phi need N entries")
+        _check(lib().sre2_sim_product_state(self._p, thp, php), "sre2_sim_product_state")
+
+    def apply_gates(self, gates, pairs):
+        """gates: (count, 4, 4) complex; pairs: (count, 2) qubits."""
+        g, gp = _gates_arg(gates)
+        p, pp, cnt = _pairs_arg(pairs)
+        if g.size != 32 * cnt:
+            raise ValueError("one 4x4 gate per pair")
+        _check(lib().sre2_sim_apply_gates(self._p, gp, pp, cnt), "sre2_sim_apply_gates")
+
+    def tfim_step(self, J: float, hx: float, hz: float, dt: float):
+        _check(lib().sre2_sim_tfim_step(self._p, J, hx, hz, dt), "sre2_sim_tfim_step")
+
+    def state(self, dtype=None):
+        """The current state as a new torch tensor (complex128 by default)."""
+        torch = _torch()
+        dtype = dtype or torch.complex128
+        out = torch.empty(1 << self.N, dtype=dtype, device=f"cuda:{self.device}")
+        _check(lib().sre2_sim_state(self._p, _dtype_code(out), ctypes.c_void_p(out.data_ptr())),
+               "sre2_sim_state")
+        return out
+
+    def _results(self, buf, steps):
+        return [Result(m2=buf[4 * t], S=buf[4 * t + 1], n=buf[4 * t + 2],
+                       status=int(buf[4 * t + 3])) for t in range(steps + 1)]
+
+    def run_tfim(self, server: "Server", J: float, hx: float, hz: float, dt: float,
+                 steps: int, dtype: str = "complex64") -> list:
+        """M2 of the state now and after each of `steps` TFIM steps, the
+        snapshots streamed into `server` while the evolution goes on."""
+        buf = (ctypes.c_double * (OUT_LEN * (steps + 1)))()
+        _check(lib().sre2_sim_run_tfim(self._p, server._p, J, hx, hz, dt, int(steps),
+                                       C64 if dtype == "complex64" else C128, buf),
+               "sre2_sim_run_tfim")
+        return self._results(buf, steps)
+
+    def run_circuit(self, server: "Server", gates, pairs, dtype: str = "complex64") -> list:
+        """gates: (steps, gates_per_step, 4, 4) complex; pairs: the bonds of a step."""
+        import numpy as np
+        gates = np.asarray(gates)
+        steps = int(gates.shape[0])
+        g, gp = _gates_arg(gates)
+        p, pp, cnt = _pairs_arg(pairs)
+        if g.size != 32 * cnt * steps:
+            raise ValueError("gates must be (steps, len(pairs), 4, 4)")
+        buf = (ctypes.c_double * (OUT_LEN * (steps + 1)))()
+        _check(lib().sre2_sim_run_circuit(self._p, server._p, gp, pp, cnt, steps,
+                                          C64 if dtype == "complex64" else C128, buf),
+               "sre2_sim_run_circuit")
+        return self._results(buf, steps)
+
+    def close(self):
+        if self._p:
+            rc = lib().sre2_sim_destroy(self._p)
+            self._p = ctypes.c_void_p()
+            _check(rc, "sre2_sim_destroy")
 
     def __del__(self):
         try:

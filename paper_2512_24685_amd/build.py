@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsre2.so")
-SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip"]
+SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -25,7 +25,7 @@ HIP_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     objs = []
     procs = []
     for src in SOURCES:

@@ -132,3 +132,18 @@ def test_server_argument_validation(L):
     assert L.sre2_server_drain(None, 1.0) == sre2.EINVAL
     assert L.sre2_server_stats(None, None, 0) == sre2.EINVAL
     assert L.sre2_server_destroy(None) == sre2.OK
+
+
+def test_sim_argument_validation(L):
+    p = ctypes.c_void_p()
+    assert L.sre2_sim_create(None, 0, 8) == sre2.EINVAL
+    assert L.sre2_sim_create(ctypes.byref(p), -1, 8) == sre2.EINVAL
+    assert L.sre2_sim_create(ctypes.byref(p), 0, 1) == sre2.EINVAL
+    assert L.sre2_sim_create(ctypes.byref(p), 0, 27) == sre2.EINVAL
+    assert L.sre2_sim_destroy(None) == sre2.OK
+    assert L.sre2_sim_product_state(None, None, None) == sre2.EINVAL
+    assert L.sre2_sim_apply_gates(None, None, None, 0) == sre2.EINVAL
+    assert L.sre2_sim_tfim_step(None, 1.0, 1.0, 1.0, 0.1) == sre2.EINVAL
+    assert L.sre2_sim_state(None, 0, FAKE) == sre2.EINVAL
+    assert L.sre2_sim_run_tfim(None, FAKE, 1.0, 1.0, 1.0, 0.1, 3, 0, None) == sre2.EINVAL
+    assert L.sre2_sim_run_circuit(None, FAKE, None, None, 0, 3, 0, None) == sre2.EINVAL
