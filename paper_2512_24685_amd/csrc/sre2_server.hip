@@ -311,7 +311,9 @@ struct sre2_server {
                 stat[SRE2_SERVER_STAT_PACKED_STATES] += counts[1];
                 stat[SRE2_SERVER_STAT_SINGLES] += counts[2];
             }
-            const bool done_any = retire(fl_small) | retire(fl_large);
+            const bool done_small = retire(fl_small);  // retire both lists
+            const bool done_large = retire(fl_large);
+            const bool done_any = done_small || done_large;
             stat[SRE2_SERVER_STAT_PEAK_BYTES] = (int64_t)arena.peak();
             if (done_any) cv.notify_all();
             const bool busy = !fl_small.empty() || !fl_large.empty();
