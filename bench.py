@@ -38,8 +38,6 @@ KERNEL_SOURCES = ["paper_2512_24685_amd/csrc/sre2_kernels.hip",
                   "paper_2512_24685_amd/csrc/sre2_geometry.h",
                   "paper_2512_24685_amd/csrc/sre2_plan.h"]
 
-# Geometry of the two-pass kernels (must match sre2_geometry.h defaults).
-ROW_BITS = {"fp32": 12, "fp64": 11}
 
 
 def log(*a):
@@ -64,12 +62,14 @@ def alg_units(N: int, form: str, kind: str, cs: int):
     over the L row bits; pass 2 = 2 per stage over the remaining bits + 5
     (|W|^2, square in FP64, FP64 add); Hermitian pass 2: + 1 (two squares).
     """
+    import paper_2512_24685_amd as sre2
+
     base = "fp64" if form.startswith("fp64") else "fp32"
     herm = form.endswith("h")
     ns = N - (1 if herm else 0)
     vals = cs * (1 << ns)
     eb = 8 if base == "fp32" else 16
-    L = ROW_BITS[base]
+    L = sre2.row_bits(N, form)
     if kind == "pass1":
         return eb * vals, (4 + 2 * L) * vals
     if kind == "pass2":

@@ -204,6 +204,12 @@ int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches);
  * shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups);
 
+/* Row bits L of pass 1 for (N, form): the slab of NS = N bits (N - 1 in the
+ * Hermitian-pair forms) is transformed as 2^(NS - L) rows of 2^L values, then
+ * by columns; 0 when N is evaluated by the fused kernel, -1 for invalid
+ * arguments. */
+int sre2_row_bits(int N, int form);
+
 /* ---- serving loop (continuous batching) ------------------------------- */
 /* A server owns a worker thread, two HIP streams, a device arena of
  * hbm_budget_bytes and max_slots request slots.  Requests are admitted in FIFO

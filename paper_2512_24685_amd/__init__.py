@@ -69,6 +69,7 @@ def lib():
         "sre2_set_timing": ([vp, c_int], c_int),
         "sre2_timing_read": ([vp, dp, ctypes.POINTER(i64)], c_int),
         "sre2_chunking": ([vp, c_int, c_int, ctypes.POINTER(i64), ctypes.POINTER(c_int)], c_int),
+        "sre2_row_bits": ([c_int, c_int], c_int),
         "sre2_server_create": ([ctypes.POINTER(vp), c_int, c_int, sz, c_int], c_int),
         "sre2_server_submit": ([vp, vp, c_int, c_int, c_int, ctypes.POINTER(ctypes.c_uint64)],
                                c_int),
@@ -103,6 +104,14 @@ def header_functions() -> list[str]:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sre2_[a-z0-9_]+)\s*\(", text)))
+
+
+def row_bits(N: int, form: str = "fp32") -> int:
+    """Pass-1 row bits for (N, form); 0 for the fused range."""
+    v = lib().sre2_row_bits(int(N), FORMS[form])
+    if v < 0:
+        raise SRE2Error(EINVAL, "sre2_row_bits")
+    return v
 
 
 def strerror(code: int) -> str:

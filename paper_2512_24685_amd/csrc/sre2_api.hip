@@ -78,7 +78,10 @@ int elem_bytes(int dtype) { return dtype == SRE2_C64 ? 8 : 16; }
 int work_dtype(int form) { return is_f64(form) ? kC128 : kC64; }
 
 int fused_max(int form) { return is_f64(form) ? fused_max_n<double>() : fused_max_n<float>(); }
-int row_bits(int form) { return is_f64(form) ? pass1_row_bits<double>() : pass1_row_bits<float>(); }
+// pass-1 row bits of a slab of NS bits
+int row_bits(int form, int NS) {
+    return is_f64(form) ? pass1_row_bits<double>(NS) : pass1_row_bits<float>(NS);
+}
 int herm_min(int form) { return is_f64(form) ? herm_min_n<double>() : herm_min_n<float>(); }
 int64_t col_tiles(int N, int form, bool herm) {
     return is_f64(form) ? pass2_col_tiles<double>(N, herm) : pass2_col_tiles<float>(N, herm);
@@ -93,7 +96,7 @@ struct Chunking {
 Chunking chunking(int N, int form, bool herm, int64_t x_count, size_t limit) {
     Chunking c;
     if (N <= fused_max(form)) return c;
-    const int L = row_bits(form);
+    const int L = row_bits(form, N - (herm ? 1 : 0));
     const size_t slab = (size_t(1) << (N - (herm ? 1 : 0))) * (size_t)elem_bytes(work_dtype(form));
     int64_t cs = 1;
     while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << L))
@@ -233,7 +236,8 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
         return SRE2_OK;
     }
     const bool herm = is_herm(form);
-    const int64_t lim = int64_t(1) << row_bits(form);
+    // Hermitian-pair two-pass needs x >= 2^L of its own (N - 1)-bit slab
+    const int64_t lim = int64_t(1) << row_bits(form, N - 1);
     const int64_t split = herm ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
     // workspace for the larger of the two chunk shapes
     size_t need = 0, need_part = 0;
@@ -478,6 +482,13 @@ int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes) {
     if (!ctx) return SRE2_EINVAL;
     ctx->scratch_limit = bytes;
     return SRE2_OK;
+}
+
+int sre2_row_bits(int N, int form) {
+    if (N < 1 || N > SRE2_MAX_N || !form_ok(form)) return -1;
+    if (N > (is_f64(form) ? max_n<double>() : max_n<float>())) return -1;
+    if (N <= fused_max(form)) return 0;
+    return row_bits(form, N - (is_herm(form) ? 1 : 0));
 }
 
 size_t sre2_workspace_bytes(int N, int dtype, int form) {

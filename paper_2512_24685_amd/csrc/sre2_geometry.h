@@ -13,7 +13,10 @@ constexpr int kMaxNAll = 26;
 //   RB_*        log2 of complex values per thread
 //   FUSED_MIN   smallest fused tile (tiles of smaller N hold several shifts)
 //   FUSED_MAX   largest N evaluated by the fused kernel
-//   ROW         row bits L of pass 1 (its tile is exactly one row)
+//   ROW         smallest row bits L of pass 1 (its tile is exactly one row)
+//   P2_ROWS     largest number of row bits H = NS - L left to pass 2 while L
+//               can still grow (up to the largest tile): with H <= P2_ROWS a
+//               pass-2 tile holds at least 128 contiguous bytes of every row
 //   P2_MIN      smallest pass-2 tile; a pass-2 tile holds all 2^H rows and at
 //               least 16 consecutive columns when the LDS allows it
 // ---------------------------------------------------------------------------
@@ -37,6 +40,9 @@ constexpr int kMaxNAll = 26;
 #endif
 #ifndef SRE2_F32_P2_MIN
 #define SRE2_F32_P2_MIN 12
+#endif
+#ifndef SRE2_P2_ROWS
+#define SRE2_P2_ROWS 10
 #endif
 #ifndef SRE2_F64_RB_FUSED
 #define SRE2_F64_RB_FUSED 4
@@ -72,6 +78,19 @@ template <> struct Tune<double> {
     static constexpr int RB1 = SRE2_F64_RB1, RB2 = SRE2_F64_RB2, P2MIN = SRE2_F64_P2_MIN;
 };
 
+// Row bits of pass 1 for a slab of NS bits (NS = N, or N - 1 in the
+// Hermitian-pair forms): ROW, grown so that pass 2 keeps at most P2_ROWS row
+// bits, up to the largest tile.  Longer rows cost pass 1 some occupancy but
+// keep pass 2's column reads in full 128-byte segments, which pays from
+// NS = 23 (FP32) / 22 (FP64) on.
+template <typename Real>
+constexpr int row_bits_of(int NS) {
+    int L = NS - SRE2_P2_ROWS;
+    if (L < Tune<Real>::ROW) L = Tune<Real>::ROW;
+    if (L > Prec<Real>::MAXTB) L = Prec<Real>::MAXTB;
+    return L;
+}
+
 template <typename Real>
 constexpr int fused_tb(int N) {
     return N > Tune<Real>::FMIN ? N : Tune<Real>::FMIN;
@@ -96,14 +115,25 @@ constexpr int max_n_of() {
     return kMaxNAll < Tune<Real>::ROW + Prec<Real>::MAXTB ? kMaxNAll : Tune<Real>::ROW + Prec<Real>::MAXTB;
 }
 
-// A pass-2 tile reads whole columns inside one row of pass 1's output.
+// A pass-2 tile reads whole columns inside one row of pass 1's output, and
+// every slab size above the fused range splits into valid rows and columns.
 template <typename Real>
 constexpr bool pass2_tiles_fit() {
-    for (int H = 1; H <= max_n_of<Real>() - Tune<Real>::ROW; ++H) {
+    for (int NS = Tune<Real>::FMAX; NS <= max_n_of<Real>(); ++NS) {
+        const int L = row_bits_of<Real>(NS), H = NS - L;
+        if (H < 1 || L < Tune<Real>::RB1 + 6 || L > Prec<Real>::MAXTB) return false;
         const int tb = pass2_tb<Real>(H);
-        if (tb < H || tb - H > Tune<Real>::ROW || tb > Prec<Real>::MAXTB) return false;
+        if (tb < H || tb - H > L || tb > Prec<Real>::MAXTB) return false;
     }
     return true;
+}
+// Largest pass-2 row count over all slab sizes.
+template <typename Real>
+constexpr int pass2_max_rows() {
+    int h = 0;
+    for (int NS = Tune<Real>::FMAX; NS <= max_n_of<Real>(); ++NS)
+        if (NS - row_bits_of<Real>(NS) > h) h = NS - row_bits_of<Real>(NS);
+    return h;
 }
 static_assert(pass2_tiles_fit<float>() && pass2_tiles_fit<double>());
 

@@ -63,12 +63,13 @@ struct Spec {
 };
 
 // Geometry queries.  Two-pass is used for N > fused_max_n; pass 1 transforms
-// the low L = pass1_row_bits bits.  The Hermitian-pair forms need
+// the low L = pass1_row_bits(NS) bits of a slab of NS bits (NS = N, or N - 1
+// in the Hermitian-pair forms).  The Hermitian-pair forms need
 // N >= herm_min_n (fused) and shifts x >= 1 (fused) or x >= 2^L (two-pass);
 // other shifts go through the plain kernels.
 template <typename Real> int max_n();
 template <typename Real> int fused_max_n();
-template <typename Real> int pass1_row_bits();
+template <typename Real> int pass1_row_bits(int NS);
 template <typename Real> int herm_min_n();
 // Column tiles per shift in pass 2 (upper bound of the column groups P).
 template <typename Real> int64_t pass2_col_tiles(int N, bool herm);

@@ -115,10 +115,11 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #define SRE2_SPLIT_P1_TAIL 1  // split-form pass 1 ends in a store-layout round
 #endif
 // Minimum waves per SIMD asked of the compiler (register budget 512 / waves).
-// Split-form pass 1 keeps its MFMA results in VGPRs at 3 (with fewer, the
-// compiler moves them through AGPRs, which costs it about half its speed);
-// LDS limits every TB = 12 kernel to 2.5 waves per SIMD anyway.  Split-form
-// pass 2 cannot reach 3 without spilling and is left alone.
+// Split-form pass 1 on 2^12 rows keeps its MFMA results in VGPRs at 3 (with
+// fewer, the compiler moves them through AGPRs, which costs it about half its
+// speed); LDS limits every TB = 12 kernel to 2.5 waves per SIMD anyway, and
+// longer rows to 2.  Split-form pass 2 cannot reach 3 without spilling and is
+// left alone.
 #ifndef SRE2_P1_WAVES
 #define SRE2_P1_WAVES 1
 #endif
@@ -536,7 +537,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // ---------------------------------------------------------------------------
 template <typename Real, int TB, int RB, bool HERM, bool SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P1S_WAVES : SRE2_P1_WAVES)))
+__attribute__((amdgpu_waves_per_eu(SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES)))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
@@ -875,8 +876,8 @@ int fused_max_n() {
     return Tune<Real>::FMAX;
 }
 template <typename Real>
-int pass1_row_bits() {
-    return Tune<Real>::ROW;
+int pass1_row_bits(int NS) {
+    return row_bits_of<Real>(NS);
 }
 template <typename Real>
 int herm_min_n() {
@@ -885,7 +886,7 @@ int herm_min_n() {
 template <typename Real>
 int64_t pass2_col_tiles(int N, bool herm) {
     const int NS = N - (herm ? 1 : 0);
-    const int HT = NS - Tune<Real>::ROW;
+    const int HT = NS - row_bits_of<Real>(NS);
     const int tb = pass2_tb_rt<Real>(HT, std::make_integer_sequence<int, Prec<Real>::MAXTB>{});
     return tb > 0 ? (int64_t)1 << (NS - tb) : 0;
 }
@@ -893,8 +894,8 @@ template int max_n<float>();
 template int max_n<double>();
 template int fused_max_n<float>();
 template int fused_max_n<double>();
-template int pass1_row_bits<float>();
-template int pass1_row_bits<double>();
+template int pass1_row_bits<float>(int);
+template int pass1_row_bits<double>(int);
 template int herm_min_n<float>();
 template int herm_min_n<double>();
 template int64_t pass2_col_tiles<float>(int, bool);
@@ -939,15 +940,11 @@ hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, in
     return shift_kernel_gen<Real, false>(psi, N, herm, split, x0, xc, S, se, pk, Spec{}, st);
 }
 
-template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
-                        void* scratch, const int* se, hipStream_t st) {
+template <typename Real, int TB>
+hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, bool split, int64_t x0, int cs,
+                           void* scratch, const int* se, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = Tune<Real>::ROW, RB = Tune<Real>::RB1;
-    if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
-    if (herm && x0 < ((int64_t)1 << TB)) return hipErrorInvalidValue;
-    const int NS = N - (herm ? 1 : 0);
+    constexpr int RB = Tune<Real>::RB1;
     const int64_t rows = (int64_t)1 << (NS - TB);
     const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB));
     if (herm)
@@ -963,14 +960,41 @@ hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x
     return hipGetLastError();
 }
 
+template <typename Real, int... Ls>
+hipError_t dispatch_pass1(int L, const void* psi, int NS, bool herm, bool split, int64_t x0,
+                          int cs, void* scratch, const int* se, hipStream_t st,
+                          std::integer_sequence<int, Ls...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((L == Tune<Real>::ROW + Ls
+          ? (e = launch_pass1_tb<Real, Tune<Real>::ROW + Ls>(psi, NS, herm, split, x0, cs, scratch,
+                                                             se, st),
+             0)
+          : 0),
+     ...);
+    return e;
+}
+
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
-                        double* part, const int* se, const Spec* sp, hipStream_t st) {
-    constexpr int ROW = Tune<Real>::ROW;
+hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
+                        void* scratch, const int* se, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
     if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
-    constexpr int HMAX = max_n_of<Real>() - ROW;
+    const int L = row_bits_of<Real>(NS);
+    if (herm && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
+    return dispatch_pass1<Real>(
+        L, psi, NS, herm, split, x0, cs, scratch, se, st,
+        std::make_integer_sequence<int, Prec<Real>::MAXTB - Tune<Real>::ROW + 1>{});
+}
+
+template <typename Real>
+hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
+                        double* part, const int* se, const Spec* sp, hipStream_t st) {
+    if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
+    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
+    const int NS = N - (herm ? 1 : 0);
+    const int ROW = row_bits_of<Real>(NS);  // this slab's pass-1 row bits
+    constexpr int HMAX = pass2_max_rows<Real>();
     if (sp) {
         if (split || sp->kind < kRedPow || sp->kind > kRedHist ||
             (sp->kind == kRedHist && (!sp->hist || !sp->nrm || sp->nbins < 2 ||

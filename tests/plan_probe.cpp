@@ -16,16 +16,16 @@ int geometry(int kind, int param, int* tb, int* rb, int* sb) {
             *tb = sre2::fused_tb<Real>(param);
             *rb = T::RBF;
             return 0;
-        case 1:  // pass 1
-            *tb = T::ROW;
+        case 1:  // pass 1, param = slab bits NS (0: the smallest row)
+            *tb = param ? sre2::row_bits_of<Real>(param) : T::ROW;
             *rb = T::RB1;
             return 0;
         case 2:  // pass 2, param = H
-            if (param < 1 || param > sre2::max_n_of<Real>() - T::ROW) return -1;
+            if (param < 1 || param > sre2::pass2_max_rows<Real>()) return -1;
             *tb = sre2::pass2_tb<Real>(param);
             *rb = T::RB2;
             return 0;
-        case 3:  // limits: tb = largest fused N, rb = row bits, sb = largest N
+        case 3:  // limits: tb = largest fused N, rb = smallest row bits, sb = largest N
             *tb = T::FMAX;
             *rb = T::ROW;
             *sb = sre2::max_n_of<Real>();

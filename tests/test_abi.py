@@ -147,3 +147,14 @@ def test_sim_argument_validation(L):
     assert L.sre2_sim_state(None, 0, FAKE) == sre2.EINVAL
     assert L.sre2_sim_run_tfim(None, FAKE, 1.0, 1.0, 1.0, 0.1, 3, 0, None) == sre2.EINVAL
     assert L.sre2_sim_run_circuit(None, FAKE, None, None, 0, 3, 0, None) == sre2.EINVAL
+
+
+def test_row_bits_query(L):
+    f = sre2.FORMS
+    assert L.sre2_row_bits(14, f["fp32"]) == 0  # fused
+    assert L.sre2_row_bits(20, f["fp32"]) == 12
+    assert L.sre2_row_bits(23, f["fp32"]) == 13 and L.sre2_row_bits(24, f["fp32"]) == 14
+    assert L.sre2_row_bits(24, f["fp32h"]) == 13  # slab of N - 1 bits
+    assert L.sre2_row_bits(22, f["fp64"]) == 12 and L.sre2_row_bits(24, f["fp64"]) == 13
+    assert L.sre2_row_bits(0, f["fp32"]) == -1 and L.sre2_row_bits(20, 99) == -1
+    assert L.sre2_row_bits(25, f["fp64"]) == -1  # beyond the FP64 maximum

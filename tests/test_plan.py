@@ -37,8 +37,9 @@ FUSED, PASS1, PASS2, LIMITS = 0, 1, 2, 3
 
 
 def geo(lib, precision, kind, param=0):
-    """(TB, RB, SB) of a kernel: fused(N), pass1, pass2(H); LIMITS gives
-    (largest fused N, pass-1 row bits, largest N)."""
+    """(TB, RB, SB) of a kernel: fused(N), pass1(NS: slab bits; 0 = the
+    smallest row), pass2(H); LIMITS gives (largest fused N, smallest pass-1
+    row bits, largest N)."""
     tb, rb, sb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     rc = lib.probe_geometry(precision, kind, param, ctypes.byref(tb), ctypes.byref(rb),
                             ctypes.byref(sb))
@@ -102,20 +103,21 @@ def mf_apply(V, a):
     """H_16 on every register group as the matrix cores compute it: for each
     setting q of the register-index bits other than a, a + 1, lane 16g + c
     supplies rows 4g + j (j = register-index bits a, a + 1) of column c and
-    receives rows 4g + r of the product in the same registers."""
+    receives rows 4g + r of the product in the same registers.  V is
+    (..., threads, registers)."""
     V = V.copy()
-    T, R = V.shape
+    T, R = V.shape[-2:]
     lanes = np.arange(64)
     g, c = lanes >> 4, lanes & 15
     for w in range(0, T, 64):
         for q in range(R // 4):
             b = (q & ((1 << a) - 1)) | ((q >> a) << (a + 2))
-            B = np.zeros((16, 16), dtype=V.dtype)
+            B = np.zeros(V.shape[:-2] + (16, 16), dtype=V.dtype)
             for j in range(4):
-                B[4 * g + j, c] = V[w + lanes, b + (j << a)]
+                B[..., 4 * g + j, c] = V[..., w + lanes, b + (j << a)]
             D = H16 @ B
             for r in range(4):
-                V[w + lanes, b + (r << a)] = D[4 * g + r, c]
+                V[..., w + lanes, b + (r << a)] = D[..., 4 * g + r, c]
     return V
 
 
@@ -125,28 +127,30 @@ def round_math(V, rd):
 
 
 def bfly(V, reg, bf):
+    """Butterflies on register bits; V is (..., threads, registers)."""
     V = V.copy()
     for b in range(32):
         if (bf >> b) & 1:
             rbit = bin(reg & ((1 << b) - 1)).count("1")
-            i = np.arange(V.shape[1])
+            i = np.arange(V.shape[-1])
             lo = i[((i >> rbit) & 1) == 0]
             hi = lo | (1 << rbit)
-            a, c = V[:, lo].copy(), V[:, hi].copy()
-            V[:, lo], V[:, hi] = a + c, a - c
+            a, c = V[..., lo].copy(), V[..., hi].copy()
+            V[..., lo], V[..., hi] = a + c, a - c
     return V
 
 
 def run_tile(X, rounds, tb, rb, sb):
-    """Replay one tile through the plan; returns the tile after the transform."""
+    """Replay tiles through the plan; X is (..., 2^tb), one tile per leading
+    index; returns the tiles after the transform."""
     E = [mapping(rd, tb, rb) for rd in rounds]
-    V = round_math(X[E[0]], rounds[0])
+    V = round_math(X[..., E[0]], rounds[0])
     for j in range(1, len(rounds)):
-        lds = np.full(1 << tb, np.nan + 0j)
-        lds[swz_np(sb, E[j - 1])] = V
-        V = round_math(lds[swz_np(sb, E[j])], rounds[j])
+        lds = np.full(X.shape[:-1] + (1 << tb,), np.nan + 0j)
+        lds[..., swz_np(sb, E[j - 1])] = V
+        V = round_math(lds[..., swz_np(sb, E[j])], rounds[j])
     out = np.empty_like(X)
-    out[E[-1]] = V
+    out[..., E[-1]] = V
     return out
 
 
@@ -180,10 +184,16 @@ def all_plans(lib):
             for N in range(rbf, fmax + 1):
                 tb, rb, sb = geo(lib, prec, FUSED, N)
                 yield prec, "fused", N, (tb, rb, sb, 0, N, 3 * split)
-            tb, rb, sb = geo(lib, prec, PASS1)
-            assert tb == row
-            yield prec, "pass1", tb, (tb, rb, sb, 0, tb, 2 * split)
-            for H in range(1, nmax - row + 1):
+            assert geo(lib, prec, PASS1)[0] == row
+            rows, hs = set(), set()
+            for NS in range(fmax, nmax + 1):  # every slab size of two-pass
+                L = geo(lib, prec, PASS1, NS)[0]
+                rows.add(L)
+                hs.add(NS - L)
+            _, rb1, sb = geo(lib, prec, PASS1)
+            for L in sorted(rows):
+                yield prec, "pass1", L, (L, rb1, sb, 0, L, 2 * split)
+            for H in sorted(hs):
                 tb, rb, sb = geo(lib, prec, PASS2, H)
                 yield prec, "pass2", H, (tb, rb, sb, tb - H, tb, split)
 
@@ -192,9 +202,16 @@ def test_geometry_limits(probe):
     for prec in (0, 1):
         fmax, row, nmax = geo(probe, prec, LIMITS)
         assert row <= fmax < nmax and nmax >= 24
-        for H in range(1, nmax - row + 1):
+        for NS in range(fmax, nmax + 1):
+            L, rb1, _ = geo(probe, prec, PASS1, NS)
+            H = NS - L
+            assert L >= row and L - rb1 >= 6
             tb, rb, _ = geo(probe, prec, PASS2, H)
-            assert H <= tb and tb - H <= row and tb - rb >= 6
+            assert H <= tb and tb - H <= L and tb - rb >= 6
+            # rows grow until pass 2 keeps <= 10 row bits or the tile is full
+            assert H <= 10 or L == (14 if prec == 0 else 13)
+            if H <= 10 and L > row:
+                assert H == 10
         for N in range(geo(probe, prec, FUSED, fmax)[1], fmax + 1):
             tb, rb, _ = geo(probe, prec, FUSED, N)
             assert tb >= N and tb - rb >= 6
@@ -318,11 +335,13 @@ def emulate_fused_partials(probe, psi, prec, herm=False, x_begin=0, split=0):
     return np.array([S[x] for x in range(x_begin, d)])
 
 
-def emulate_two_pass_partials(probe, psi, prec, xs, herm=False, split=0):
-    """Per-shift sums as k_pass1 / k_pass2 index them (row slab, then columns)."""
+def emulate_two_pass_partials(probe, psi, prec, xs, herm=False, split=0, L=None):
+    """Per-shift sums as k_pass1 / k_pass2 index them (row slab, then columns);
+    L overrides the slab's pass-1 row bits (the kernels are generic in it)."""
     N = psi.size.bit_length() - 1
     NS = N - int(herm)
-    L, rb1, sb = geo(probe, prec, PASS1)
+    L0, rb1, sb = geo(probe, prec, PASS1, NS)
+    L = L0 if L is None else L
     HT = NS - L
     tb2, rb2, _ = geo(probe, prec, PASS2, HT)
     p1 = plan(probe, L, rb1, sb, 0, L, 2 * split)
@@ -330,21 +349,18 @@ def emulate_two_pass_partials(probe, psi, prec, xs, herm=False, split=0):
     e1 = np.arange(1 << L)
     e2 = np.arange(1 << tb2)
     cb = tb2 - HT
+    srows = np.arange(1 << HT)
     out = []
     for x in xs:
         assert not herm or x >= (1 << L)
-        slab = np.empty(1 << NS, dtype=np.complex128)
-        for srow in range(1 << HT):
-            row = insert0(srow, x.bit_length() - 1 - L) if herm else srow
-            rowbase = row << L
-            prow = rowbase ^ (x & ~((1 << L) - 1))
-            X = np.conj(psi[prow + (e1 ^ (x & ((1 << L) - 1)))]) * psi[rowbase + e1]
-            slab[srow << L:(srow + 1) << L] = run_tile(X, p1, L, rb1, sb)
-        acc = 0.0
-        for ct in range(1 << (L - cb)):
-            src = (e2 >> cb << L) + (ct << cb) + (e2 & ((1 << cb) - 1))
-            acc += reduce4(run_tile(slab[src], p2, tb2, rb2, sb), herm)
-        out.append(acc)
+        rows = insert0(srows, x.bit_length() - 1 - L) if herm else srows
+        rowbase = (rows << L)[:, None]
+        prow = rowbase ^ (x & ~((1 << L) - 1))
+        X = np.conj(psi[prow + (e1 ^ (x & ((1 << L) - 1)))[None, :]]) * psi[rowbase + e1[None, :]]
+        slab = run_tile(X, p1, L, rb1, sb).reshape(-1)  # all rows at once
+        cts = np.arange(1 << (L - cb))[:, None]
+        src = (e2 >> cb << L)[None, :] + (cts << cb) + (e2 & ((1 << cb) - 1))[None, :]
+        out.append(reduce4(run_tile(slab[src], p2, tb2, rb2, sb), herm))
     return np.array(out)
 
 
@@ -374,3 +390,20 @@ def test_two_pass_indexing_matches_oracle(probe, oracle_mod, prec, extra, herm, 
     S = emulate_two_pass_partials(probe, psi, prec, xs, herm, split)
     ref = oracle_mod.partials(psi, xs)
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("prec,L,herm,split", [(0, 13, False, 0), (0, 14, False, 0),
+                                               (0, 14, True, 0), (0, 13, False, 1),
+                                               (0, 14, False, 1), (1, 12, False, 0),
+                                               (1, 13, True, 0)])
+def test_two_pass_long_rows_match_oracle(probe, oracle_mod, prec, L, herm, split):
+    """Pass-1 rows longer than the smallest row (taken by large slabs), on a
+    small slab: every row and column tile of the longer-row kernels."""
+    _, row, nmax = geo(probe, prec, LIMITS)
+    assert L > row
+    assert any(geo(probe, prec, PASS1, NS)[0] == L for NS in range(row, nmax + 1))
+    N = L + 3 + int(herm)
+    psi = W.haar(N, 13 + L)
+    xs = [1 << L, (1 << N) - 1] if herm else [0, (1 << N) - 1 - 0x155, 1 << (N - 1)]
+    S = emulate_two_pass_partials(probe, psi, prec, xs, herm, split, L=L)
+    assert np.allclose(S, oracle_mod.partials(psi, xs), rtol=1e-11, atol=0)
