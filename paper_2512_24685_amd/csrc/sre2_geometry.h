@@ -33,7 +33,7 @@ constexpr int kMaxNAll = 26;
 #define SRE2_F32_ROW 12
 #endif
 #ifndef SRE2_F32_RB1
-#define SRE2_F32_RB1 5
+#define SRE2_F32_RB1 4
 #endif
 #ifndef SRE2_F32_RB2
 #define SRE2_F32_RB2 5
