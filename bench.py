@@ -221,6 +221,8 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
         r = sre2.m2(torch.from_numpy(psi).to("cuda:0"), form=form)
         base_lat.append(time.perf_counter() - (t0 + arrivals[i]))
         base_res.append(r)
+        if (i + 1) % 512 == 0:
+            log(f"serving: one-at-a-time {i + 1}/{count}")
     base_makespan = time.perf_counter() - t0
     log(f"serving: one-at-a-time done in {base_makespan:.1f} s")
 
@@ -244,6 +246,8 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
             time.sleep(0.0002)
         lag.append(time.perf_counter() - (t0 + arrivals[i]))
         tickets.append(srv.submit(psi))
+        if (i + 1) % 512 == 0:
+            log(f"serving: server {i + 1}/{count} submitted, {len(done)} done")
     while len(done) < count:
         poll_some()
         time.sleep(0.0002)
