@@ -370,6 +370,30 @@ __device__ __forceinline__ void run_transform(typename CT<Real>::T* lds,
     RoundRunner<Real, TB, RB, PK, 1>::run(lds, v, amat);
 }
 
+// Sum over a block of NT threads (NT a multiple of 64): a butterfly of
+// cross-lane exchanges inside each wave (XOR partners 32, 16, ..., 1, so every
+// lane ends with the same wave sum), then the wave sums, added in wave order
+// by thread 0 through LDS.  The order is fixed by NT alone.  The result is
+// valid in thread 0; `red` needs NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    static_assert(NT % 64 == 0, "whole waves");
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    constexpr int NW = NT / 64;
+    if constexpr (NW == 1) {
+        return v;
+    } else {
+        __syncthreads();  // earlier readers of red are done
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0.0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < NW; ++w) t += red[w];
+        return t;
+    }
+}
+
 // Fixed-shape tree over T doubles in LDS; segments of `seg` consecutive entries
 // are reduced independently (seg divides T, both powers of two).  Result of
 // segment j lands in red[j * seg].
@@ -639,9 +663,8 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
         if constexpr (HERM) acc *= 16.0;
         if constexpr (SPLIT) acc *= ldexp(1.0, -4 * *scale_exp);
     }
-    red[threadIdx.x] = acc;
-    seg_tree<T>(red, T);
-    if (threadIdx.x == 0) part[b] = red[0];
+    const double tot = block_sum<T>(acc, red);
+    if (threadIdx.x == 0) part[b] = tot;
     if constexpr (GEN) hist_flush(lh, sp);
 }
 
@@ -684,15 +707,11 @@ __global__ __launch_bounds__(kRedThreads) void k_norm_part(const C* __restrict__
         if (!isfinite(re) || !isfinite(im)) bad = 1;
         s += re * re + im * im;
     }
-    red[threadIdx.x] = s;
-    seg_tree<kRedThreads>(red, kRedThreads);
-    const double tot = red[0];
-    __syncthreads();
-    red[threadIdx.x] = bad ? 1.0 : 0.0;
-    seg_tree<kRedThreads>(red, kRedThreads);
+    const double tot = block_sum<kRedThreads>(s, red);
+    const double nbad = block_sum<kRedThreads>(bad ? 1.0 : 0.0, red);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = tot;
-        flag[blockIdx.x] = red[0];
+        flag[blockIdx.x] = nbad;
     }
 }
 
@@ -720,9 +739,8 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_part(const double* __restri
         if (Sx) Sx[x] = sx;
         s += sx;
     }
-    red[threadIdx.x] = s;
-    seg_tree<kRedThreads>(red, kRedThreads);
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    const double tot = block_sum<kRedThreads>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // Sx[s] = sum_p part[s*P + p] in p order (one thread per shift).
@@ -754,17 +772,9 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
         b += npart[i];
         c += nflag[i];
     }
-    red[threadIdx.x] = a;
-    seg_tree<kRedThreads>(red, kRedThreads);
-    const double S = red[0];
-    __syncthreads();
-    red[threadIdx.x] = b;
-    seg_tree<kRedThreads>(red, kRedThreads);
-    const double n = red[0];
-    __syncthreads();
-    red[threadIdx.x] = c;
-    seg_tree<kRedThreads>(red, kRedThreads);
-    const double bad = red[0];
+    const double S = block_sum<kRedThreads>(a, red);
+    const double n = block_sum<kRedThreads>(b, red);
+    const double bad = block_sum<kRedThreads>(c, red);
     if (threadIdx.x == 0) {
         const bool ok = bad == 0.0 && n > 0.0 && isfinite(n) && isfinite(S);
         const double n2 = n * n;
