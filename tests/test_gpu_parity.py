@@ -6,6 +6,9 @@ Tolerances (bars of the method's two precisions):
     over up to 26 stages; S_x = sum |W|^4 is dominated by the largest |W|,
     whose relative error is a few FP32 ulps times sqrt(N)).
 The oracle always receives the exact bytes the GPU receives, upcast to FP64.
+Sizes: every N from 1 to 16 in full; N = 20 (the benchmark state) in full
+against the stored oracle M2 and per-shift sums; N = 22 and 24 on stored
+sampled shifts; N = 26 (the largest FP32 slab) on one shift computed here.
 """
 import hashlib
 import json
@@ -208,7 +211,7 @@ def test_n20_full_size(oracle_mod, form):
     assert abs(rt.m2 - 10 * LOG43) <= closed_tol(form)
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "fp64", "fp64h"])
 @pytest.mark.parametrize("N", [22, 24])
 def test_large_n_sampled_shifts(N, form):
     g = _golden()
@@ -225,3 +228,32 @@ def test_large_n_sampled_shifts(N, form):
     for x in xs:
         got = sre2.shift_partials(d, x, 1, form=form).item()
         assert abs(got - ref[x]) <= TOL_SX[form] * ref[x], x
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+def test_max_n_sampled_shift(oracle_mod, form):
+    """The largest N of the FP32 forms (2^26 amplitudes, 512 MiB): one
+    shift's S_x against the oracle, computed here."""
+    N = sre2.MAX_N
+    psi = _max_n_state()
+    x = (1 << (N - 1)) + 0x2345
+    case_id("max-n", N, form)
+    got = sre2.shift_partials(dev(psi), x, 1, form=form).item()
+    ref = _max_n_ref(x)
+    assert abs(got - ref) <= TOL_SX[form] * ref
+
+
+_MAXN = {}
+
+
+def _max_n_state():
+    if "psi" not in _MAXN:
+        _MAXN["psi"] = W.haar(sre2.MAX_N, W.SEED_LARGE + 9, np.complex64)
+    return _MAXN["psi"]
+
+
+def _max_n_ref(x):
+    import oracle
+    if x not in _MAXN:
+        _MAXN[x] = float(oracle.partials(_max_n_state(), [x], threads=1)[0])
+    return _MAXN[x]
