@@ -277,6 +277,41 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
     }
 
 
+def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"), chunks=3):
+    """Large slabs: a few two-pass chunks of the full-evaluation launch shape
+    (shifts from x = 2^(N-1)) per (N, form), with each pass's algorithmic
+    HBM rate and its fraction of the 8 TB/s peak, and the full-evaluation
+    time this implies."""
+    out = {}
+    for N in Ns:
+        psi = torch.from_numpy(W.haar(N, W.SEED_LARGE + (0 if N == 22 else 1), np.complex64))
+        d = psi.to("cuda:0")
+        for form in forms:
+            ctx = sre2.Context(0)
+            cs, P = ctx.chunking(N, form)
+            x0 = 1 << (N - 1)
+            sre2.shift_partials(d, x0, cs, form=form, ctx=ctx)  # warm-up chunk
+            torch.cuda.synchronize()
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            sre2.shift_partials(d, x0 + cs, chunks * cs, form=form, ctx=ctx)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            kt = ctx.timing_read()
+            ctx.close()
+            by, _ = alg_units(N, form, "pass1", cs)
+            rec = {"shifts_per_chunk": cs, "row_bits": sre2.row_bits(N, form),
+                   "s_per_evaluation": dt / (chunks * cs) * (1 << N)}
+            for k in ("pass1", "pass2"):
+                ms, n = kt[k]
+                gbs = by / (ms / 1e3 / n) / 1e9
+                rec[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_GBs": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            out[f"N{N}_{form}"] = rec
+            log(f"large N={N} {form}: {rec}")
+    return out
+
+
 def dynamics_benchmark(sre2, torch, W, N: int, steps: int, form: str):
     """TFIM quench (the paper's first dynamics example) from a random product
     state: M2 after every step (a) through the snapshot pipeline, evolution
@@ -329,6 +364,7 @@ def main():
     ap.add_argument("--dynamics", type=int, default=20, metavar="STEPS",
                     help="TFIM quench steps of the snapshot-pipeline measurement (0: skip)")
     ap.add_argument("--dynamics-N", type=int, default=16)
+    ap.add_argument("--large", type=int, default=1, help="large-slab measurement (0: skip)")
     ap.add_argument("--profile-chunks", type=int, default=0, metavar="C",
                     help="run only C two-pass chunks (the benchmark's launch shape) from "
                          "x = 2^(N-1), for counter collection")
@@ -390,6 +426,7 @@ def main():
     serving = None
     if args.serving:
         serving = serving_benchmark(sre2, torch, W, args.serving, "fp32")
+    large = large_n_benchmark(sre2, torch, W) if args.large else None
     dynamics = None
     if args.dynamics:
         dynamics = dynamics_benchmark(sre2, torch, W, args.dynamics_N, args.dynamics, "fp32")
@@ -420,6 +457,7 @@ def main():
         "roofline": roof,
         "forms": forms,
         "serving": serving,
+        "large_n": large,
         "dynamics": dynamics,
         "cpu_baseline": cpu,
     }
