@@ -215,18 +215,33 @@ __device__ __forceinline__ uint32_t thread_base() {
     return b;
 }
 
+// LDS slot of register element i: swz(base | r) with r = pdep(i, REG).  The
+// swizzle is linear, and the bits of swz(r) at or above SB are tile bits of
+// REG, where swz(base) is zero, so swz(base) ^ swz(r) = (swz(base) ^ lo) + hi
+// with lo, hi the parts of swz(r) below and above bit SB: one XOR per
+// distinct lo, and hi becomes the instruction's constant offset.  Byte
+// offsets are formed once per thread.
+template <int SB, typename C>
+__device__ __forceinline__ C* lds_slot(C* lds, uint32_t pb_bytes, uint32_t r) {
+    const uint32_t e = swz<SB>(r);
+    const uint32_t lo = e & ((1u << SB) - 1u), hi = e & ~((1u << SB) - 1u);
+    return reinterpret_cast<C*>(reinterpret_cast<char*>(lds) + hi * (uint32_t)sizeof(C) +
+                                (pb_bytes ^ (lo * (uint32_t)sizeof(C))));
+}
+
 template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
 __device__ __forceinline__ void lds_put(C* lds, const C (&v)[1 << RB]) {
-    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>());
+    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))] = v[i];
+    for (int i = 0; i < (1 << RB); ++i) *lds_slot<SB>(lds, pb, pdep((uint32_t)i, REG)) = v[i];
 }
 
 template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
 __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
-    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>());
+    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) v[i] = lds[pb ^ swz<SB>(pdep((uint32_t)i, REG))];
+    for (int i = 0; i < (1 << RB); ++i)
+        v[i] = *lds_slot<SB>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
 }
 
 // Plan selector (PK encodes the kind so that plans stay constexpr):
@@ -584,11 +599,16 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     const C* __restrict__ pb = psi + prow;
     C v[1 << RB];
     {
+        // element e = base | r (disjoint bits): psi[e] = (pa + r)[base], and
+        // e ^ xlo = (base ^ (xlo outside REG)) + (r ^ (xlo inside REG)), so
+        // the per-element parts are uniform and the per-thread parts are
+        // formed once
         const uint32_t base = thread_base<r0.lperm, r0.wave>();
+        const uint32_t vb = base ^ (xlo & ~r0.reg), xr = xlo & r0.reg;
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
-            const uint32_t e = base | pdep((uint32_t)i, r0.reg);
-            v[i] = cmul_conj_a(pb[e ^ xlo], pa[e]);
+            const uint32_t r = pdep((uint32_t)i, r0.reg);
+            v[i] = cmul_conj_a((pb + (r ^ xr))[vb], (pa + r)[base]);
         }
         if constexpr (SPLIT) {
             const Real sc = ldexpf(1.0f, *scale_exp);
@@ -603,7 +623,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     C* __restrict__ out = scratch + ((uint64_t)s << NS) + ((uint64_t)srow << TB);
     const uint32_t base = thread_base<rl.lperm, rl.wave>();
 #pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) slab_store(out + (base | pdep((uint32_t)i, rl.reg)), v[i]);
+    for (int i = 0; i < (1 << RB); ++i) slab_store((out + pdep((uint32_t)i, rl.reg)) + base, v[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -644,11 +664,15 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     for (int ct = g * per; ct < (g + 1) * per; ++ct) {
         const C* __restrict__ src = slab + ((uint64_t)ct << CB);
         C v[1 << RB];
+        // tile element e -> slab offset (e >> CB) * 2^L + (e & CMASK), which
+        // adds over disjoint bits: the thread's part once, the register
+        // element's part as a uniform offset
         const uint32_t base = thread_base<r0.lperm, r0.wave>();
+        const uint64_t vb = ((uint64_t)(base >> CB) << L) + (base & CMASK);
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
-            const uint32_t e = base | pdep((uint32_t)i, r0.reg);
-            v[i] = slab_load(src + ((uint64_t)(e >> CB) << L) + (e & CMASK));
+            const uint32_t r = pdep((uint32_t)i, r0.reg);
+            v[i] = slab_load((src + (((uint64_t)(r >> CB) << L) + (r & CMASK))) + vb);
         }
         run_transform<Real, TB, RB, PK>(lds, v);
         if constexpr (GEN) {
