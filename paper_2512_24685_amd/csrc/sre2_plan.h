@@ -11,9 +11,15 @@
 // order of bits across rounds gives the same transform.
 //
 // LDS addresses are XOR-swizzled: tile bit b feeds bank slot bit (b mod SB),
-// where a slot is one complex value (SB = 5 for 8-byte, 4 for 16-byte values).
-// Lane bits 0..SB-1 of every round are placed on tile bits with distinct
-// residues mod SB, so each group of 2^SB lanes touches 2^SB distinct slots.
+// where a slot is one complex value (SB = 5 for 8-byte, 4 for 16-byte
+// values: 2^SB slots are 256 bytes, the 64 four-byte banks).  Measured
+// on gfx950 with rocprof's LDS bank-conflict counter, an access is free of
+// conflicts when each group of 2^SB lanes hits 2^SB distinct slots modulo
+// 2^SB and, inside it, each half group (128 bytes) hits distinct slots
+// modulo 2^(SB-1): lane bits 0..SB-2 may map onto slot bits 0..SB-2 in any
+// order, but lane bit SB-1 must map onto slot bit SB-1.  So lane bit i of
+// every round sits on a tile bit of residue i mod SB (i < SB), or at least
+// lane bits 0..SB-2 on residues 0..SB-2 and lane bit SB-1 on residue SB-1.
 #pragma once
 #include <stdint.h>
 
@@ -53,6 +59,7 @@ __host__ __device__ constexpr uint32_t lperm_of_mask(uint32_t lane) {
 }
 
 constexpr int kMaxRounds = 8;
+constexpr int kMaxTileBits = 16;
 
 struct Plan {
     int tb = 0, rb = 0, nrounds = 0;
@@ -140,13 +147,19 @@ __host__ __device__ constexpr Round make_round(int tb, int sb, uint32_t reg, uin
             }
         }
     }
-    // the matched bits take the low lane-id bits (ascending), the lowest
-    // remaining bits fill the rest
+    // lane-id bit i takes the matched bit of residue i, the lowest remaining
+    // bits fill the rest
     const uint32_t fill = low_bits(free_bits, 6 - popc(matched));
-    const int nm = popc(matched);
+    uint32_t lp = 0;
+    int nl = 0;
+    for (int i = 0; i < sb && i < 6; ++i)
+        for (int b = 0; b < tb; ++b)
+            if (((matched >> b) & 1u) && (b % sb) == i) lp |= (uint32_t)b << (5 * nl++);
+    for (int b = 0; b < tb; ++b)
+        if ((fill >> b) & 1u) lp |= (uint32_t)b << (5 * nl++);
     rd.lane = matched | fill;
     rd.wave = free_bits & ~fill;
-    rd.lperm = lperm_of_mask(matched) | (lperm_of_mask(fill) << (5 * nm));
+    rd.lperm = lp;
     rd.mf = 0;
     return rd;
 }
@@ -285,10 +298,12 @@ __host__ __device__ constexpr Round make_mf_round_as(int tb, int rb, int sb, uin
     return rd;
 }
 
-// True when lane-id bits 0..4 of a round have distinct bank-slot residues.
+// True when lane-id bits 0..SB-2 of a round sit on residues 0..SB-2 (in any
+// order) and lane-id bit SB-1 on residue SB-1.
 __host__ __device__ constexpr bool lanes_conflict_free(const Round& rd, int sb) {
+    if ((int)(((rd.lperm >> (5 * (sb - 1))) & 31u) % sb) != sb - 1) return false;
     uint32_t used = 0;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < sb && i < 6; ++i) {
         const uint32_t r = 1u << (((rd.lperm >> (5 * i)) & 31u) % sb);
         if (used & r) return false;
         used |= r;
@@ -384,8 +399,30 @@ __host__ __device__ constexpr Plan make_split_plan(int tb, int rb, int sb, int l
                     }
                 }
             } else {
+                // the factor on the lowest four bits, unless another four of
+                // the remaining bits give conflict-free lanes (lane-id bit
+                // SB - 1, a factor bit, needs a tile bit of residue SB - 1)
                 mf = low_bits(todo, 4);
                 v = top_bits(todo & ~mf, nv);
+                if (!lanes_conflict_free(make_mf_round(tb, rb, sb, mf, v, done, false), sb)) {
+                    int tbits[kMaxTileBits] = {};
+                    int nt = 0;
+                    for (int b = 0; b < 32 && nt < kMaxTileBits; ++b)
+                        if ((todo >> b) & 1u) tbits[nt++] = b;
+                    bool found = false;
+                    for (uint32_t sel = 0; sel < (1u << nt) && !found; ++sel) {
+                        if (popc(sel) != 4) continue;
+                        uint32_t m = 0;
+                        for (int i = 0; i < nt; ++i)
+                            if ((sel >> i) & 1u) m |= 1u << tbits[i];
+                        const uint32_t vv = top_bits(todo & ~m, nv);
+                        if (lanes_conflict_free(make_mf_round(tb, rb, sb, m, vv, done, false), sb)) {
+                            mf = m;
+                            v = vv;
+                            found = true;
+                        }
+                    }
+                }
             }
             p.r[k++] = make_mf_round(tb, rb, sb, mf, v, done, first);
             todo &= ~(mf | v);

@@ -61,6 +61,6 @@ int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, unsigned* out)
 }
 
 unsigned probe_swz(int sb, unsigned e) {
-    return sb == 5 ? sre2::swz<5>(e) : sre2::swz<4>(e);
+    return sb == 5 ? sre2::swz<5>(e) : sb == 4 ? sre2::swz<4>(e) : sre2::swz<3>(e);
 }
 }
