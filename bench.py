@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="fp32")
-    ap.add_argument("--also", default="fp32h,split16", help="other forms, comma separated")
+    ap.add_argument("--also", default="fp32h,split16,splitbf16", help="other forms, comma separated")
     ap.add_argument("--N", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -76,6 +76,10 @@ extern "C" {
  * FP64 at the end).  Stages left over (N mod 4) use FP32 butterflies; N < 5
  * uses the FP32 kernel. */
 #define SRE2_FORM_SPLIT_F16 1
+/* SPLIT_BF16: the same factors on v_mfma_f32_16x16x32_bf16 with BF16 hi + lo
+ * halves (16 significant bits per value instead of 22; BF16 has FP32's
+ * exponent range).  Same plans, scale and tolerance bar as SPLIT_F16. */
+#define SRE2_FORM_SPLIT_BF16 2
 /* FP64: everything in float64 (complex64 input is widened exactly). */
 #define SRE2_FORM_FP64 3
 /* Hermitian-pair forms: same arithmetic precision as FP32 / FP64 and the same

@@ -26,7 +26,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sre2.h")
 OK, EINVAL, EDTYPE, EFORM, ENORM, ENOMEM, EHIP, EBUSY, ECANCELLED, ENOTFOUND = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 C64, C128 = 0, 1
-FORMS = {"fp32": 0, "split16": 1, "fp64": 3, "fp32h": 4, "fp64h": 5}
+FORMS = {"fp32": 0, "split16": 1, "splitbf16": 2, "fp64": 3, "fp32h": 4, "fp64h": 5}
 MAX_N = 26
 OUT_LEN = 4
 KINDS = ("shift", "pass1", "pass2", "aux")

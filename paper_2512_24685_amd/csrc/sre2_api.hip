@@ -67,9 +67,14 @@ int ensure(void** buf, size_t* have, size_t need) {
 
 bool form_ok(int form) {
     return form == SRE2_FORM_FP32 || form == SRE2_FORM_FP64 || form == SRE2_FORM_FP32_HERM ||
-           form == SRE2_FORM_FP64_HERM || form == SRE2_FORM_SPLIT_F16;
+           form == SRE2_FORM_FP64_HERM || form == SRE2_FORM_SPLIT_F16 ||
+           form == SRE2_FORM_SPLIT_BF16;
 }
-bool is_split(int form) { return form == SRE2_FORM_SPLIT_F16; }
+// Split kind of the kernels: 0 none, 1 FP16 halves, 2 BF16 halves.
+int split_kind(int form) {
+    return form == SRE2_FORM_SPLIT_F16 ? 1 : form == SRE2_FORM_SPLIT_BF16 ? 2 : 0;
+}
+bool is_split(int form) { return split_kind(form) != 0; }
 bool is_f64(int form) { return form == SRE2_FORM_FP64 || form == SRE2_FORM_FP64_HERM; }
 bool is_herm(int form) { return form == SRE2_FORM_FP32_HERM || form == SRE2_FORM_FP64_HERM; }
 bool dtype_ok(int dtype) { return dtype == SRE2_C64 || dtype == SRE2_C128; }
@@ -176,7 +181,8 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
 // Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
 int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
              double* Sx, const int* se, const Spec* spec, hipStream_t st) {
-    const bool f64 = is_f64(form), split = is_split(form);
+    const bool f64 = is_f64(form);
+    const int split = split_kind(form);
     const Chunking ch = chunking(N, form, herm, xc, ctx->scratch_limit);
     for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
         // a short last chunk keeps the same column grouping
@@ -210,7 +216,8 @@ int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_
 // or N too small) through the plain kernels of the same precision.
 int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
                double* Sx, const int* se, const Spec* spec, hipStream_t st) {
-    const bool f64 = is_f64(form), sp = is_split(form);
+    const bool f64 = is_f64(form);
+    const int sp = split_kind(form);
     const int64_t x1 = x0 + xc;
     if (N <= fused_max(form)) {
         const bool herm = is_herm(form) && N >= herm_min(form);
@@ -372,7 +379,8 @@ int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, 
             pk.psi[i] = dst;
         }
     }
-    const bool f64 = is_f64(form), sp = is_split(form);
+    const bool f64 = is_f64(form);
+    const int sp = split_kind(form);
     const bool herm = is_herm(form) && N >= herm_min(form);
     const int nb = red_blocks(n);
     {

@@ -75,23 +75,24 @@ template <typename Real> int herm_min_n();
 template <typename Real> int64_t pass2_col_tiles(int N, bool herm);
 
 // S[i] = S_{x0+i} for shifts [x0, x0 + xc): tiny kernel (plain, N < RB) or
-// fused kernel (N <= fused_max_n).  `split` selects the split-FP16 MFMA
-// transform (FP32 only, not with herm); it reads the scale exponent *se.
+// fused kernel (N <= fused_max_n).  `split` selects the split MFMA transform
+// (0 none, 1 FP16 halves, 2 BF16 halves; FP32 only, not with herm); it reads
+// the scale exponent *se.
 // With pk.count > 0 the launch covers pk.count states of the same N (grid
 // y = state); psi / S / se then come from the pack (S = S_x of state y + x0).
 // sp != nullptr selects the general reduction (not with split or packs).
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int64_t x0,
                                int64_t xc, double* S, const int* se, const Pack& pk,
                                const Spec* sp, hipStream_t st);
 // Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
 // row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
 // pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
+hipError_t launch_pass1(const void* psi, int N, bool herm, int split, int64_t x0, int cs,
                         void* scratch, const int* se, hipStream_t st);
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
+hipError_t launch_pass2(const void* scratch, int N, bool herm, int split, int cs, int P,
                         double* part, const int* se, const Spec* sp, hipStream_t st);
 // *nrm = sum of the norm partials (for the histogram's normalisation).
 hipError_t launch_norm_total(const double* npart, int nb, double* nrm, hipStream_t st);

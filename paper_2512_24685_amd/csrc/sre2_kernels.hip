@@ -248,14 +248,15 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
 //   PK = 1000 + N : whole transform over tile bits [0, N)        (fused)
 //   PK = 2000     : row transform over all TB tile bits          (pass 1)
 //   PK = 3000 + H : column transform over the top H tile bits    (pass 2)
-//   PK + 10000    : the same transform in the split-FP16 form, with H_16
-//                   factors on the matrix cores (pass 1 ends with a round
-//                   whose lanes run over the lowest bits, for the stores)
+//   PK + 10000 s  : the same transform in split form s (1: FP16, 2: BF16
+//                   halves; one plan for both), with H_16 factors on the
+//                   matrix cores (pass 1 ends with a round whose lanes run
+//                   over the lowest bits, for the stores)
 template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
     constexpr int SB = Prec<Real>::SB;
     if (PK >= 10000) {
-        constexpr int K = PK - 10000;
+        constexpr int K = PK % 10000;
         if (K >= 3000) return make_split_plan(TB, RB, SB, TB - (K - 3000), TB, 0);
         if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, SRE2_SPLIT_P1_TAIL);
         return make_split_plan(TB, RB, SB, 0, K - 1000, 2);
@@ -274,52 +275,82 @@ __host__ __device__ constexpr bool plan_has_mf() {
 }
 
 // ---------------------------------------------------------------------------
-// Split-FP16 MFMA form.  H_16 = H_2^{(x)4} applied along four tile bits is a
-// 16x16 matrix of +-1 (exact in FP16).  Each FP32 value v (pre-scaled by a
-// power of two so that every |v| <= 2^14) is split into hi = fp16(v) and
-// lo = fp16(v - hi) (both rounded to nearest; v - hi is exact in FP32), and
-// one v_mfma_f32_16x16x32_f16 computes H_16 (hi + lo) with FP32 accumulation
-// for a 16 x 16 block: K = 32 holds the hi and lo halves of 16 rows.
+// Split MFMA forms.  H_16 = H_2^{(x)4} applied along four tile bits is a
+// 16x16 matrix of +-1 (exact in FP16 and BF16).  Each FP32 value v (pre-scaled
+// by a power of two so that every |v| <= 2^14, which FP16's range needs) is
+// split into hi = h(v) and lo = h(v - hi), h = fp16 (SPLIT 1) or bf16
+// (SPLIT 2), both rounded to nearest (v - hi is exact in FP32), and one
+// v_mfma_f32_16x16x32_{f16,bf16} computes H_16 (hi + lo) with FP32
+// accumulation for a 16 x 16 block: K = 32 holds the hi and lo halves of 16
+// rows.  The pair carries 22 significant bits with FP16 and 16 with BF16.
 // Operand layout (lane l, i = l % 16, g = l / 16):
 //   A[i][8g + j], B[8g + j][i] for j = 0..7,  D[4g + r][i] for r = 0..3.
 // K order used here: k = 8g + j  ->  row 4g + (j & 3), part j >> 2 (hi, lo),
 // so lane l feeds rows 4g..4g+3 and receives the same rows back.
 // ---------------------------------------------------------------------------
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float f32x2c __attribute__((ext_vector_type(2)));
+typedef short op8 __attribute__((ext_vector_type(8)));  // 8 halves, as bits
 
-__device__ __forceinline__ half8 h16_operand() {
+template <int SPLIT>
+struct SplitT;
+template <>
+struct SplitT<1> {
+    typedef _Float16 e8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 e2 __attribute__((ext_vector_type(2)));
+    __device__ __forceinline__ static floatx4 mfma(op8 a, op8 b) {
+        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(e8, a),
+                                                      __builtin_bit_cast(e8, b), zero, 0, 0, 0);
+    }
+};
+template <>
+struct SplitT<2> {
+    typedef __bf16 e8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 e2 __attribute__((ext_vector_type(2)));
+    __device__ __forceinline__ static floatx4 mfma(op8 a, op8 b) {
+        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(e8, a),
+                                                       __builtin_bit_cast(e8, b), zero, 0, 0, 0);
+    }
+};
+
+template <int SPLIT>
+__device__ __forceinline__ op8 h16_operand() {
+    using E8 = typename SplitT<SPLIT>::e8;
+    using E = decltype(E8{}[0]);
     const int l = threadIdx.x & 63;
     const int i = l & 15, g = l >> 4;
-    half8 a;
+    E8 a;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = 4 * g + (j & 3);
-        a[j] = (__builtin_popcount(i & k) & 1) ? (_Float16)-1.0f : (_Float16)1.0f;
+        a[j] = (__builtin_popcount(i & k) & 1) ? (E)-1.0f : (E)1.0f;
     }
-    return a;
+    return __builtin_bit_cast(op8, a);
 }
 
-typedef float f32x2c __attribute__((ext_vector_type(2)));
-
-// Two FP32 values to FP16, rounded to nearest (v_cvt_pk_f16_f32).
-__device__ __forceinline__ half2v pk_rne(float a, float b) {
+// Two FP32 values to FP16 / BF16, rounded to nearest (v_cvt_pk_f16_f32,
+// v_cvt_pk_bf16_f32).
+template <int SPLIT>
+__device__ __forceinline__ typename SplitT<SPLIT>::e2 pk_rne(float a, float b) {
     const f32x2c v = {a, b};
-    return __builtin_convertvector(v, half2v);
+    return __builtin_convertvector(v, typename SplitT<SPLIT>::e2);
 }
 
-// hi/lo halves of four values in the K order above.  hi = fp16(v) rounded to
-// nearest; v - hi is exact in FP32 (it is an integer multiple of v's FP32 ulp
-// below 2^13 of them), and lo = fp16(v - hi), also rounded to nearest, so the
-// split carries no systematic bias.
-__device__ __forceinline__ half8 split4(float a, float b, float c, float d) {
-    const half2v hab = pk_rne(a, b);
-    const half2v hcd = pk_rne(c, d);
-    const half2v lab = pk_rne(a - (float)hab[0], b - (float)hab[1]);
-    const half2v lcd = pk_rne(c - (float)hcd[0], d - (float)hcd[1]);
-    half8 r = {hab[0], hab[1], hcd[0], hcd[1], lab[0], lab[1], lcd[0], lcd[1]};
-    return r;
+// hi/lo halves of four values in the K order above.  hi = h(v) rounded to
+// nearest; v - hi is exact in FP32 (a multiple of v's FP32 ulp below 2^13 of
+// them for FP16, 2^16 for BF16), and lo = h(v - hi), also rounded to nearest,
+// so the split carries no systematic bias.
+template <int SPLIT>
+__device__ __forceinline__ op8 split4(float a, float b, float c, float d) {
+    const auto hab = pk_rne<SPLIT>(a, b);
+    const auto hcd = pk_rne<SPLIT>(c, d);
+    const auto lab = pk_rne<SPLIT>(a - (float)hab[0], b - (float)hab[1]);
+    const auto lcd = pk_rne<SPLIT>(c - (float)hcd[0], d - (float)hcd[1]);
+    const typename SplitT<SPLIT>::e8 r = {hab[0], hab[1], hcd[0], hcd[1],
+                                          lab[0], lab[1], lcd[0], lcd[1]};
+    return __builtin_bit_cast(op8, r);
 }
 
 // One round's H_16 factor in registers.  The factor's tile bits are the
@@ -327,17 +358,16 @@ __device__ __forceinline__ half8 split4(float a, float b, float c, float d) {
 // setting q of the other register-index bits, lane 16g + c holds rows 4g + j
 // of column c, which is the B operand layout, and receives rows 4g + r of the
 // product in the same registers.
-template <int RB, int A>
-__device__ __forceinline__ void mf_apply(float2 (&v)[1 << RB], const half8 amat) {
-    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+template <int SPLIT, int RB, int A>
+__device__ __forceinline__ void mf_apply(float2 (&v)[1 << RB], const op8 amat) {
 #pragma unroll
     for (int q = 0; q < (1 << (RB - 2)); ++q) {
         const int b = (q & ((1 << A) - 1)) | ((q >> A) << (A + 2));
         constexpr int s = 1 << A;
-        const half8 br = split4(v[b].x, v[b + s].x, v[b + 2 * s].x, v[b + 3 * s].x);
-        const half8 bi = split4(v[b].y, v[b + s].y, v[b + 2 * s].y, v[b + 3 * s].y);
-        const floatx4 dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, br, zero, 0, 0, 0);
-        const floatx4 di = __builtin_amdgcn_mfma_f32_16x16x32_f16(amat, bi, zero, 0, 0, 0);
+        const op8 br = split4<SPLIT>(v[b].x, v[b + s].x, v[b + 2 * s].x, v[b + 3 * s].x);
+        const op8 bi = split4<SPLIT>(v[b].y, v[b + s].y, v[b + 2 * s].y, v[b + 3 * s].y);
+        const floatx4 dr = SplitT<SPLIT>::mfma(amat, br);
+        const floatx4 di = SplitT<SPLIT>::mfma(amat, bi);
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[b + r * s] = make_float2(dr[r], di[r]);
     }
@@ -346,12 +376,12 @@ __device__ __forceinline__ void mf_apply(float2 (&v)[1 << RB], const half8 amat)
 // The arithmetic of round J: butterflies on its FP32 bits, then its H_16
 // factor (split form).
 template <typename Real, int TB, int RB, int PK, int J>
-__device__ __forceinline__ void round_math(typename CT<Real>::T (&v)[1 << RB], const half8 amat) {
+__device__ __forceinline__ void round_math(typename CT<Real>::T (&v)[1 << RB], const op8 amat) {
     constexpr Round rd = plan_of<Real, TB, RB, PK>().r[J];
     butterflies<RB, rd.reg, rd.bfly>(v);
     if constexpr (rd.mf != 0) {
         static_assert(sizeof(Real) == 4, "H_16 factors act on FP32 values");
-        mf_apply<RB, mf_reg_index(rd)>(v, amat);
+        mf_apply<PK / 10000, RB, mf_reg_index(rd)>(v, amat);
     }
 }
 
@@ -361,7 +391,7 @@ struct RoundRunner {
     using C = typename CT<Real>::T;
     static constexpr Plan P = plan_of<Real, TB, RB, PK>();
     static constexpr int SB = Prec<Real>::SB;
-    __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB], const half8 amat) {
+    __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB], const op8 amat) {
         if constexpr (J < P.nrounds) {
             constexpr Round prev = P.r[J - 1];
             constexpr Round cur = P.r[J];
@@ -379,8 +409,8 @@ struct RoundRunner {
 template <typename Real, int TB, int RB, int PK>
 __device__ __forceinline__ void run_transform(typename CT<Real>::T* lds,
                                               typename CT<Real>::T (&v)[1 << RB]) {
-    half8 amat = {};
-    if constexpr (PK >= 10000) amat = h16_operand();
+    op8 amat = {};
+    if constexpr (PK >= 10000) amat = h16_operand<PK / 10000>();
     round_math<Real, TB, RB, PK, 0>(v, amat);
     RoundRunner<Real, TB, RB, PK, 1>::run(lds, v, amat);
 }
@@ -478,7 +508,7 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 //                Re or twice i Im of this half transform, so
 //                S_x = 16 sum_z' (Re^4 + Im^4).
 // ---------------------------------------------------------------------------
-template <typename Real, int NT, int TB, int RB, bool HERM, bool SPLIT, bool GEN>
+template <typename Real, int NT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES : SRE2_FUSED_WAVES)))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
@@ -486,7 +516,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
              const Pack pk, const Spec sp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 1000 + NT + (SPLIT ? 10000 : 0);
+    constexpr int PK = 1000 + NT + 10000 * SPLIT;
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
@@ -574,13 +604,13 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // row bit and only rows with that bit clear are built).  Block b -> slab row
 // b / cs, shift slot b % cs, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
-template <typename Real, int TB, int RB, bool HERM, bool SPLIT>
+template <typename Real, int TB, int RB, bool HERM, int SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES)))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
-    constexpr int PK = 2000 + (SPLIT ? 10000 : 0);
+    constexpr int PK = 2000 + 10000 * SPLIT;
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
@@ -632,14 +662,14 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // columns.  Block b -> shift slot b / P, column group b % P; the group loops
 // over its column tiles and writes one FP64 partial of S_x.
 // ---------------------------------------------------------------------------
-template <typename Real, int HT, int TB, int RB, bool HERM, bool SPLIT, bool GEN>
+template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES)))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
-    constexpr int PK = 3000 + HT + (SPLIT ? 10000 : 0);
+    constexpr int PK = 3000 + HT + 10000 * SPLIT;
     constexpr Plan PL = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = PL.r[0];
     constexpr int CB = TB - HT;  // column bits per tile
@@ -831,7 +861,7 @@ hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S,
     return hipGetLastError();
 }
 
-template <typename Real, int NT, bool HERM, bool SPLIT, bool GEN>
+template <typename Real, int NT, bool HERM, int SPLIT, bool GEN>
 hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, const int* se,
                            const Pack& pk, const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
@@ -844,7 +874,7 @@ hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, c
     return hipGetLastError();
 }
 
-template <typename Real, int HT, bool HERM, bool SPLIT, bool GEN>
+template <typename Real, int HT, bool HERM, int SPLIT, bool GEN>
 hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part, const int* se,
                            const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
@@ -864,7 +894,7 @@ hipError_t dispatch_tiny(int N, const void* psi, int64_t x0, int64_t xc, double*
     return e;
 }
 
-template <typename Real, bool HERM, bool SPLIT, bool GEN, int... Ns>
+template <typename Real, bool HERM, int SPLIT, bool GEN, int... Ns>
 hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, double* S,
                           const int* se, const Pack& pk, const Spec& sp, hipStream_t st,
                           std::integer_sequence<int, Ns...>) {
@@ -878,7 +908,7 @@ hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, doubl
     return e;
 }
 
-template <typename Real, bool HERM, bool SPLIT, bool GEN, int... Hs>
+template <typename Real, bool HERM, int SPLIT, bool GEN, int... Hs>
 hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, double* part,
                           const int* se, const Spec& sp, hipStream_t st,
                           std::integer_sequence<int, Hs...>) {
@@ -936,33 +966,37 @@ template int64_t pass2_col_tiles<float>(int, bool);
 template int64_t pass2_col_tiles<double>(int, bool);
 
 template <typename Real, bool GEN>
-hipError_t shift_kernel_gen(const void* psi, int N, bool herm, bool split, int64_t x0,
+hipError_t shift_kernel_gen(const void* psi, int N, bool herm, int split, int64_t x0,
                             int64_t xc, double* S, const int* se, const Pack& pk, const Spec& sp,
                             hipStream_t st) {
     constexpr int RB = Tune<Real>::RBF, FMAX = Tune<Real>::FMAX;
     if (herm) {
         if (x0 < 1 || N - 1 < RB) return hipErrorInvalidValue;
-        return dispatch_fused<Real, true, false, GEN>(N - 1, psi, x0, xc, S, se, pk, sp, st,
+        return dispatch_fused<Real, true, 0, GEN>(N - 1, psi, x0, xc, S, se, pk, sp, st,
                                                       std::make_integer_sequence<int, FMAX - RB>{});
     }
     if (N < RB)
         return dispatch_tiny<Real, GEN>(N, psi, x0, xc, S, pk, sp, st,
                                         std::make_integer_sequence<int, RB - 1>{});
     if constexpr (sizeof(Real) == 4 && !GEN) {
-        if (split)
-            return dispatch_fused<Real, false, true, false>(
+        if (split == 1)
+            return dispatch_fused<Real, false, 1, false>(
+                N, psi, x0, xc, S, se, pk, sp, st, std::make_integer_sequence<int, FMAX - RB + 1>{});
+        if (split == 2)
+            return dispatch_fused<Real, false, 2, false>(
                 N, psi, x0, xc, S, se, pk, sp, st, std::make_integer_sequence<int, FMAX - RB + 1>{});
     }
-    return dispatch_fused<Real, false, false, GEN>(N, psi, x0, xc, S, se, pk, sp, st,
+    return dispatch_fused<Real, false, 0, GEN>(N, psi, x0, xc, S, se, pk, sp, st,
                                                    std::make_integer_sequence<int, FMAX - RB + 1>{});
 }
 
 template <typename Real>
-hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, int64_t x0,
+hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int64_t x0,
                                int64_t xc, double* S, const int* se, const Pack& pk,
                                const Spec* sp, hipStream_t st) {
     constexpr int FMAX = Tune<Real>::FMAX;
-    if (N > FMAX || (split && (herm || sizeof(Real) != 4)) || pk.count > kMaxPack)
+    if (N > FMAX || split < 0 || split > 2 || (split && (herm || sizeof(Real) != 4)) ||
+        pk.count > kMaxPack)
         return hipErrorInvalidValue;
     if (sp) {
         if (split || pk.count || sp->kind < kRedPow || sp->kind > kRedHist ||
@@ -975,27 +1009,32 @@ hipError_t launch_shift_kernel(const void* psi, int N, bool herm, bool split, in
 }
 
 template <typename Real, int TB>
-hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, bool split, int64_t x0, int cs,
+hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, int split, int64_t x0, int cs,
                            void* scratch, const int* se, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int RB = Tune<Real>::RB1;
     const int64_t rows = (int64_t)1 << (NS - TB);
     const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB));
     if (herm)
-        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, false>), grid, block, 0, st, (const C*)psi,
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
                            NS, x0, cs, (C*)scratch, se);
     else if (split) {
-        if constexpr (sizeof(Real) == 4)
-            hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, true>), grid, block, 0, st,
-                               (const C*)psi, NS, x0, cs, (C*)scratch, se);
+        if constexpr (sizeof(Real) == 4) {
+            if (split == 1)
+                hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 1>), grid, block, 0, st,
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se);
+            else
+                hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 2>), grid, block, 0, st,
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se);
+        }
     } else
-        hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, false>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 0>), grid, block, 0, st,
                            (const C*)psi, NS, x0, cs, (C*)scratch, se);
     return hipGetLastError();
 }
 
 template <typename Real, int... Ls>
-hipError_t dispatch_pass1(int L, const void* psi, int NS, bool herm, bool split, int64_t x0,
+hipError_t dispatch_pass1(int L, const void* psi, int NS, bool herm, int split, int64_t x0,
                           int cs, void* scratch, const int* se, hipStream_t st,
                           std::integer_sequence<int, Ls...>) {
     hipError_t e = hipErrorInvalidValue;
@@ -1009,10 +1048,11 @@ hipError_t dispatch_pass1(int L, const void* psi, int NS, bool herm, bool split,
 }
 
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x0, int cs,
+hipError_t launch_pass1(const void* psi, int N, bool herm, int split, int64_t x0, int cs,
                         void* scratch, const int* se, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
+    if (split < 0 || split > 2 || (split && (herm || sizeof(Real) != 4)))
+        return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
     const int L = row_bits_of<Real>(NS);
     if (herm && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
@@ -1022,10 +1062,11 @@ hipError_t launch_pass1(const void* psi, int N, bool herm, bool split, int64_t x
 }
 
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int cs, int P,
+hipError_t launch_pass2(const void* scratch, int N, bool herm, int split, int cs, int P,
                         double* part, const int* se, const Spec* sp, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    if (split && (herm || sizeof(Real) != 4)) return hipErrorInvalidValue;
+    if (split < 0 || split > 2 || (split && (herm || sizeof(Real) != 4)))
+        return hipErrorInvalidValue;
     const int NS = N - (herm ? 1 : 0);
     const int ROW = row_bits_of<Real>(NS);  // this slab's pass-1 row bits
     constexpr int HMAX = pass2_max_rows<Real>();
@@ -1035,41 +1076,45 @@ hipError_t launch_pass2(const void* scratch, int N, bool herm, bool split, int c
                                       sp->nbins > kMaxBins)))
             return hipErrorInvalidValue;
         if (herm)
-            return dispatch_pass2<Real, true, false, true>(NS - ROW, scratch, NS, cs, P, part, se,
+            return dispatch_pass2<Real, true, 0, true>(NS - ROW, scratch, NS, cs, P, part, se,
                                                            *sp, st,
                                                            std::make_integer_sequence<int, HMAX>{});
-        return dispatch_pass2<Real, false, false, true>(NS - ROW, scratch, NS, cs, P, part, se,
+        return dispatch_pass2<Real, false, 0, true>(NS - ROW, scratch, NS, cs, P, part, se,
                                                         *sp, st,
                                                         std::make_integer_sequence<int, HMAX>{});
     }
     const Spec none{};
     if (herm)
-        return dispatch_pass2<Real, true, false, false>(NS - ROW, scratch, NS, cs, P, part, se,
+        return dispatch_pass2<Real, true, 0, false>(NS - ROW, scratch, NS, cs, P, part, se,
                                                         none, st,
                                                         std::make_integer_sequence<int, HMAX>{});
     if constexpr (sizeof(Real) == 4) {
-        if (split)
-            return dispatch_pass2<Real, false, true, false>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                            none, st,
-                                                            std::make_integer_sequence<int, HMAX>{});
+        if (split == 1)
+            return dispatch_pass2<Real, false, 1, false>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                         none, st,
+                                                         std::make_integer_sequence<int, HMAX>{});
+        if (split == 2)
+            return dispatch_pass2<Real, false, 2, false>(NS - ROW, scratch, NS, cs, P, part, se,
+                                                         none, st,
+                                                         std::make_integer_sequence<int, HMAX>{});
     }
-    return dispatch_pass2<Real, false, false, false>(NS - ROW, scratch, NS, cs, P, part, se, none,
+    return dispatch_pass2<Real, false, 0, false>(NS - ROW, scratch, NS, cs, P, part, se, none,
                                                      st, std::make_integer_sequence<int, HMAX>{});
 }
 
-template hipError_t launch_shift_kernel<float>(const void*, int, bool, bool, int64_t, int64_t,
+template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int64_t, int64_t,
                                                double*, const int*, const Pack&, const Spec*,
                                                hipStream_t);
-template hipError_t launch_shift_kernel<double>(const void*, int, bool, bool, int64_t, int64_t,
+template hipError_t launch_shift_kernel<double>(const void*, int, bool, int, int64_t, int64_t,
                                                 double*, const int*, const Pack&, const Spec*,
                                                 hipStream_t);
-template hipError_t launch_pass1<float>(const void*, int, bool, bool, int64_t, int, void*,
+template hipError_t launch_pass1<float>(const void*, int, bool, int, int64_t, int, void*,
                                         const int*, hipStream_t);
-template hipError_t launch_pass1<double>(const void*, int, bool, bool, int64_t, int, void*,
+template hipError_t launch_pass1<double>(const void*, int, bool, int, int64_t, int, void*,
                                          const int*, hipStream_t);
-template hipError_t launch_pass2<float>(const void*, int, bool, bool, int, int, double*,
+template hipError_t launch_pass2<float>(const void*, int, bool, int, int, int, double*,
                                         const int*, const Spec*, hipStream_t);
-template hipError_t launch_pass2<double>(const void*, int, bool, bool, int, int, double*,
+template hipError_t launch_pass2<double>(const void*, int, bool, int, int, int, double*,
                                          const int*, const Spec*, hipStream_t);
 
 // s = 14 - ceil(log2 n) from the norm partials (0 when n is not positive and

@@ -70,6 +70,7 @@ def test_sre_and_spectrum_argument_validation(L, ctx):
     assert L.sre2_sre(h, FAKE, 10, 7, 0, 3.0, None, FAKE) == sre2.EDTYPE
     assert L.sre2_sre(h, FAKE, 10, 0, sre2.FORMS["split16"], 3.0, None, FAKE) == sre2.EFORM
     assert L.sre2_sre(h, FAKE, 10, 0, sre2.FORMS["split16"], 1.0, None, FAKE) == sre2.EFORM
+    assert L.sre2_sre(h, FAKE, 10, 0, sre2.FORMS["splitbf16"], 3.0, None, FAKE) == sre2.EFORM
     sp = L.sre2_pauli_spectrum
     assert sp(h, FAKE, 10, 0, 0, 1, None, FAKE, FAKE) == sre2.EINVAL
     assert sp(h, FAKE, 10, 0, 0, 65, None, FAKE, FAKE) == sre2.EINVAL
@@ -77,6 +78,7 @@ def test_sre_and_spectrum_argument_validation(L, ctx):
     assert sp(h, FAKE, 10, 0, 0, 16, None, FAKE, None) == sre2.EINVAL
     assert sp(h, FAKE, 0, 0, 0, 16, None, FAKE, FAKE) == sre2.EINVAL
     assert sp(h, FAKE, 10, 0, sre2.FORMS["split16"], 16, None, FAKE, FAKE) == sre2.EFORM
+    assert sp(h, FAKE, 10, 0, sre2.FORMS["splitbf16"], 16, None, FAKE, FAKE) == sre2.EFORM
 
 
 def test_partials_argument_validation(L, ctx):

@@ -69,7 +69,7 @@ def test_alpha_matches_oracle(form, N):
         assert err <= TOL[form], (alpha, err)
 
 
-@pytest.mark.parametrize("form", FORMS + ["split16"])
+@pytest.mark.parametrize("form", FORMS + ["split16", "splitbf16"])
 def test_alpha2_is_m2_bitwise(form):
     for N in (4, 11, 16):
         psi = W.haar(N, 77 + N, np.complex64)

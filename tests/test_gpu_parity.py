@@ -25,12 +25,15 @@ pytestmark = pytest.mark.gpu
 import paper_2512_24685_amd as sre2  # noqa: E402
 
 LOG43 = np.log2(4.0 / 3.0)
-TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9, "fp32h": 1e-5, "fp64h": 1e-9, "split16": 1e-5}
-TOL_SX = {"fp32": 1e-4, "fp64": 1e-11, "fp32h": 1e-4, "fp64h": 1e-11, "split16": 1e-4}
-FORMS = ["fp32", "fp64", "fp32h", "fp64h", "split16"]
+TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9, "fp32h": 1e-5, "fp64h": 1e-9, "split16": 1e-5,
+          "splitbf16": 1e-5}
+TOL_SX = {"fp32": 1e-4, "fp64": 1e-11, "fp32h": 1e-4, "fp64h": 1e-11, "split16": 1e-4,
+          "splitbf16": 1e-4}
+FORMS = ["fp32", "fp64", "fp32h", "fp64h", "split16", "splitbf16"]
 # Closed forms on complex64 inputs: the amplitude rounding alone moves M2 by
-# < 1e-6; the split form's 22-bit hi/lo values add up to its 1e-5 bound.
-CLOSED_TOL = {"split16": 1e-5}
+# < 1e-6; the split forms' 22-bit (FP16) and 16-bit (BF16) hi/lo values add
+# up to their 1e-5 bound.
+CLOSED_TOL = {"split16": 1e-5, "splitbf16": 1e-5}
 
 
 def closed_tol(form):
@@ -143,7 +146,7 @@ def test_shard_sum_equals_whole():
     assert abs(sum(parts) - r.S) <= 1e-12 * r.S
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16"])
 def test_determinism_and_batched(form):
     psis = [dev(W.haar(N, 60 + N, np.complex64)) for N in (3, 8, 12, 15, 16)]
     case_id("determinism", form)
@@ -211,7 +214,7 @@ def test_n20_full_size(oracle_mod, form):
     assert abs(rt.m2 - 10 * LOG43) <= closed_tol(form)
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "fp64", "fp64h"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16", "fp64", "fp64h"])
 @pytest.mark.parametrize("N", [22, 24])
 def test_large_n_sampled_shifts(N, form):
     g = _golden()
@@ -230,7 +233,7 @@ def test_large_n_sampled_shifts(N, form):
         assert abs(got - ref[x]) <= TOL_SX[form] * ref[x], x
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16"])
 def test_max_n_sampled_shift(oracle_mod, form):
     """The largest N of the FP32 forms (2^26 amplitudes, 512 MiB): one
     shift's S_x against the oracle, computed here."""

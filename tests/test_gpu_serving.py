@@ -46,7 +46,7 @@ def mixed_states(count, seed, n_lo, n_hi, dtype=np.complex64):
     return out
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "fp64", "fp64h"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16", "fp64", "fp64h"])
 def test_packed_batch_bitwise_equals_single(form):
     states = mixed_states(60, 11, 1, 16)
     states += [W.haar(9, 500 + i, np.complex64) for i in range(70)]  # > one pack of N=9

@@ -47,7 +47,7 @@ def dev(psi):
     return torch.from_numpy(np.ascontiguousarray(psi)).to("cuda")
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16"])
 def test_n16_batch(form):
     print("CASE n16-batch", form, flush=True)
     inputs = W.workload_inputs("n16_batch")
@@ -57,7 +57,7 @@ def test_n16_batch(form):
     for i, ((name, psi, closed), r) in enumerate(zip(inputs, res)):
         assert r.status == 0
         if closed is not None:
-            tol = 1e-5 if form == "split16" else 1e-6
+            tol = 1e-5 if form.startswith("split") else 1e-6
             assert abs(r.m2 - closed) <= tol, name
             checked += 1
         else:
