@@ -135,6 +135,17 @@ size_t sre2_workspace_bytes(int N, int dtype, int form);
 int sre2_m2(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, void* stream,
             double* out, double* partials);
 
+/* Moments of the input as given (the state written in the computational
+ * basis, main text): out[0] = n = sum_t |psi_t|^2, out[1] = sum_t |psi_t|^4
+ * (the inverse participation ratio times n^2; by Parseval on the x = 0
+ * transform, f_0 = |psi|^2, sum_z |W_0(z)|^2 = 2^N out[1]), out[2] = number
+ * of non-finite amplitudes.  FP64 over the input's own element type, fixed
+ * summation order (bitwise reproducible).  Stream-ordered, no host sync.
+ *   psi  device, 2^N amplitudes of `dtype`;  out  device, 3 doubles
+ * Errors: SRE2_EINVAL (null pointer, N outside [1, SRE2_MAX_N]), SRE2_EDTYPE,
+ * SRE2_ENOMEM, SRE2_EHIP. */
+int sre2_moments(sre2_ctx* ctx, const void* psi, int N, int dtype, void* stream, double* out);
+
 /* Stabilizer Renyi entropy of any index alpha > 0 (Eq. 1):
  *   M_alpha = log2( sum_P |<P>|^(2 alpha) / 2^N ) / (1 - alpha),
  * and for alpha = 1 its limit M_1 = -sum_P Xi_P log2 Xi_P - N with

@@ -12,6 +12,7 @@ Functions
 ---------
 m2(psi)                  M2 by Algorithm 1 over all shifts (Eq. final1 / Eq. 1).
 total(psi)               (S, n): S = sum_{x,z} |W_x(z)|^4 and n = sum |psi|^2.
+norm2(psi), ipr(psi)     n = sum |psi|^2 and sum |psi|^4 of the state as given.
 partials(psi, xs)        S_x = sum_z |W_x(z)|^4 for selected shifts.
 brute_sum(psi)           sum over all 4^N Pauli strings of |<P>|^4, O(8^N).
 pauli_expect(psi, x, z)  <psi|X^x Z^z|psi> by the direct sum (Eq. Pauli_expect).
@@ -66,6 +67,7 @@ def _load():
         "sre2o_all_partials": [dp, c_int, c_int, dp],
         "sre2o_sum_ascending": [dp, c_i64, dp],
         "sre2o_norm2": [dp, c_int, dp],
+        "sre2o_ipr": [dp, c_int, dp],
         "sre2o_m2": [dp, c_int, c_int, dp, dp, dp],
         "sre2o_max_threads": [],
         "sre2o_alpha_sum": [dp, c_int, ctypes.c_double, c_int, c_int, dp],
@@ -125,6 +127,14 @@ def norm2(psi) -> float:
     a, N = _as_c128(psi)
     out = ctypes.c_double()
     _check(_load().sre2o_norm2(_dp(a), N, ctypes.byref(out)), "norm2")
+    return float(out.value)
+
+
+def ipr(psi) -> float:
+    """sum |psi|^4 of the state as given (FP64, compensated)."""
+    a, N = _as_c128(psi)
+    out = ctypes.c_double()
+    _check(_load().sre2o_ipr(_dp(a), N, ctypes.byref(out)), "ipr")
     return float(out.value)
 
 

@@ -281,6 +281,26 @@ int sre2o_norm2(const double *psi, int N, double *out)
     return 0;
 }
 
+/* Inverse participation ratio sum_t |psi(t)|^4 of the state as given (no
+ * normalisation), ascending compensated FP64 sum.  By Parseval applied to the
+ * x = 0 transform (f_0 = |psi|^2), sum_z |W_0(z)|^2 = 2^N times this value. */
+int sre2o_ipr(const double *psi, int N, double *out)
+{
+    if (!psi || !out || N < 0 || N > ORACLE_MAX_N)
+        return -1;
+    const int64_t d = (int64_t)1 << N;
+    double *q = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!q)
+        return -2;
+    for (int64_t t = 0; t < d; ++t) {
+        const double m = psi[2 * t] * psi[2 * t] + psi[2 * t + 1] * psi[2 * t + 1];
+        q[t] = m * m;
+    }
+    *out = compensated_sum(q, d);
+    free(q);
+    return 0;
+}
+
 /* M2 by Algorithm 1: all shifts, FWHT per shift, ascending compensated sum,
  * then M2 = -log2( S / (2^N n^4) ).  Optionally returns S and n. */
 int sre2o_m2(const double *psi, int N, int nthreads, double *m2, double *total,

@@ -62,6 +62,7 @@ def lib():
         "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_partials": ([vp, vp, c_int, c_int, c_int, i64, i64, vp, vp], c_int),
+        "sre2_moments": ([vp, vp, c_int, c_int, vp, vp], c_int),
         "sre2_sre": ([vp, vp, c_int, c_int, c_int, ctypes.c_double, vp, vp], c_int),
         "sre2_pauli_spectrum": ([vp, vp, c_int, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_m2_batched": ([vp, ctypes.POINTER(vp), ctypes.POINTER(c_int), c_int, c_int, c_int,
@@ -283,6 +284,22 @@ def pauli_spectrum(psi, nbins: int = 32, form: str = "fp32", ctx: Context | None
                                    ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_pauli_spectrum")
     return counts.cpu().numpy(), _result(out.cpu())
+
+
+def moments(psi, ctx: Context | None = None, stream=None):
+    """(n, sum |psi|^4, non-finite count) of the state as given, in FP64
+    (synchronises to read them)."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    ctx = ctx or context(psi.device.index or 0)
+    out = torch.empty(3, dtype=torch.float64, device=psi.device)
+    rc = lib().sre2_moments(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
+                            ctypes.c_void_p(_stream_ptr(psi, stream)),
+                            ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_moments")
+    n, ipr, bad = out.cpu().tolist()
+    return n, ipr, int(bad)
 
 
 def shift_partials(psi, x_begin: int = 0, x_count: int | None = None, form: str = "fp32",

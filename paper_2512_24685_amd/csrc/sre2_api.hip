@@ -552,6 +552,20 @@ int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int fo
     return m2_one(ctx, psi, N, dtype, form, (hipStream_t)stream, out, nullptr, &sp);
 }
 
+int sre2_moments(sre2_ctx* ctx, const void* psi, int N, int dtype, void* stream, double* out) {
+    if (!ctx || !psi || !out || N < 1 || N > SRE2_MAX_N) return SRE2_EINVAL;
+    if (!dtype_ok(dtype)) return SRE2_EDTYPE;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    Red r;
+    const int rc = red_buffers(ctx, &r);
+    if (rc) return rc;
+    const int64_t n = int64_t(1) << N;
+    Timed tm(ctx, (hipStream_t)stream, SRE2_KIND_AUX);
+    return hip_status(launch_moments(psi, dtype == SRE2_C64 ? kC64 : kC128, n, red_blocks(n),
+                                     ctx->red, out, (hipStream_t)stream));
+}
+
 int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
                   int64_t x_count, void* stream, double* partials) {
     int rc = validate(ctx, psi, N, dtype, form);

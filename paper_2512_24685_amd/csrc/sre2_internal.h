@@ -94,6 +94,10 @@ hipError_t launch_pass1(const void* psi, int N, bool herm, int split, int64_t x0
 template <typename Real>
 hipError_t launch_pass2(const void* scratch, int N, bool herm, int split, int cs, int P,
                         double* part, const int* se, const Spec* sp, hipStream_t st);
+// out[0..2] = (sum |psi|^2, sum |psi|^4, non-finite count) of the input as
+// given, in FP64; m holds 3 kMaxRed doubles of block partials.
+hipError_t launch_moments(const void* psi, int dtype, int64_t n, int nblocks, double* m,
+                          double* out, hipStream_t st);
 // *nrm = sum of the norm partials (for the histogram's normalisation).
 hipError_t launch_norm_total(const double* npart, int nb, double* nrm, hipStream_t st);
 // p[0 .. count) = 0 (a kernel, so that callers may capture it in a graph).

@@ -769,6 +769,44 @@ __global__ __launch_bounds__(kRedThreads) void k_norm_part(const C* __restrict__
     }
 }
 
+// Moments of the input as given, per block over the same fixed ranges as
+// k_norm_part: m[b] = sum |psi|^2, m[K + b] = sum |psi|^4 (the inverse
+// participation ratio's numerator), m[2K + b] = count of non-finite
+// amplitudes, K = kMaxRed; all in FP64.
+template <typename C>
+__global__ __launch_bounds__(kRedThreads) void k_moment_part(const C* __restrict__ psi, int64_t n,
+                                                             int64_t per_block,
+                                                             double* __restrict__ m) {
+    __shared__ double red[kRedThreads];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < n ? lo + per_block : n;
+    double s2 = 0.0, s4 = 0.0, bad = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedThreads) {
+        const double re = (double)psi[i].x, im = (double)psi[i].y;
+        if (!isfinite(re) || !isfinite(im)) bad += 1.0;
+        const double q = re * re + im * im;
+        s2 += q;
+        s4 += q * q;
+    }
+    const double t2 = block_sum<kRedThreads>(s2, red);
+    const double t4 = block_sum<kRedThreads>(s4, red);
+    const double tb = block_sum<kRedThreads>(bad, red);
+    if (threadIdx.x == 0) {
+        m[blockIdx.x] = t2;
+        m[kMaxRed + blockIdx.x] = t4;
+        m[2 * kMaxRed + blockIdx.x] = tb;
+    }
+}
+
+// out[j] = sum over b < nb of m[j K + b] in b order, j = 0, 1, 2.
+__global__ void k_moment_final(const double* __restrict__ m, int nb, double* __restrict__ out) {
+    const int j = threadIdx.x;
+    if (j >= 3) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += m[j * kMaxRed + b];
+    out[j] = a;
+}
+
 // part[b] = sum of v over block b's fixed range (optionally with stride-P
 // grouping: entry x*P+p belongs to shift x; Sx, when non-null, receives
 // sum_p v[x*P+p] in p order).
@@ -1167,6 +1205,22 @@ hipError_t launch_norm(const void* psi, int dtype, int64_t n, int nblocks, doubl
     else
         hipLaunchKernelGGL((k_norm_part<double2>), grid, dim3(kRedThreads), 0, st,
                            (const double2*)psi, n, per, part, flag, pk);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const void* psi, int dtype, int64_t n, int nblocks, double* m,
+                          double* out, hipStream_t st) {
+    if (nblocks < 1 || nblocks > kMaxRed) return hipErrorInvalidValue;
+    const int64_t per = (n + nblocks - 1) / nblocks;
+    if (dtype == kC64)
+        hipLaunchKernelGGL((k_moment_part<float2>), dim3(nblocks), dim3(kRedThreads), 0, st,
+                           (const float2*)psi, n, per, m);
+    else
+        hipLaunchKernelGGL((k_moment_part<double2>), dim3(nblocks), dim3(kRedThreads), 0, st,
+                           (const double2*)psi, n, per, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moment_final, dim3(1), dim3(64), 0, st, m, nblocks, out);
     return hipGetLastError();
 }
 

@@ -89,6 +89,12 @@ def test_partials_argument_validation(L, ctx):
     assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 0, None, FAKE) == sre2.EINVAL
     assert L.sre2_partials(h, FAKE, 4, 0, 0, 0, 4, None, None) == sre2.EINVAL
     assert L.sre2_partials(h, FAKE, 4, 3, 0, 0, 4, None, FAKE) == sre2.EDTYPE
+    assert L.sre2_moments(None, FAKE, 4, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_moments(h, None, 4, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_moments(h, FAKE, 4, 0, None, None) == sre2.EINVAL
+    assert L.sre2_moments(h, FAKE, 0, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_moments(h, FAKE, 27, 0, None, FAKE) == sre2.EINVAL
+    assert L.sre2_moments(h, FAKE, 4, 2, None, FAKE) == sre2.EDTYPE
 
 
 def test_batched_argument_validation(L, ctx):

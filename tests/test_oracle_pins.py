@@ -189,6 +189,28 @@ def test_purity_parseval_hermiticity_bounds(oracle_mod):
     assert 0.0 <= m <= N
 
 
+def test_norm_and_ipr(oracle_mod):
+    """n and sum |psi|^4: basis state (1, 1), |+>^N (1, 2^-N), a scaled
+    state (c^2 n, c^4 IPR), Parseval on the x = 0 transform
+    (sum_z |W_0(z)|^2 = 2^N sum |psi|^4), and the Haar mean 2 / (2^N + 1)."""
+    N = 7
+    d = 1 << N
+    e = np.zeros(d, np.complex128)
+    e[37] = 1.0
+    assert oracle_mod.norm2(e) == 1.0 and oracle_mod.ipr(e) == 1.0
+    plus = np.full(d, 2.0 ** (-N / 2), np.complex128)
+    assert abs(oracle_mod.norm2(plus) - 1.0) < 1e-15
+    assert abs(oracle_mod.ipr(plus) / 2.0 ** -N - 1.0) < 1e-14
+    psi = W.haar(N, 21)
+    c = 1.3
+    assert abs(oracle_mod.norm2(c * psi) - c * c * oracle_mod.norm2(psi)) < 1e-14
+    assert abs(oracle_mod.ipr(c * psi) - c ** 4 * oracle_mod.ipr(psi)) < 1e-14
+    W0 = oracle_mod.shift_transform(psi, 0)
+    assert abs(np.sum(abs(W0) ** 2) - d * oracle_mod.ipr(psi)) < 1e-12 * d
+    vals = [oracle_mod.ipr(W.haar(10, 700 + i)) for i in range(8)]
+    assert abs(np.mean(vals) * (2 ** 10 + 1) / 2 - 1.0) < 0.05
+
+
 def test_haar_average_law(oracle_mod):
     """Fig. 1(b): Haar average close to log2(2^N + 3) - 2 (statistical)."""
     N = 10
