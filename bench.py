@@ -449,9 +449,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.form.startswith("fp64") else "f32",
         "data": "synthetic",
-        "config": {"workload": f"exact M2 of one N={N} Haar-random complex64 state, plain "
-                               f"XOR-FWHT ({args.form} butterflies, FP64 sums), two-pass "
-                               f"row/column transform through an HBM slab",
+        "config": {"workload": f"exact M2 of one N={N} Haar-random complex64 state, "
+                               f"XOR-FWHT in the {args.form} form (FP64 sums), "
+                               + ("two-pass row/column transform through an HBM slab"
+                                  if dom != "shift" else
+                                  "whole transforms in one workgroup's LDS (fused kernel)"),
                    "N": N, "pauli_strings_per_step": 4 ** N, "form": args.form,
                    "shifts_per_chunk": cs, "column_groups": P, "M2": m2},
         "roofline": roof,
