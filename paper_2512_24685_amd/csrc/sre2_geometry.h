@@ -18,7 +18,7 @@ constexpr int kMaxNAll = 26;
 //               can still grow (up to the largest tile): with H <= P2_ROWS a
 //               pass-2 tile holds at least 128 contiguous bytes of every row
 //   P2_MIN      smallest pass-2 tile; a pass-2 tile holds all 2^H rows and at
-//               least 16 consecutive columns when the LDS allows it
+//               least 2^P2_COLS consecutive columns when the LDS allows it
 // ---------------------------------------------------------------------------
 #ifndef SRE2_F32_RB_FUSED
 #define SRE2_F32_RB_FUSED 5
@@ -40,6 +40,9 @@ constexpr int kMaxNAll = 26;
 #endif
 #ifndef SRE2_F32_P2_MIN
 #define SRE2_F32_P2_MIN 12
+#endif
+#ifndef SRE2_F32_P2_COLS
+#define SRE2_F32_P2_COLS 4
 #endif
 #ifndef SRE2_P2_ROWS
 #define SRE2_P2_ROWS 10
@@ -65,17 +68,22 @@ constexpr int kMaxNAll = 26;
 #ifndef SRE2_F64_P2_MIN
 #define SRE2_F64_P2_MIN 11
 #endif
+#ifndef SRE2_F64_P2_COLS
+#define SRE2_F64_P2_COLS 3
+#endif
 
 template <typename Real> struct Tune;
 template <> struct Tune<float> {
     static constexpr int RBF = SRE2_F32_RB_FUSED, FMIN = SRE2_F32_FUSED_MIN;
     static constexpr int FMAX = SRE2_F32_FUSED_MAX, ROW = SRE2_F32_ROW;
     static constexpr int RB1 = SRE2_F32_RB1, RB2 = SRE2_F32_RB2, P2MIN = SRE2_F32_P2_MIN;
+    static constexpr int P2COLS = SRE2_F32_P2_COLS;
 };
 template <> struct Tune<double> {
     static constexpr int RBF = SRE2_F64_RB_FUSED, FMIN = SRE2_F64_FUSED_MIN;
     static constexpr int FMAX = SRE2_F64_FUSED_MAX, ROW = SRE2_F64_ROW;
     static constexpr int RB1 = SRE2_F64_RB1, RB2 = SRE2_F64_RB2, P2MIN = SRE2_F64_P2_MIN;
+    static constexpr int P2COLS = SRE2_F64_P2_COLS;
 };
 
 // Row bits of pass 1 for a slab of NS bits (NS = N, or N - 1 in the
@@ -97,7 +105,8 @@ constexpr int fused_tb(int N) {
 }
 template <typename Real>
 constexpr int pass2_tb(int H) {
-    int tb = H + 4 > Tune<Real>::P2MIN ? H + 4 : Tune<Real>::P2MIN;
+    const int want = H + Tune<Real>::P2COLS;
+    int tb = want > Tune<Real>::P2MIN ? want : Tune<Real>::P2MIN;
     if (tb > Prec<Real>::MAXTB) tb = Prec<Real>::MAXTB;
     if (tb < H) tb = H;
     if (tb < Tune<Real>::RB2 + 6) tb = Tune<Real>::RB2 + 6;
