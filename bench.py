@@ -144,8 +144,18 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
                       f"2^{N} Pauli strings (Algorithm 1 loop body), {dt:.1f} s on {cores} threads"}
 
 
-def measure(sre2, torch, d_psi, form, steps, warmup):
+SCRATCH_LIMIT = 0  # bytes; 0 keeps the library default
+
+
+def new_context(sre2):
     ctx = sre2.Context(0)
+    if SCRATCH_LIMIT:
+        ctx.set_scratch_limit(SCRATCH_LIMIT)
+    return ctx
+
+
+def measure(sre2, torch, d_psi, form, steps, warmup):
+    ctx = new_context(sre2)
     stream = torch.cuda.current_stream()
     for i in range(warmup):
         out, _ = sre2.m2_async(d_psi, form=form, ctx=ctx)
@@ -277,18 +287,22 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
     }
 
 
-def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"), chunks=3):
-    """Large slabs: a few two-pass chunks of the full-evaluation launch shape
-    (shifts from x = 2^(N-1)) per (N, form), with each pass's algorithmic
-    HBM rate and its fraction of the 8 TB/s peak, and the full-evaluation
-    time this implies."""
+def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"),
+                      work=2 ** 35):
+    """Large slabs: whole two-pass chunks of the full-evaluation launch shape
+    (shifts from x = 2^(N-1)) per (N, form), `work` slab values in total
+    (about 0.14 s: a timed region of only a few launches reads low, because
+    the clocks ramp up after the host's synchronisation), with each pass's
+    algorithmic HBM rate and its fraction of the 8 TB/s peak, and the
+    full-evaluation time this implies."""
     out = {}
     for N in Ns:
         psi = torch.from_numpy(W.haar(N, W.SEED_LARGE + (0 if N == 22 else 1), np.complex64))
         d = psi.to("cuda:0")
         for form in forms:
-            ctx = sre2.Context(0)
+            ctx = new_context(sre2)
             cs, P = ctx.chunking(N, form)
+            chunks = max(1, work // (cs << N))
             x0 = 1 << (N - 1)
             sre2.shift_partials(d, x0, cs, form=form, ctx=ctx)  # warm-up chunk
             torch.cuda.synchronize()
@@ -300,7 +314,8 @@ def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"), ch
             kt = ctx.timing_read()
             ctx.close()
             by, _ = alg_units(N, form, "pass1", cs)
-            rec = {"shifts_per_chunk": cs, "row_bits": sre2.row_bits(N, form),
+            rec = {"shifts_per_chunk": cs, "chunks_timed": chunks,
+                   "row_bits": sre2.row_bits(N, form),
                    "s_per_evaluation": dt / (chunks * cs) * (1 << N)}
             for k in ("pass1", "pass2"):
                 ms, n = kt[k]
@@ -365,6 +380,8 @@ def main():
                     help="TFIM quench steps of the snapshot-pipeline measurement (0: skip)")
     ap.add_argument("--dynamics-N", type=int, default=16)
     ap.add_argument("--large", type=int, default=1, help="large-slab measurement (0: skip)")
+    ap.add_argument("--scratch-gib", type=float, default=0.0,
+                    help="two-pass scratch limit per context in GiB (0: library default)")
     ap.add_argument("--profile-chunks", type=int, default=0, metavar="C",
                     help="run only C two-pass chunks (the benchmark's launch shape) from "
                          "x = 2^(N-1), for counter collection")
@@ -377,6 +394,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    global SCRATCH_LIMIT
+    SCRATCH_LIMIT = int(args.scratch_gib * 2 ** 30)
 
     import torch
 
@@ -394,7 +413,7 @@ def main():
     psi = W.haar(N, W.SEED_N20, np.complex64)
     d_psi = torch.from_numpy(psi).to("cuda:0")
     if args.profile_chunks:
-        ctx = sre2.Context(0)
+        ctx = new_context(sre2)
         cs, _ = ctx.chunking(N, args.form)
         x0 = 1 << (N - 1)
         for c in range(args.profile_chunks):

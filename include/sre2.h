@@ -119,8 +119,12 @@ int sre2_create(sre2_ctx** out, int hip_device);
 int sre2_destroy(sre2_ctx* ctx);
 
 /* Upper bound for the two-pass scratch slab (N >= 15 in FP32, N >= 14 in
- * FP64); shifts are processed in chunks that fit it.  Default 4 GiB; values
- * below one shift's slab are raised to one slab. */
+ * FP64); shifts are processed in chunks that fit it (at most 2^L shifts per
+ * chunk, L = sre2_row_bits).  Default 32 GiB: larger chunks keep both passes
+ * closer to the memory rate.  Values below one shift's slab are raised to one
+ * slab.  When the device cannot allocate a call's slab, that call halves its
+ * chunks until the slab fits (down to one shift per chunk); results never
+ * depend on the chunk size. */
 int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes);
 
 /* Device workspace (bytes) a call with these arguments grows the context to,

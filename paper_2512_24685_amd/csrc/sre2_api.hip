@@ -48,6 +48,8 @@ int fault_injected(const char* what) {
 int ensure(void** buf, size_t* have, size_t need) {
     if (*have >= need && *buf) return SRE2_OK;
     if (fault_injected("alloc")) return SRE2_ENOMEM;
+    // a device with little free memory: requests above 4 GiB fail
+    if (need > (size_t(4) << 30) && fault_injected("alloc_4g")) return SRE2_ENOMEM;
     if (*buf) {
         if (hipFree(*buf) != hipSuccess) return SRE2_EHIP;
         *buf = nullptr;
@@ -180,10 +182,10 @@ int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipS
 
 // Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
 int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
-             double* Sx, const int* se, const Spec* spec, hipStream_t st) {
+             double* Sx, const int* se, const Spec* spec, size_t limit, hipStream_t st) {
     const bool f64 = is_f64(form);
     const int split = split_kind(form);
-    const Chunking ch = chunking(N, form, herm, xc, ctx->scratch_limit);
+    const Chunking ch = chunking(N, form, herm, xc, limit);
     for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
         // a short last chunk keeps the same column grouping
         const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
@@ -246,31 +248,43 @@ int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int
     // Hermitian-pair two-pass needs x >= 2^L of its own (N - 1)-bit slab
     const int64_t lim = int64_t(1) << row_bits(form, N - 1);
     const int64_t split = herm ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
-    // workspace for the larger of the two chunk shapes
-    size_t need = 0, need_part = 0;
+    // workspace for the larger of the two chunk shapes; when the device
+    // cannot hold it, the chunks shrink (halving the limit for this call)
+    // down to one shift per chunk.  Chunking never changes a result bit.
+    size_t limit = ctx->scratch_limit, need = 0, need_part = 0;
     const int elem = elem_bytes(work_dtype(form));
-    if (split > x0) {
-        const Chunking c = chunking(N, form, false, split - x0, ctx->scratch_limit);
-        need = (size_t)c.cs * (size_t(1) << N) * elem;
-        need_part = (size_t)c.cs * c.P;
+    int rc;
+    for (;;) {
+        need = 0;
+        need_part = 0;
+        int64_t cs_max = 0;
+        if (split > x0) {
+            const Chunking c = chunking(N, form, false, split - x0, limit);
+            need = (size_t)c.cs * (size_t(1) << N) * elem;
+            need_part = (size_t)c.cs * c.P;
+            cs_max = c.cs;
+        }
+        if (x1 > split) {
+            const Chunking c = chunking(N, form, true, x1 - split, limit);
+            const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
+            need = need > b ? need : b;
+            need_part = need_part > (size_t)c.cs * c.P ? need_part : (size_t)c.cs * c.P;
+            cs_max = cs_max > c.cs ? cs_max : c.cs;
+        }
+        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
+        if (rc != SRE2_ENOMEM || cs_max <= 1) break;
+        limit = need / 2;
     }
-    if (x1 > split) {
-        const Chunking c = chunking(N, form, true, x1 - split, ctx->scratch_limit);
-        const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
-        need = need > b ? need : b;
-        need_part = need_part > (size_t)c.cs * c.P ? need_part : (size_t)c.cs * c.P;
-    }
-    int rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
     if (rc) return rc;
     rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
     if (rc) return rc;
     if (split > x0) {
-        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, spec, st);
+        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, spec, limit, st);
         if (rc) return rc;
     }
     if (x1 > split)
         rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), se, spec,
-                      st);
+                      limit, st);
     return rc;
 }
 

@@ -9,7 +9,7 @@
 
 struct sre2_ctx {
     int device = 0;
-    size_t scratch_limit = size_t(4) << 30;
+    size_t scratch_limit = size_t(32) << 30;  // halved on allocation failure, per call
     void* psi_work = nullptr;
     size_t psi_work_bytes = 0;
     double* sx = nullptr;  // S_x when the caller passes no partials buffer

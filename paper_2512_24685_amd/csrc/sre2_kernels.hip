@@ -160,16 +160,20 @@ __device__ __forceinline__ void slab_store(double2* p, double2 v) {
         *p = v;
     }
 }
+// NT = false keeps the line in the caches (for tiles that read only part of
+// a 128-byte line per row: the next column tile takes the rest).
+template <bool NT = SRE2_NT_SLAB>
 __device__ __forceinline__ float2 slab_load(const float2* p) {
-    if constexpr (SRE2_NT_SLAB) {
+    if constexpr (NT) {
         const f32x2v w = __builtin_nontemporal_load(reinterpret_cast<const f32x2v*>(p));
         return make_float2(w.x, w.y);
     } else {
         return *p;
     }
 }
+template <bool NT = SRE2_NT_SLAB>
 __device__ __forceinline__ double2 slab_load(const double2* p) {
-    if constexpr (SRE2_NT_SLAB) {
+    if constexpr (NT) {
         const f64x2v w = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p));
         return make_double2(w.x, w.y);
     } else {
@@ -674,6 +678,8 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     constexpr Round r0 = PL.r[0];
     constexpr int CB = TB - HT;  // column bits per tile
     constexpr uint32_t CMASK = (1u << CB) - 1u;
+    // streaming loads only when a tile reads whole 128-byte lines of a row
+    constexpr bool NT = SRE2_NT_SLAB && ((int)sizeof(C) << CB) >= 128;
     __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
     __shared__ double red[T];
     __shared__ unsigned lh[GEN ? kMaxBins : 1];
@@ -702,7 +708,7 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t r = pdep((uint32_t)i, r0.reg);
-            v[i] = slab_load((src + (((uint64_t)(r >> CB) << L) + (r & CMASK))) + vb);
+            v[i] = slab_load<NT>((src + (((uint64_t)(r >> CB) << L) + (r & CMASK))) + vb);
         }
         run_transform<Real, TB, RB, PK>(lds, v);
         if constexpr (GEN) {

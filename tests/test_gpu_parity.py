@@ -178,6 +178,22 @@ def test_scratch_limit_does_not_change_result():
     assert a.m2 == b.m2 and a.S == b.S  # chunking never changes the summation order
 
 
+def test_scratch_fallback_when_allocation_fails(monkeypatch):
+    """A device that cannot hold the default slab (allocations above 4 GiB
+    fail here) gets smaller chunks, with bitwise the same result."""
+    psi = dev(W.haar(18, 6, np.complex64))  # 2 MiB per shift: 8 GiB chunks by default
+    case_id("scratch-fallback")
+    a = sre2.m2(psi)
+    ctx = sre2.Context(0)
+    ctx.set_timing(True)
+    monkeypatch.setenv("SRE2_FAULT", "alloc_4g")
+    b = sre2.m2(psi, ctx=ctx)
+    launches = ctx.timing_read()["pass1"][1]
+    ctx.close()
+    assert a.m2 == b.m2 and a.S == b.S
+    assert launches == (1 << 18) // 2048  # 4 GiB chunks of 2048 shifts
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         return {}
