@@ -119,8 +119,11 @@ Chunking chunking(int N, int form, bool herm, int64_t x_count, size_t limit) {
     return c;
 }
 
+// Reduction blocks of a state of n amplitudes / shifts: about 1024 values per
+// block (four per thread), so that small states do not wait on one block's
+// long dependent chain; fixed by n, hence part of every result's fixed order.
 int red_blocks(int64_t n) {
-    int64_t b = n >> 14;
+    int64_t b = n >> 10;
     if (b < 1) b = 1;
     if (b > kMaxRed) b = kMaxRed;
     return (int)b;
