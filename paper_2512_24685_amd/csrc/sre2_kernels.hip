@@ -138,6 +138,11 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #ifndef SRE2_FUSEDS_WAVES
 #define SRE2_FUSEDS_WAVES 2
 #endif
+// Half-LDS pass-2 tiles: four waves per SIMD, i.e. at most 128 registers, so
+// that two 512-thread workgroups share a CU.
+#ifndef SRE2_HALF_WAVES
+#define SRE2_HALF_WAVES 4
+#endif
 // Slab traffic: streamed through the caches (no reuse until the other pass).
 #ifndef SRE2_NT_SLAB
 #define SRE2_NT_SLAB 1
@@ -233,19 +238,25 @@ __device__ __forceinline__ C* lds_slot(C* lds, uint32_t pb_bytes, uint32_t r) {
                                 (pb_bytes ^ (lo * (uint32_t)sizeof(C))));
 }
 
-template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
-__device__ __forceinline__ void lds_put(C* lds, const C (&v)[1 << RB]) {
-    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
-#pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) *lds_slot<SB>(lds, pb, pdep((uint32_t)i, REG)) = v[i];
-}
-
-template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, typename C>
-__device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
+// Registers v[OFF + i], i < 2^RB, hold the elements base | pdep(i, REG).
+template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0, typename C,
+          int NV>
+__device__ __forceinline__ void lds_put(C* lds, const C (&v)[NV]) {
+    static_assert(OFF + (1 << RB) <= NV, "registers");
     const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i)
-        v[i] = *lds_slot<SB>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
+        *lds_slot<SB>(lds, pb, pdep((uint32_t)i, REG)) = v[OFF + i];
+}
+
+template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0, typename C,
+          int NV>
+__device__ __forceinline__ void lds_get(const C* lds, C (&v)[NV]) {
+    static_assert(OFF + (1 << RB) <= NV, "registers");
+    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i)
+        v[OFF + i] = *lds_slot<SB>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
 }
 
 // Plan selector (PK encodes the kind so that plans stay constexpr):
@@ -256,6 +267,9 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[1 << RB]) {
 //                   halves; one plan for both), with H_16 factors on the
 //                   matrix cores (pass 1 ends with a round whose lanes run
 //                   over the lowest bits, for the stores)
+//   tiles above 64 KiB (half_lds) take the half-LDS plan in the plain
+//   two-pass kernels (not in the fused kernel, whose threads need more than
+//   the 128 registers that two workgroups per CU leave them)
 template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
     constexpr int SB = Prec<Real>::SB;
@@ -265,9 +279,17 @@ __host__ __device__ constexpr Plan plan_of() {
         if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, SRE2_SPLIT_P1_TAIL);
         return make_split_plan(TB, RB, SB, 0, K - 1000, 2);
     }
-    if (PK >= 3000) return make_plan(TB, RB, SB, TB - (PK - 3000), TB);
-    if (PK >= 2000) return make_plan(TB, RB, SB, 0, TB);
+    constexpr bool H = half_lds<Real>(TB);
+    if (PK >= 3000)
+        return H ? make_plan_half(TB, RB, SB, TB - (PK - 3000))
+                 : make_plan(TB, RB, SB, TB - (PK - 3000), TB);
+    if (PK >= 2000) return H ? make_plan_half(TB, RB, SB, 0) : make_plan(TB, RB, SB, 0, TB);
     return make_plan(TB, RB, SB, 0, PK - 1000);
+}
+
+// LDS values a kernel with plan P declares (1 when it has a single round).
+__host__ __device__ constexpr int lds_values(const Plan& P) {
+    return P.nrounds < 2 ? 1 : (P.half ? 1 << (P.tb - 1) : 1 << P.tb);
 }
 
 template <int TB, int RB, int PK>
@@ -399,10 +421,27 @@ struct RoundRunner {
         if constexpr (J < P.nrounds) {
             constexpr Round prev = P.r[J - 1];
             constexpr Round cur = P.r[J];
-            __syncthreads();  // previous readers of the LDS tile are done
-            lds_put<SB, RB, prev.reg, prev.lperm, prev.wave>(lds, v);
-            __syncthreads();
-            lds_get<SB, RB, cur.reg, cur.lperm, cur.wave>(lds, v);
+            if constexpr (P.half) {
+                // the top tile bit is the top register-index bit of both
+                // layouts: move the registers with that bit 0, then 1,
+                // through half the tile's LDS (slots drop the top bit)
+                constexpr uint32_t low = (1u << (TB - 1)) - 1u;
+                constexpr int HR = 1 << (RB - 1);
+                static_assert((prev.reg >> (TB - 1)) & (cur.reg >> (TB - 1)) & 1u, "half plan");
+                __syncthreads();  // previous readers of the LDS buffer are done
+                lds_put<SB, RB - 1, prev.reg & low, prev.lperm, prev.wave, 0>(lds, v);
+                __syncthreads();
+                lds_get<SB, RB - 1, cur.reg & low, cur.lperm, cur.wave, 0>(lds, v);
+                __syncthreads();
+                lds_put<SB, RB - 1, prev.reg & low, prev.lperm, prev.wave, HR>(lds, v);
+                __syncthreads();
+                lds_get<SB, RB - 1, cur.reg & low, cur.lperm, cur.wave, HR>(lds, v);
+            } else {
+                __syncthreads();  // previous readers of the LDS tile are done
+                lds_put<SB, RB, prev.reg, prev.lperm, prev.wave>(lds, v);
+                __syncthreads();
+                lds_get<SB, RB, cur.reg, cur.lperm, cur.wave>(lds, v);
+            }
             round_math<Real, TB, RB, PK, J>(v, amat);
             RoundRunner<Real, TB, RB, PK, J + 1>::run(lds, v, amat);
         }
@@ -527,7 +566,10 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     constexpr int SPT = 1 << (TB - NT);
     constexpr uint32_t KMASK = (1u << NT) - 1u;
     static_assert((rl.reg & ~KMASK) == 0, "last round: one shift per thread");
-    __shared__ C lds[1 << TB];
+    // the buffer also holds the reduction's 2^(TB - RB) doubles
+    constexpr int NRED = (1 << (TB - RB)) * (int)sizeof(double) / (int)sizeof(C);
+    constexpr int NL = lds_values(P);
+    __shared__ C lds[NL > NRED ? NL : NRED];
     __shared__ unsigned lh[GEN ? kMaxBins : 1];
     double* red = reinterpret_cast<double*>(lds);
     if (pk.count) {
@@ -618,7 +660,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
     constexpr Round r0 = P.r[0];
     constexpr Round rl = P.r[P.nrounds - 1];
-    __shared__ C lds[1 << TB];
+    __shared__ C lds[lds_values(P)];
 
     const int64_t b = blockIdx.x;
     const uint32_t srow = (uint32_t)(b / cs);  // row within the slab
@@ -668,7 +710,8 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // ---------------------------------------------------------------------------
 template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES)))
+__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES
+                                          : (half_lds<Real>(TB) ? SRE2_HALF_WAVES : SRE2_P2_WAVES))))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
     using C = typename CT<Real>::T;
@@ -680,7 +723,7 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     constexpr uint32_t CMASK = (1u << CB) - 1u;
     // streaming loads only when a tile reads whole 128-byte lines of a row
     constexpr bool NT = SRE2_NT_SLAB && ((int)sizeof(C) << CB) >= 128;
-    __shared__ C lds[PL.nrounds > 1 ? (1 << TB) : 1];
+    __shared__ C lds[lds_values(PL)];
     __shared__ double red[T];
     __shared__ unsigned lh[GEN ? kMaxBins : 1];
     Real lnorm2 = Real(0);
@@ -1056,19 +1099,19 @@ template <typename Real, int TB>
 hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, int split, int64_t x0, int cs,
                            void* scratch, const int* se, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int RB = Tune<Real>::RB1;
+    constexpr int RB = pass1_rb<Real>(TB, false), RBS = pass1_rb<Real>(TB, true);
     const int64_t rows = (int64_t)1 << (NS - TB);
-    const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB));
+    const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB)), blocks(1 << (TB - RBS));
     if (herm)
         hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
                            NS, x0, cs, (C*)scratch, se);
     else if (split) {
         if constexpr (sizeof(Real) == 4) {
             if (split == 1)
-                hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 1>), grid, block, 0, st,
+                hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 1>), grid, blocks, 0, st,
                                    (const C*)psi, NS, x0, cs, (C*)scratch, se);
             else
-                hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 2>), grid, block, 0, st,
+                hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 2>), grid, blocks, 0, st,
                                    (const C*)psi, NS, x0, cs, (C*)scratch, se);
         }
     } else

@@ -63,6 +63,10 @@ constexpr int kMaxTileBits = 16;
 
 struct Plan {
     int tb = 0, rb = 0, nrounds = 0;
+    // half: every round holds the top tile bit in its top register-index
+    // bit, so each LDS transpose runs in two phases (register halves with
+    // that bit 0, then 1) through an LDS buffer of half the tile
+    bool half = false;
     Round r[kMaxRounds] = {};
 };
 
@@ -215,6 +219,23 @@ __host__ __device__ constexpr Plan make_plan(int tb, int rb, int sb, int lo, int
         done |= b;
     }
     p.nrounds = k;
+    return p;
+}
+
+// Half-LDS plan for a transform over [lo, tb) of a 2^tb tile (lo < tb - 1):
+// the plan of the lower tb - 1 bits with rb - 1 registers per thread (its
+// lanes, waves, bank residues and round order unchanged), with the top tile
+// bit added to every round's registers as the top register-index bit and
+// butterflied in the first round.  The thread count is that of the full
+// plan, 2^(tb - rb), and each transpose moves half the tile at a time.
+__host__ __device__ constexpr Plan make_plan_half(int tb, int rb, int sb, int lo) {
+    Plan p = make_plan(tb - 1, rb - 1, sb, lo, tb - 1);
+    const uint32_t top = 1u << (tb - 1);
+    for (int j = 0; j < p.nrounds; ++j) p.r[j].reg |= top;
+    p.r[0].bfly |= top;
+    p.tb = tb;
+    p.rb = rb;
+    p.half = true;
     return p;
 }
 

@@ -16,9 +16,9 @@ int geometry(int kind, int param, int* tb, int* rb, int* sb) {
             *tb = sre2::fused_tb<Real>(param);
             *rb = T::RBF;
             return 0;
-        case 1:  // pass 1, param = slab bits NS (0: the smallest row)
+        case 1:  // pass 1, param = slab bits NS (0: the smallest row); plain forms
             *tb = param ? sre2::row_bits_of<Real>(param) : T::ROW;
-            *rb = T::RB1;
+            *rb = sre2::pass1_rb<Real>(*tb, false);
             return 0;
         case 2:  // pass 2, param = H
             if (param < 1 || param > sre2::pass2_max_rows<Real>()) return -1;
@@ -43,12 +43,25 @@ int probe_geometry(int precision, int kind, int param, int* tb, int* rb, int* sb
                           : geometry<double>(kind, param, tb, rb, sb);
 }
 
-// Rounds of a plan, six words each: reg, bfly, lane, wave, lperm, mf.
-// split = 0: FP32 plan; otherwise the split-FP16 plan with tail split - 1
-// (0 none, 1 store round, 2 registers inside [0, hi) at the end).
-int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, unsigned* out) {
-    const sre2::Plan p = split ? sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1)
-                               : sre2::make_plan(tb, rb, sb, lo, hi);
+// Registers per pass-1 thread (log2) for a row of tb bits.
+int probe_pass1_rb(int precision, int tb, int split) {
+    return precision == 0 ? sre2::pass1_rb<float>(tb, split != 0)
+                          : sre2::pass1_rb<double>(tb, split != 0);
+}
+
+// Rounds of a plan, six words each: reg, bfly, lane, wave, lperm, mf, as the
+// kernels select it (sb = 5: complex64 tiles, 4: complex128).  split = 0:
+// plain plan, for a two-pass kernel (two_pass != 0) the half-LDS plan for
+// tiles above 64 KiB; otherwise the split-FP16 plan with tail split - 1
+// (0 none, 1 store round, 2 registers inside [0, hi) at the end).  Returns
+// the round count, plus 100 for a half-LDS plan.
+int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int two_pass, unsigned* out) {
+    const bool half = !split && two_pass && hi == tb && lo < tb - 1 &&
+                      ((sb == 5 && sre2::half_lds<float>(tb)) ||
+                       (sb == 4 && sre2::half_lds<double>(tb)));
+    const sre2::Plan p = split  ? sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1)
+                         : half ? sre2::make_plan_half(tb, rb, sb, lo)
+                                : sre2::make_plan(tb, rb, sb, lo, hi);
     for (int j = 0; j < p.nrounds; ++j) {
         out[6 * j + 0] = p.r[j].reg;
         out[6 * j + 1] = p.r[j].bfly;
@@ -57,7 +70,7 @@ int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, unsigned* out)
         out[6 * j + 4] = p.r[j].lperm;
         out[6 * j + 5] = p.r[j].mf;
     }
-    return p.nrounds;
+    return p.nrounds + (p.half ? 100 : 0);
 }
 
 unsigned probe_swz(int sb, unsigned e) {

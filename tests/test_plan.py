@@ -47,12 +47,28 @@ def geo(lib, precision, kind, param=0):
     return tb.value, rb.value, sb.value
 
 
-def plan(lib, tb, rb, sb, lo, hi, split=0):
-    """Rounds (reg, bfly, lane, wave, lperm, mf); split 0 = FP32 plan, else the
-    split-FP16 plan with tail split - 1 (1: pass-1 store round, 2: fused)."""
+class Rounds(list):
+    """A plan's rounds; half = True for a half-LDS plan (the top tile bit is
+    the top register-index bit of every round and each transpose moves the
+    register halves with that bit 0, then 1, through half the tile)."""
+    half = False
+
+
+def plan(lib, tb, rb, sb, lo, hi, split=0, kind="pass"):
+    """Rounds (reg, bfly, lane, wave, lperm, mf) as the kernels select them;
+    split 0 = plain plan (half-LDS above 64 KiB tiles of the two-pass
+    kernels), else the split-FP16 plan with tail split - 1 (1: pass-1 store
+    round, 2: fused)."""
     out = (ctypes.c_uint * 48)()
-    n = lib.probe_plan(tb, rb, sb, lo, hi, split, out)
-    return [tuple(out[6 * j:6 * j + 6]) for j in range(n)]
+    n = lib.probe_plan(tb, rb, sb, lo, hi, split, int(kind != "fused"), out)
+    r = Rounds(tuple(out[6 * j:6 * j + 6]) for j in range(n % 100))
+    r.half = n >= 100
+    return r
+
+
+def p1rb(lib, prec, L, split=0):
+    """Registers (log2) per pass-1 thread for rows of L bits."""
+    return lib.probe_pass1_rb(prec, L, split)
 
 
 def lane_bits(rd):
@@ -142,13 +158,30 @@ def bfly(V, reg, bf):
 
 def run_tile(X, rounds, tb, rb, sb):
     """Replay tiles through the plan; X is (..., 2^tb), one tile per leading
-    index; returns the tiles after the transform."""
+    index; returns the tiles after the transform.  Half-LDS plans move the
+    two register halves through a buffer of 2^(tb-1) slots (the top tile bit
+    dropped from the slot), as the kernels do."""
     E = [mapping(rd, tb, rb) for rd in rounds]
     V = round_math(X[..., E[0]], rounds[0])
+    half = getattr(rounds, "half", False)
+    top, hr = 1 << (tb - 1), 1 << (rb - 1)
     for j in range(1, len(rounds)):
-        lds = np.full(X.shape[:-1] + (1 << tb,), np.nan + 0j)
-        lds[..., swz_np(sb, E[j - 1])] = V
-        V = round_math(lds[..., swz_np(sb, E[j])], rounds[j])
+        if not half:
+            lds = np.full(X.shape[:-1] + (1 << tb,), np.nan + 0j)
+            lds[..., swz_np(sb, E[j - 1])] = V
+            V = round_math(lds[..., swz_np(sb, E[j])], rounds[j])
+            continue
+        W = np.empty_like(V)
+        for h in (0, 1):
+            regs = slice(h * hr, (h + 1) * hr)
+            # the register half holds exactly the elements with top bit h
+            assert np.all((E[j - 1][:, regs] & top) == h * top)
+            assert np.all((E[j][:, regs] & top) == h * top)
+            lds = np.full(X.shape[:-1] + (top,), np.nan + 0j)
+            lds[..., swz_np(sb, E[j - 1][:, regs] & (top - 1))] = V[..., regs]
+            W[..., regs] = lds[..., swz_np(sb, E[j][:, regs] & (top - 1))]
+            assert not np.isnan(W[..., regs]).any()
+        V = round_math(W, rounds[j])
     out = np.empty_like(X)
     out[..., E[-1]] = V
     return out
@@ -190,9 +223,9 @@ def all_plans(lib):
                 L = geo(lib, prec, PASS1, NS)[0]
                 rows.add(L)
                 hs.add(NS - L)
-            _, rb1, sb = geo(lib, prec, PASS1)
+            sb = geo(lib, prec, PASS1)[2]
             for L in sorted(rows):
-                yield prec, "pass1", L, (L, rb1, sb, 0, L, 2 * split)
+                yield prec, "pass1", L, (L, p1rb(lib, prec, L, split), sb, 0, L, 2 * split)
             for H in sorted(hs):
                 tb, rb, sb = geo(lib, prec, PASS2, H)
                 yield prec, "pass2", H, (tb, rb, sb, tb - H, tb, split)
@@ -220,7 +253,7 @@ def test_geometry_limits(probe):
 def test_plan_structure(probe):
     for prec, kind, par, args in all_plans(probe):
         tb, rb, sb, lo, hi, split = args
-        rounds = plan(probe, *args)
+        rounds = plan(probe, *args, kind=kind)
         full = (1 << tb) - 1
         tmask = sum(1 << b for b in range(lo, hi))
         seen = 0
@@ -241,6 +274,12 @@ def test_plan_structure(probe):
                 assert bin(mf & reg).count("1") == 2
             seen |= bf | mf
         assert seen == tmask, case
+        # tiles above 64 KiB transpose through half the LDS (plain forms)
+        big = (8 if prec == 0 else 16) << tb > 65536
+        assert rounds.half == (big and not split and kind != "fused"), case
+        if rounds.half:
+            assert all((reg >> (tb - 1)) & 1 for reg, *_ in rounds), case
+            assert rounds[0][1] >> (tb - 1) & 1, case  # butterflied in the first round
         if kind == "fused":  # last round holds one shift per thread
             assert rounds[-1][0] & ~((1 << par) - 1) == 0, case
         if split == 2:  # pass-1 store round: lanes on the lowest bits
@@ -277,11 +316,12 @@ def test_lds_bank_slots_distinct(probe):
     factor bits, and too few bits are left to choose them from."""
     for prec, kind, par, args in all_plans(probe):
         tb, rb, sb, lo, hi, split = args
-        rounds = plan(probe, *args)
+        rounds = plan(probe, *args, kind=kind)
         if len(rounds) == 1:
             continue
         for j, rd in enumerate(rounds):
-            E = swz_np(sb, mapping(rd, tb, rb))
+            M = mapping(rd, tb, rb)
+            E = swz_np(sb, M & ((1 << (tb - 1)) - 1) if rounds.half else M)
             slots = E & ((1 << sb) - 1)
             g = 1 << sb
             T = E.shape[0]
@@ -302,7 +342,7 @@ def test_tile_transform_matches_wht(probe):
     rng = np.random.default_rng(3)
     for prec, kind, par, (tb, rb, sb, lo, hi, split) in all_plans(probe):
         X = rng.standard_normal(1 << tb) + 1j * rng.standard_normal(1 << tb)
-        out = run_tile(X, plan(probe, tb, rb, sb, lo, hi, split), tb, rb, sb)
+        out = run_tile(X, plan(probe, tb, rb, sb, lo, hi, split, kind), tb, rb, sb)
         assert np.allclose(out, wht_bits(X, lo, hi)), (prec, kind, par, split)
 
 
@@ -321,7 +361,7 @@ def emulate_fused_partials(probe, psi, prec, herm=False, x_begin=0, split=0):
     N = psi.size.bit_length() - 1
     NT = N - int(herm)
     tb, rb, sb = geo(probe, prec, FUSED, NT)
-    rounds = plan(probe, tb, rb, sb, 0, NT, 3 * split)
+    rounds = plan(probe, tb, rb, sb, 0, NT, 3 * split, kind="fused")
     spt = 1 << (tb - NT)
     d = 1 << N
     S = {}
@@ -348,8 +388,9 @@ def emulate_two_pass_partials(probe, psi, prec, xs, herm=False, split=0, L=None)
     L overrides the slab's pass-1 row bits (the kernels are generic in it)."""
     N = psi.size.bit_length() - 1
     NS = N - int(herm)
-    L0, rb1, sb = geo(probe, prec, PASS1, NS)
+    L0, _, sb = geo(probe, prec, PASS1, NS)
     L = L0 if L is None else L
+    rb1 = p1rb(probe, prec, L, split)
     HT = NS - L
     tb2, rb2, _ = geo(probe, prec, PASS2, HT)
     p1 = plan(probe, L, rb1, sb, 0, L, 2 * split)
@@ -382,6 +423,19 @@ def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N, herm, split):
     S = emulate_fused_partials(probe, psi, prec, herm, x0, split)
     ref = oracle_mod.partials(psi)[x0:]
     assert np.allclose(S, ref, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_largest_tiles_match_oracle(probe, oracle_mod, prec):
+    """The largest fused tile (2^14 complex64 / 2^13 complex128, full LDS)
+    on its last shifts."""
+    N = geo(probe, prec, LIMITS)[0]
+    tb, rb, sb = geo(probe, prec, FUSED, N)
+    assert not plan(probe, tb, rb, sb, 0, N, kind="fused").half
+    psi = W.haar(N, 77)
+    x0 = (1 << N) - 3
+    S = emulate_fused_partials(probe, psi, prec, False, x0)
+    assert np.allclose(S, oracle_mod.partials(psi, np.arange(x0, 1 << N)), rtol=1e-11, atol=0)
 
 
 @pytest.mark.parametrize("prec,extra,herm,split", [
