@@ -100,17 +100,18 @@ constexpr int row_bits_of(int NS) {
 }
 
 // Two-pass tiles above 64 KiB (2^14 complex64, 2^13 complex128) transpose
-// through half the LDS (make_plan_half), so that two workgroups fit a CU; the
-// split MFMA plans and the fused kernel keep full tiles.  Pass 1 then takes one more register bit per thread
-// so that the thread count, and with it the round count, stays that of the
-// smaller tile.
+// through half the LDS (make_plan_half, make_split_plan_half), so that two
+// workgroups fit a CU; the fused kernel keeps full tiles.  Pass 1 then takes
+// one more register bit per thread so that the thread count, and with it the
+// round count, stays that of the smaller tile.
 template <typename Real>
 constexpr bool half_lds(int tb) {
     return ((int64_t)(2 * sizeof(Real)) << tb) > 65536;
 }
 template <typename Real>
 constexpr int pass1_rb(int tb, bool split) {
-    return Tune<Real>::RB1 + (half_lds<Real>(tb) && !split ? 1 : 0);
+    (void)split;  // the split form takes the same geometry
+    return Tune<Real>::RB1 + (half_lds<Real>(tb) ? 1 : 0);
 }
 
 template <typename Real>

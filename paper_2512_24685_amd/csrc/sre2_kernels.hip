@@ -138,8 +138,8 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #ifndef SRE2_FUSEDS_WAVES
 #define SRE2_FUSEDS_WAVES 2
 #endif
-// Half-LDS pass-2 tiles: four waves per SIMD, i.e. at most 128 registers, so
-// that two 512-thread workgroups share a CU.
+// Half-LDS two-pass tiles: four waves per SIMD, i.e. at most 128 registers,
+// so that two 512-thread workgroups share a CU.
 #ifndef SRE2_HALF_WAVES
 #define SRE2_HALF_WAVES 4
 #endif
@@ -267,19 +267,23 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[NV]) {
 //                   halves; one plan for both), with H_16 factors on the
 //                   matrix cores (pass 1 ends with a round whose lanes run
 //                   over the lowest bits, for the stores)
-//   tiles above 64 KiB (half_lds) take the half-LDS plan in the plain
-//   two-pass kernels (not in the fused kernel, whose threads need more than
-//   the 128 registers that two workgroups per CU leave them)
+//   tiles above 64 KiB (half_lds) take half-LDS plans in the two-pass
+//   kernels (not in the fused kernel, whose threads need more than the 128
+//   registers that two workgroups per CU leave them)
 template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
     constexpr int SB = Prec<Real>::SB;
+    constexpr bool H = half_lds<Real>(TB);
     if (PK >= 10000) {
         constexpr int K = PK % 10000;
-        if (K >= 3000) return make_split_plan(TB, RB, SB, TB - (K - 3000), TB, 0);
-        if (K >= 2000) return make_split_plan(TB, RB, SB, 0, TB, SRE2_SPLIT_P1_TAIL);
+        if (K >= 3000)
+            return H ? make_split_plan_half(TB, RB, SB, TB - (K - 3000), 0)
+                     : make_split_plan(TB, RB, SB, TB - (K - 3000), TB, 0);
+        if (K >= 2000)
+            return H ? make_split_plan_half(TB, RB, SB, 0, SRE2_SPLIT_P1_TAIL)
+                     : make_split_plan(TB, RB, SB, 0, TB, SRE2_SPLIT_P1_TAIL);
         return make_split_plan(TB, RB, SB, 0, K - 1000, 2);
     }
-    constexpr bool H = half_lds<Real>(TB);
     if (PK >= 3000)
         return H ? make_plan_half(TB, RB, SB, TB - (PK - 3000))
                  : make_plan(TB, RB, SB, TB - (PK - 3000), TB);
@@ -652,7 +656,8 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // ---------------------------------------------------------------------------
 template <typename Real, int TB, int RB, bool HERM, int SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES)))
+__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? SRE2_HALF_WAVES
+                                   : (SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES))))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
     using C = typename CT<Real>::T;
@@ -710,8 +715,8 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // ---------------------------------------------------------------------------
 template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_P2S_WAVES
-                                          : (half_lds<Real>(TB) ? SRE2_HALF_WAVES : SRE2_P2_WAVES))))
+__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? SRE2_HALF_WAVES
+                                   : (SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES))))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
     using C = typename CT<Real>::T;

@@ -478,4 +478,19 @@ template <> struct Prec<double> {
     static constexpr int MAXTB = 13;  // 2^13 complex128 = 128 KiB
 };
 
+
+// Half-LDS split plan (see make_plan_half): the split plan of the lower
+// tb - 1 bits with rb - 1 registers per thread, plus the top tile bit as the
+// top register-index bit of every round, butterflied in FP32 in the first.
+__host__ __device__ constexpr Plan make_split_plan_half(int tb, int rb, int sb, int lo, int tail) {
+    Plan p = make_split_plan(tb - 1, rb - 1, sb, lo, tb - 1, tail);
+    const uint32_t top = 1u << (tb - 1);
+    for (int j = 0; j < p.nrounds; ++j) p.r[j].reg |= top;
+    p.r[0].bfly |= top;
+    p.tb = tb;
+    p.rb = rb;
+    p.half = true;
+    return p;
+}
+
 }  // namespace sre2

@@ -51,17 +51,18 @@ int probe_pass1_rb(int precision, int tb, int split) {
 
 // Rounds of a plan, six words each: reg, bfly, lane, wave, lperm, mf, as the
 // kernels select it (sb = 5: complex64 tiles, 4: complex128).  split = 0:
-// plain plan, for a two-pass kernel (two_pass != 0) the half-LDS plan for
-// tiles above 64 KiB; otherwise the split-FP16 plan with tail split - 1
-// (0 none, 1 store round, 2 registers inside [0, hi) at the end).  Returns
-// the round count, plus 100 for a half-LDS plan.
+// plain plan, otherwise the split-FP16 plan with tail split - 1 (0 none,
+// 1 store round, 2 registers inside [0, hi) at the end); for a two-pass
+// kernel (two_pass != 0) the half-LDS version for tiles above 64 KiB.
+// Returns the round count, plus 100 for a half-LDS plan.
 int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int two_pass, unsigned* out) {
-    const bool half = !split && two_pass && hi == tb && lo < tb - 1 &&
+    const bool half = two_pass && hi == tb && lo < tb - 1 &&
                       ((sb == 5 && sre2::half_lds<float>(tb)) ||
                        (sb == 4 && sre2::half_lds<double>(tb)));
-    const sre2::Plan p = split  ? sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1)
-                         : half ? sre2::make_plan_half(tb, rb, sb, lo)
-                                : sre2::make_plan(tb, rb, sb, lo, hi);
+    const sre2::Plan p =
+        split ? (half ? sre2::make_split_plan_half(tb, rb, sb, lo, split - 1)
+                      : sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1))
+              : (half ? sre2::make_plan_half(tb, rb, sb, lo) : sre2::make_plan(tb, rb, sb, lo, hi));
     for (int j = 0; j < p.nrounds; ++j) {
         out[6 * j + 0] = p.r[j].reg;
         out[6 * j + 1] = p.r[j].bfly;

@@ -56,9 +56,9 @@ class Rounds(list):
 
 def plan(lib, tb, rb, sb, lo, hi, split=0, kind="pass"):
     """Rounds (reg, bfly, lane, wave, lperm, mf) as the kernels select them;
-    split 0 = plain plan (half-LDS above 64 KiB tiles of the two-pass
-    kernels), else the split-FP16 plan with tail split - 1 (1: pass-1 store
-    round, 2: fused)."""
+    split 0 = plain plan, else the split-FP16 plan with tail split - 1 (1:
+    pass-1 store round, 2: fused); half-LDS above 64 KiB tiles of the
+    two-pass kernels."""
     out = (ctypes.c_uint * 48)()
     n = lib.probe_plan(tb, rb, sb, lo, hi, split, int(kind != "fused"), out)
     r = Rounds(tuple(out[6 * j:6 * j + 6]) for j in range(n % 100))
@@ -276,7 +276,7 @@ def test_plan_structure(probe):
         assert seen == tmask, case
         # tiles above 64 KiB transpose through half the LDS (plain forms)
         big = (8 if prec == 0 else 16) << tb > 65536
-        assert rounds.half == (big and not split and kind != "fused"), case
+        assert rounds.half == (big and kind != "fused"), case
         if rounds.half:
             assert all((reg >> (tb - 1)) & 1 for reg, *_ in rounds), case
             assert rounds[0][1] >> (tb - 1) & 1, case  # butterflied in the first round
