@@ -101,9 +101,9 @@ constexpr int row_bits_of(int NS) {
 
 // Two-pass tiles above 64 KiB (2^14 complex64, 2^13 complex128) transpose
 // through half the LDS (make_plan_half, make_split_plan_half), so that two
-// workgroups fit a CU; the fused kernel keeps full tiles.  Pass 1 then takes
-// one more register bit per thread so that the thread count, and with it the
-// round count, stays that of the smaller tile.
+// workgroups fit a CU; pass 1 then takes one more register bit per thread, so
+// that the round count stays that of the smaller tile.  Fused tiles: see
+// fused_half.
 template <typename Real>
 constexpr bool half_lds(int tb) {
     return ((int64_t)(2 * sizeof(Real)) << tb) > 65536;
@@ -117,6 +117,30 @@ constexpr int pass1_rb(int tb, bool split) {
 template <typename Real>
 constexpr int fused_tb(int N) {
     return N > Tune<Real>::FMIN ? N : Tune<Real>::FMIN;
+}
+// Half-LDS fused tiles (plain forms) take SRE2_FUSED_HALF_RB more register
+// bits per thread.  Measured on the largest tiles: the FP64 one (2^13) runs
+// 1.7x faster so; the FP32 one (2^14, 64 values per thread) spills at the
+// 256 registers that two workgroups per CU leave and runs 1.7x slower, so it
+// keeps its full tile.
+#ifndef SRE2_F32_FUSED_HALF
+#define SRE2_F32_FUSED_HALF 0
+#endif
+#ifndef SRE2_F64_FUSED_HALF
+#define SRE2_F64_FUSED_HALF 1
+#endif
+#ifndef SRE2_FUSED_HALF_RB
+#define SRE2_FUSED_HALF_RB 1
+#endif
+template <typename Real>
+constexpr bool fused_half(int N) {
+    return (sizeof(Real) == 4 ? SRE2_F32_FUSED_HALF : SRE2_F64_FUSED_HALF) &&
+           half_lds<Real>(fused_tb<Real>(N)) && N == fused_tb<Real>(N);
+}
+// Registers (log2) per fused thread for transforms of N bits.
+template <typename Real>
+constexpr int fused_rb(int N, bool split) {
+    return Tune<Real>::RBF + (!split && fused_half<Real>(N) ? SRE2_FUSED_HALF_RB : 0);
 }
 template <typename Real>
 constexpr int pass2_tb(int H) {

@@ -139,7 +139,11 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #define SRE2_FUSEDS_WAVES 2
 #endif
 // Half-LDS two-pass tiles: four waves per SIMD, i.e. at most 128 registers,
-// so that two 512-thread workgroups share a CU.
+// so that two 512-thread workgroups share a CU; the half-LDS fused tile (256
+// threads of 64 values) needs two waves per SIMD for two workgroups.
+#ifndef SRE2_FUSEDH_WAVES
+#define SRE2_FUSEDH_WAVES 2
+#endif
 #ifndef SRE2_HALF_WAVES
 #define SRE2_HALF_WAVES 4
 #endif
@@ -267,9 +271,8 @@ __device__ __forceinline__ void lds_get(const C* lds, C (&v)[NV]) {
 //                   halves; one plan for both), with H_16 factors on the
 //                   matrix cores (pass 1 ends with a round whose lanes run
 //                   over the lowest bits, for the stores)
-//   tiles above 64 KiB (half_lds) take half-LDS plans in the two-pass
-//   kernels (not in the fused kernel, whose threads need more than the 128
-//   registers that two workgroups per CU leave them)
+//   tiles above 64 KiB (half_lds) take half-LDS plans (not the fused split
+//   form); the fused kernel's then hold 64 values per thread
 template <typename Real, int TB, int RB, int PK>
 __host__ __device__ constexpr Plan plan_of() {
     constexpr int SB = Prec<Real>::SB;
@@ -288,7 +291,8 @@ __host__ __device__ constexpr Plan plan_of() {
         return H ? make_plan_half(TB, RB, SB, TB - (PK - 3000))
                  : make_plan(TB, RB, SB, TB - (PK - 3000), TB);
     if (PK >= 2000) return H ? make_plan_half(TB, RB, SB, 0) : make_plan(TB, RB, SB, 0, TB);
-    return make_plan(TB, RB, SB, 0, PK - 1000);
+    return fused_half<Real>(PK - 1000) ? make_plan_half(TB, RB, SB, 0)
+                                       : make_plan(TB, RB, SB, 0, PK - 1000);
 }
 
 // LDS values a kernel with plan P declares (1 when it has a single round).
@@ -557,7 +561,9 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 // ---------------------------------------------------------------------------
 template <typename Real, int NT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES : SRE2_FUSED_WAVES)))
+__attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES
+                                   : (fused_half<Real>(NT) ? SRE2_FUSEDH_WAVES
+                                                           : SRE2_FUSED_WAVES))))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out, const int* __restrict__ scale_exp,
              const Pack pk, const Spec sp) {
@@ -594,7 +600,23 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t x0 = x_begin + tile * SPT;  // first shift of the tile
         C v[1 << RB];
-        {
+        if constexpr (SPT == 1 && !HERM) {
+            // one shift per tile, k = e = base | r (disjoint bits): as in
+            // pass 1, k ^ x = (base ^ (x outside REG)) + (r ^ (x inside REG)),
+            // so the per-element address parts are uniform
+            const uint32_t x = (uint32_t)x0;
+            const uint32_t base = thread_base<r0.lperm, r0.wave>();
+            const uint32_t vb = base ^ (x & ~r0.reg), xr = x & r0.reg;
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                const uint32_t r = pdep((uint32_t)i, r0.reg);
+                v[i] = cmul_conj_a((psi + (r ^ xr))[vb], (psi + r)[base]);
+                if constexpr (SPLIT) {
+                    v[i].x *= sc;
+                    v[i].y *= sc;
+                }
+            }
+        } else {
             const uint32_t base = thread_base<r0.lperm, r0.wave>();
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) {
@@ -957,7 +979,7 @@ template <typename Real, int NT, bool HERM, int SPLIT, bool GEN>
 hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, const int* se,
                            const Pack& pk, const Spec& sp, hipStream_t st) {
     using C = typename CT<Real>::T;
-    constexpr int TB = fused_tb<Real>(NT), RB = Tune<Real>::RBF;
+    constexpr int TB = fused_tb<Real>(NT), RB = fused_rb<Real>(NT, SPLIT != 0);
     constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
     const int64_t grid = ntiles < 65536 ? ntiles : 65536;

@@ -14,7 +14,7 @@ int geometry(int kind, int param, int* tb, int* rb, int* sb) {
         case 0:  // fused, param = N
             if (param < T::RBF || param > T::FMAX) return -1;
             *tb = sre2::fused_tb<Real>(param);
-            *rb = T::RBF;
+            *rb = sre2::fused_rb<Real>(param, false);
             return 0;
         case 1:  // pass 1, param = slab bits NS (0: the smallest row); plain forms
             *tb = param ? sre2::row_bits_of<Real>(param) : T::ROW;
@@ -43,6 +43,12 @@ int probe_geometry(int precision, int kind, int param, int* tb, int* rb, int* sb
                           : geometry<double>(kind, param, tb, rb, sb);
 }
 
+// Registers per fused thread (log2) for transforms of N bits.
+int probe_fused_rb(int precision, int N, int split) {
+    return precision == 0 ? sre2::fused_rb<float>(N, split != 0)
+                          : sre2::fused_rb<double>(N, split != 0);
+}
+
 // Registers per pass-1 thread (log2) for a row of tb bits.
 int probe_pass1_rb(int precision, int tb, int split) {
     return precision == 0 ? sre2::pass1_rb<float>(tb, split != 0)
@@ -50,15 +56,18 @@ int probe_pass1_rb(int precision, int tb, int split) {
 }
 
 // Rounds of a plan, six words each: reg, bfly, lane, wave, lperm, mf, as the
-// kernels select it (sb = 5: complex64 tiles, 4: complex128).  split = 0:
-// plain plan, otherwise the split-FP16 plan with tail split - 1 (0 none,
-// 1 store round, 2 registers inside [0, hi) at the end); for a two-pass
-// kernel (two_pass != 0) the half-LDS version for tiles above 64 KiB.
-// Returns the round count, plus 100 for a half-LDS plan.
-int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int two_pass, unsigned* out) {
-    const bool half = two_pass && hi == tb && lo < tb - 1 &&
-                      ((sb == 5 && sre2::half_lds<float>(tb)) ||
-                       (sb == 4 && sre2::half_lds<double>(tb)));
+// kernel of `kind` (0 fused, 1 pass 1, 2 pass 2) selects it (sb = 5:
+// complex64 tiles, 4: complex128).  split = 0: plain plan, otherwise the
+// split-FP16 plan with tail split - 1 (0 none, 1 store round, 2 registers
+// inside [0, hi) at the end); half-LDS plans for the two-pass tiles above
+// 64 KiB and the fused tiles of fused_half.  Returns the round count, plus
+// 100 for a half-LDS plan.
+int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int kind, unsigned* out) {
+    const bool f32 = sb == 5;
+    const bool big = f32 ? sre2::half_lds<float>(tb) : sre2::half_lds<double>(tb);
+    const bool half =
+        kind == 0 ? !split && (f32 ? sre2::fused_half<float>(hi) : sre2::fused_half<double>(hi))
+                  : big && hi == tb && lo < tb - 1;
     const sre2::Plan p =
         split ? (half ? sre2::make_split_plan_half(tb, rb, sb, lo, split - 1)
                       : sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1))

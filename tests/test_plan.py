@@ -54,16 +54,24 @@ class Rounds(list):
     half = False
 
 
-def plan(lib, tb, rb, sb, lo, hi, split=0, kind="pass"):
-    """Rounds (reg, bfly, lane, wave, lperm, mf) as the kernels select them;
-    split 0 = plain plan, else the split-FP16 plan with tail split - 1 (1:
-    pass-1 store round, 2: fused); half-LDS above 64 KiB tiles of the
-    two-pass kernels."""
+KINDS = {"fused": 0, "pass1": 1, "pass2": 2}
+
+
+def plan(lib, tb, rb, sb, lo, hi, split=0, kind="pass1"):
+    """Rounds (reg, bfly, lane, wave, lperm, mf) as the kernel of `kind`
+    selects them; split 0 = plain plan, else the split-FP16 plan with tail
+    split - 1 (1: pass-1 store round, 2: fused); half-LDS plans for two-pass
+    tiles above 64 KiB and for the largest plain fused tiles."""
     out = (ctypes.c_uint * 48)()
-    n = lib.probe_plan(tb, rb, sb, lo, hi, split, int(kind != "fused"), out)
+    n = lib.probe_plan(tb, rb, sb, lo, hi, split, KINDS[kind], out)
     r = Rounds(tuple(out[6 * j:6 * j + 6]) for j in range(n % 100))
     r.half = n >= 100
     return r
+
+
+def fusedrb(lib, prec, N, split=0):
+    """Registers (log2) per fused thread for transforms of N bits."""
+    return lib.probe_fused_rb(prec, N, split)
 
 
 def p1rb(lib, prec, L, split=0):
@@ -212,11 +220,11 @@ def all_plans(lib):
     uses; the split form exists for complex64 tiles only."""
     for prec in (0, 1):
         fmax, row, nmax = geo(lib, prec, LIMITS)
-        rbf = geo(lib, prec, FUSED, fmax)[1]
+        rbf = fusedrb(lib, prec, 1)  # smallest fused N
         for split in ((0, 1) if prec == 0 else (0,)):
             for N in range(rbf, fmax + 1):
-                tb, rb, sb = geo(lib, prec, FUSED, N)
-                yield prec, "fused", N, (tb, rb, sb, 0, N, 3 * split)
+                tb, _, sb = geo(lib, prec, FUSED, N)
+                yield prec, "fused", N, (tb, fusedrb(lib, prec, N, split), sb, 0, N, 3 * split)
             assert geo(lib, prec, PASS1)[0] == row
             rows, hs = set(), set()
             for NS in range(fmax, nmax + 1):  # every slab size of two-pass
@@ -276,7 +284,10 @@ def test_plan_structure(probe):
         assert seen == tmask, case
         # tiles above 64 KiB transpose through half the LDS (plain forms)
         big = (8 if prec == 0 else 16) << tb > 65536
-        assert rounds.half == (big and kind != "fused"), case
+        if kind != "fused":
+            assert rounds.half == (big and hi == tb), case
+        elif rounds.half:
+            assert big and hi == tb and not split, case
         if rounds.half:
             assert all((reg >> (tb - 1)) & 1 for reg, *_ in rounds), case
             assert rounds[0][1] >> (tb - 1) & 1, case  # butterflied in the first round
@@ -360,8 +371,9 @@ def emulate_fused_partials(probe, psi, prec, herm=False, x_begin=0, split=0):
     """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-NT) shifts)."""
     N = psi.size.bit_length() - 1
     NT = N - int(herm)
-    tb, rb, sb = geo(probe, prec, FUSED, NT)
-    rounds = plan(probe, tb, rb, sb, 0, NT, 3 * split, kind="fused")
+    tb, _, sb = geo(probe, prec, FUSED, NT)
+    rb = fusedrb(probe, prec, NT, split)
+    rounds = plan(probe, tb, rb, sb, 0, NT, 3 * split, "fused")
     spt = 1 << (tb - NT)
     d = 1 << N
     S = {}
@@ -393,8 +405,8 @@ def emulate_two_pass_partials(probe, psi, prec, xs, herm=False, split=0, L=None)
     rb1 = p1rb(probe, prec, L, split)
     HT = NS - L
     tb2, rb2, _ = geo(probe, prec, PASS2, HT)
-    p1 = plan(probe, L, rb1, sb, 0, L, 2 * split)
-    p2 = plan(probe, tb2, rb2, sb, tb2 - HT, tb2, split)
+    p1 = plan(probe, L, rb1, sb, 0, L, 2 * split, "pass1")
+    p2 = plan(probe, tb2, rb2, sb, tb2 - HT, tb2, split, "pass2")
     e1 = np.arange(1 << L)
     e2 = np.arange(1 << tb2)
     cb = tb2 - HT
@@ -427,11 +439,11 @@ def test_fused_indexing_matches_oracle(probe, oracle_mod, prec, N, herm, split):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fused_largest_tiles_match_oracle(probe, oracle_mod, prec):
-    """The largest fused tile (2^14 complex64 / 2^13 complex128, full LDS)
-    on its last shifts."""
+    """The largest fused tile (2^14 complex64 / 2^13 complex128) on its
+    last shifts, in the plan and register count the kernel takes."""
     N = geo(probe, prec, LIMITS)[0]
     tb, rb, sb = geo(probe, prec, FUSED, N)
-    assert not plan(probe, tb, rb, sb, 0, N, kind="fused").half
+    assert rb == fusedrb(probe, prec, N)
     psi = W.haar(N, 77)
     x0 = (1 << N) - 3
     S = emulate_fused_partials(probe, psi, prec, False, x0)
