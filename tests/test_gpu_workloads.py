@@ -85,6 +85,8 @@ def test_n20_snapshot_sequence(form):
         assert r.status == 0
         m[t] = r.m2
         rec = g.get(f"ising20_t{t}")
+        if t in (5, 21):  # stored oracle values (tests/golden)
+            assert rec and rec["sha256"] == sha(psi), t
         if rec and rec["sha256"] == sha(psi):
             assert abs(r.m2 - rec["m2"]) <= 1e-5, t
     for t in (0, 16, 32, 48):

@@ -143,7 +143,25 @@ def test_ising_snapshot_clifford_points_and_symmetries(oracle_mod):
     for t in range(1, 32):
         assert abs(m[t] - m[t + 32]) < 1e-11
         assert abs(m[t] - m[32 - t]) < 1e-11
+    # theta -> pi/4 - theta: psi becomes a diagonal Clifford (the bond phases
+    # at pi/4) times conj(psi), so M2(t) = M2(16 - t)
+    for t in range(1, 16):
+        assert abs(m[t] - m[16 - t]) < 1e-11
     assert max(m.values()) > 0.5  # non-trivial away from Clifford angles
+
+
+def test_stored_n20_snapshots_obey_the_reflections():
+    """The oracle's stored N = 20 snapshot values at t = 5 and 21 (computed
+    independently, hours apart) agree as M2(t) = M2(16 - t) = M2(32 - t)
+    requires: 21 -> 11 -> 5."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_values.json")
+    with open(path) as f:
+        g = json.load(f)
+    assert abs(g["ising20_t5"]["m2"] - g["ising20_t21"]["m2"]) < 1e-12
+    assert g["ising20_t5"]["m2"] > 1.0
 
 
 def test_additivity(oracle_mod):
