@@ -119,3 +119,4 @@ def test_spectrum_haar_matches_oracle(oracle_mod, form, N):
     ref, near = oracle_mod.spectrum(psi, nbins, eps=2e-3 if not c128 else 1e-7)
     diff = int(np.abs(counts - ref).sum())
     assert diff <= 2 * near, (diff, near)
+
