@@ -18,6 +18,12 @@
 //              per-workgroup FP64 partial sum; nothing is written back.
 //  k_convert / k_norm_part / k_sum_part / k_final: input staging, FP64 norm,
 //              fixed-order FP64 reductions and the logarithm.
+//  k_moment_part / k_moment_final: sum |psi|^2, sum |psi|^4 and non-finite
+//              count of an input (sre2_moments).
+//
+// Forms: FP32 or FP64 butterflies; the Hermitian pair (half the transform
+// of shifts x >= 1); the split forms, whose H_16 factors run on the matrix
+// cores with FP16 or BF16 hi/lo halves (SPLIT = 1, 2).
 //
 // Accumulation: |W|^2 is formed in the working precision, squared and summed
 // in FP64 per element; per-thread sums are combined by fixed-shape trees, so a

@@ -20,6 +20,11 @@
 // order, but lane bit SB-1 must map onto slot bit SB-1.  So lane bit i of
 // every round sits on a tile bit of residue i mod SB (i < SB), or at least
 // lane bits 0..SB-2 on residues 0..SB-2 and lane bit SB-1 on residue SB-1.
+//
+// Tiles above 64 KiB would leave one workgroup per CU (160 KiB of LDS); their
+// half-LDS plans keep the top tile bit in every round's registers, so each
+// transpose moves half the tile at a time through a buffer of 2^(TB-1)
+// slots (make_plan_half).
 #pragma once
 #include <stdint.h>
 
