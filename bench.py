@@ -152,6 +152,7 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
 
 
 SCRATCH_LIMIT = 0  # bytes; 0 keeps the library default
+LAST_STEPS = None  # per-step ms (min, median, max) of the last measure()
 
 
 def new_context(sre2):
@@ -170,12 +171,15 @@ def measure(sre2, torch, d_psi, form, steps, warmup):
         log(f"[{form}] warmup {i}: M2={out[0].item():.10f}")
     ctx.set_timing(True)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    outs = [sre2.m2_async(d_psi, form=form, ctx=ctx)[0] for _ in range(steps)]
-    ev1.record(stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    outs = []
+    for i in range(steps):
+        outs.append(sre2.m2_async(d_psi, form=form, ctx=ctx)[0])
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
+    elapsed_ms = evs[0].elapsed_time(evs[-1])
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     kt = ctx.timing_read()
     ctx.set_timing(False)
     m2s = [o[0].item() for o in outs]
@@ -184,6 +188,9 @@ def measure(sre2, torch, d_psi, form, steps, warmup):
     cs, P = ctx.chunking(d_psi.numel().bit_length() - 1, form)
     ctx.close()
     log(f"[{form}] {steps} steps: {elapsed_ms:.1f} ms; M2={m2s[0]:.12f}; kernels={kt}")
+    global LAST_STEPS
+    LAST_STEPS = {"min": round(per_step[0], 3), "median": round(per_step[len(per_step) // 2], 3),
+                  "max": round(per_step[-1], 3)}
     return elapsed_ms / steps, m2s[0], kt, cs, P
 
 
@@ -430,6 +437,7 @@ def main():
         return
 
     ms_per_step, m2, kt, cs, P = measure(sre2, torch, d_psi, args.form, args.steps, args.warmup)
+    step_ms = LAST_STEPS
     value = float(4 ** N) / (ms_per_step / 1e3)
     dom = max((k for k in kt if k != "aux" and kt[k][1] > 0), key=lambda k: kt[k][0])
     kname = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[dom]
@@ -440,9 +448,11 @@ def main():
     forms = {}
     for f in [x for x in args.also.split(",") if x and x != args.form]:
         fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, max(1, args.steps // 2), 1)
+        fsteps = LAST_STEPS
         fdom = max((k for k in fkt if k != "aux" and fkt[k][1] > 0), key=lambda k: fkt[k][0])
         fk = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[fdom]
-        forms[f] = {"value": float(4 ** N) / (fms / 1e3), "ms_per_step": fms, "M2": fm2,
+        forms[f] = {"value": float(4 ** N) / (fms / 1e3), "ms_per_step": fms, "step_ms": fsteps,
+                    "M2": fm2,
                     "abs_dM2_vs_headline": abs(fm2 - m2),
                     "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1], fcs,
                                          stored_traffic(fk, N, f),
@@ -481,7 +491,7 @@ def main():
                                   if dom != "shift" else
                                   "whole transforms in one workgroup's LDS (fused kernel)"),
                    "N": N, "pauli_strings_per_step": 4 ** N, "form": args.form,
-                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2},
+                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2, "step_ms": step_ms},
         "roofline": roof,
         "forms": forms,
         "serving": serving,
