@@ -104,14 +104,20 @@ constexpr int row_bits_of(int NS) {
 // workgroups fit a CU; pass 1 then takes one more register bit per thread, so
 // that the round count stays that of the smaller tile.  Fused tiles: see
 // fused_half.
+#ifndef SRE2_HALF_ABOVE
+#define SRE2_HALF_ABOVE 65536  // bytes of a tile above which it goes half-LDS
+#endif
+#ifndef SRE2_P1_HALF_RB
+#define SRE2_P1_HALF_RB 1
+#endif
 template <typename Real>
 constexpr bool half_lds(int tb) {
-    return ((int64_t)(2 * sizeof(Real)) << tb) > 65536;
+    return ((int64_t)(2 * sizeof(Real)) << tb) > SRE2_HALF_ABOVE;
 }
 template <typename Real>
 constexpr int pass1_rb(int tb, bool split) {
     (void)split;  // the split form takes the same geometry
-    return Tune<Real>::RB1 + (half_lds<Real>(tb) ? 1 : 0);
+    return Tune<Real>::RB1 + (half_lds<Real>(tb) ? SRE2_P1_HALF_RB : 0);
 }
 
 template <typename Real>

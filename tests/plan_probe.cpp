@@ -43,6 +43,11 @@ int probe_geometry(int precision, int kind, int param, int* tb, int* rb, int* sb
                           : geometry<double>(kind, param, tb, rb, sb);
 }
 
+// 1 when tiles of tb bits transpose through half the LDS in two-pass kernels.
+int probe_half_lds(int precision, int tb) {
+    return precision == 0 ? sre2::half_lds<float>(tb) : sre2::half_lds<double>(tb);
+}
+
 // Registers per fused thread (log2) for transforms of N bits.
 int probe_fused_rb(int precision, int N, int split) {
     return precision == 0 ? sre2::fused_rb<float>(N, split != 0)

@@ -282,8 +282,8 @@ def test_plan_structure(probe):
                 assert bin(mf & reg).count("1") == 2
             seen |= bf | mf
         assert seen == tmask, case
-        # tiles above 64 KiB transpose through half the LDS (plain forms)
-        big = (8 if prec == 0 else 16) << tb > 65536
+        # tiles above the half-LDS size transpose through half the LDS
+        big = bool(probe.probe_half_lds(prec, tb))
         if kind != "fused":
             assert rounds.half == (big and hi == tb), case
         elif rounds.half:
@@ -305,6 +305,15 @@ def test_plan_structure(probe):
         free = [b for b in range(tb) if not (busy >> b) & 1]
         if not (kind == "fused" and par <= 10):
             assert set(free[:4]) <= set(lane_bits(rounds[0])), case
+
+
+def test_half_lds_above_64_kib(probe):
+    """Two-pass tiles of more than 64 KiB (one workgroup per CU) take the
+    half-LDS plans; 64 KiB and less keep full tiles."""
+    for prec in (0, 1):
+        for tb in range(6, 15):
+            big = (8 if prec == 0 else 16) << tb > 65536
+            assert bool(probe.probe_half_lds(prec, tb)) == big, (prec, tb)
 
 
 def test_swizzle_bijective_and_linear(probe):
