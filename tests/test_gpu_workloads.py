@@ -1,5 +1,7 @@
 """GPU checks on the benchmark workloads beyond the N=20 single state.
 
+* N=10 small states (complex128): Haar, |T>^10 and a graph state in every
+  form against the oracle and the closed forms.
 * N=16 batch: 32 Haar states against stored oracle M2 values (each stored
   value keeps the SHA-256 of its input bytes) and 8 graph+T states against
   m log2(4/3), through the packed batched path.
@@ -45,6 +47,21 @@ def sha(psi):
 
 def dev(psi):
     return torch.from_numpy(np.ascontiguousarray(psi)).to("cuda")
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64", "fp32h", "fp64h", "split16", "splitbf16"])
+def test_n10_small(oracle_mod, form):
+    """The N = 10 complex128 workload (Haar, |T>^10, graph state) in every
+    form against the oracle on the same bytes and the closed forms."""
+    print("CASE n10-small", form, flush=True)
+    tol = 1e-9 if form.startswith("fp64") else 1e-5
+    for name, psi, closed in W.workload_inputs("n10_small"):
+        r = sre2.m2(dev(psi), form=form)
+        assert r.status == 0, name
+        assert abs(r.m2 - oracle_mod.m2(psi)) <= tol, (name, r.m2)
+        if closed is not None:
+            ctol = 1e-12 if form.startswith("fp64") else tol
+            assert abs(r.m2 - closed) <= ctol, (name, r.m2, closed)
 
 
 @pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16"])
