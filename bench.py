@@ -380,7 +380,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="fp32")
     ap.add_argument("--also", default="fp32h,split16,splitbf16", help="other forms, comma separated")
     ap.add_argument("--N", type=int, default=20)
@@ -447,7 +447,8 @@ def main():
 
     forms = {}
     for f in [x for x in args.also.split(",") if x and x != args.form]:
-        fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, max(1, args.steps // 2), 1)
+        fsteps_n = max(3, args.steps // 2)
+        fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, fsteps_n, min(2, args.warmup))
         fsteps = LAST_STEPS
         fdom = max((k for k in fkt if k != "aux" and fkt[k][1] > 0), key=lambda k: fkt[k][0])
         fk = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[fdom]
@@ -456,8 +457,8 @@ def main():
                     "abs_dM2_vs_headline": abs(fm2 - m2),
                     "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1], fcs,
                                          stored_traffic(fk, N, f),
-                                         evals=max(1, args.steps // 2)),
-                    "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps // 2), 3)
+                                         evals=fsteps_n),
+                    "kernels_ms_per_step": {k: round(v[0] / fsteps_n, 3)
                                             for k, v in fkt.items()}}
     serving = None
     if args.serving:
