@@ -13,13 +13,15 @@
  * Quantities (qubit j = bit j of the basis index, LSB = qubit 0):
  *   Pauli string      P = X^x Z^z, x,z in Z_2^N           (main text, bit-string
  *                                                           encoding of Paulis)
- *   expectation       <psi|X^x Z^z|psi>
- *                       = sum_t (-1)^{z.t} conj(psi[t^x]) psi[t]   (Eq. Pauli_expect)
+ *   expectation       <psi|X^x Z^z|psi>: by the brute force, psi with the
+ *                       one-qubit factors of X^x Z^z applied, then an inner
+ *                       product; by the transform, Eq. Pauli_expect,
+ *                       sum_t (-1)^{z.t} conj(psi[t^x]) psi[t]
  *   SRE, alpha = 2    M2 = -log2( (1/d) sum_{x,z} |<X^x Z^z>|^4 ), d = 2^N  (Eq. 1)
  *   XOR-FWHT form     sum_{x,z} |<X^x Z^z>|^4 = sum_x sum_z |FWHT_k(G_x)(z)|^4,
  *                     G_x[k] = conj(psi[k^x]) psi[k]        (Eq. final1, Algorithm 1)
- *   FWHT              unnormalised Walsh-Hadamard transform, N butterfly
- *                     stages (a,b) -> (a+b, a-b)            (SI, fast WHT section)
+ *   FWHT              unnormalised Walsh-Hadamard transform, H_2 on every
+ *                     qubit in turn, (a,b) -> (a+b, a-b)     (SI, fast WHT section)
  *
  * Reading adopted for unnormalised input: with n = sum_t |psi[t]|^2 the
  * oracle returns M2 = -log2( S / (2^N n^4) ), which is the paper's value when
@@ -45,17 +47,6 @@
 #endif
 
 #define ORACLE_MAX_N 30
-
-static int popcount_parity(uint64_t v)
-{
-    /* parity of the binary inner product z.t = sum_j z_j t_j mod 2 */
-    int p = 0;
-    while (v) {
-        p ^= (int)(v & 1u);
-        v >>= 1;
-    }
-    return p;
-}
 
 /* Neumaier-compensated running sum, ascending index order. */
 static double compensated_sum(const double *v, int64_t n)
@@ -91,7 +82,56 @@ int sre2o_max_threads(void)
 #endif
 }
 
-/* <psi| X^x Z^z |psi> by the direct sum over t (Eq. Pauli_expect). */
+/* phi = X^x Z^z psi, built one single-qubit factor at a time from the
+ * action of the Pauli matrices on the computational basis (main text: a
+ * Pauli string is a tensor product of one-qubit Paulis; P = X^x Z^z with
+ * x, z in Z_2^N): Z on qubit j flips the sign of every amplitude whose bit j
+ * is 1, then X on qubit j exchanges the two amplitudes of every pair that
+ * differs only in bit j.  Z^z acts first (it is the right factor). */
+static void apply_pauli(const double *psi, int N, uint64_t x, uint64_t z, double *phi)
+{
+    const uint64_t d = (uint64_t)1 << N;
+    memcpy(phi, psi, sizeof(double) * 2 * (size_t)d);
+    for (int j = 0; j < N; ++j) {
+        const uint64_t m = (uint64_t)1 << j;
+        if (!(z & m))
+            continue;
+        for (uint64_t t = 0; t < d; ++t)
+            if (t & m) {
+                phi[2 * t] = -phi[2 * t];
+                phi[2 * t + 1] = -phi[2 * t + 1];
+            }
+    }
+    for (int j = 0; j < N; ++j) {
+        const uint64_t m = (uint64_t)1 << j;
+        if (!(x & m))
+            continue;
+        for (uint64_t t = 0; t < d; ++t)
+            if (!(t & m)) {
+                const uint64_t u = t | m;
+                const double r = phi[2 * t], i = phi[2 * t + 1];
+                phi[2 * t] = phi[2 * u];
+                phi[2 * t + 1] = phi[2 * u + 1];
+                phi[2 * u] = r;
+                phi[2 * u + 1] = i;
+            }
+    }
+}
+
+/* <psi|phi> = sum_t conj(psi[t]) phi[t], ascending t. */
+static void inner(const double *psi, const double *phi, uint64_t d, double *re, double *im)
+{
+    double sr = 0.0, si = 0.0;
+    for (uint64_t t = 0; t < d; ++t) {
+        sr += psi[2 * t] * phi[2 * t] + psi[2 * t + 1] * phi[2 * t + 1];
+        si += psi[2 * t] * phi[2 * t + 1] - psi[2 * t + 1] * phi[2 * t];
+    }
+    *re = sr;
+    *im = si;
+}
+
+/* <psi| X^x Z^z |psi> of Eq. 1 by applying the Pauli string to psi (not by
+ * the index formula of Eq. Pauli_expect, which the transform path uses). */
 int sre2o_pauli_expect(const double *psi, int N, uint64_t x, uint64_t z,
                        double *out_re, double *out_im)
 {
@@ -100,29 +140,18 @@ int sre2o_pauli_expect(const double *psi, int N, uint64_t x, uint64_t z,
     const uint64_t d = (uint64_t)1 << N;
     if (x >= d || z >= d)
         return -1;
-    double re = 0.0, im = 0.0;
-    for (uint64_t t = 0; t < d; ++t) {
-        const uint64_t u = t ^ x;
-        /* conj(psi[u]) * psi[t] */
-        const double ar = psi[2 * u], ai = -psi[2 * u + 1];
-        const double br = psi[2 * t], bi = psi[2 * t + 1];
-        const double pr = ar * br - ai * bi;
-        const double pi = ar * bi + ai * br;
-        if (popcount_parity(z & t)) {
-            re -= pr;
-            im -= pi;
-        } else {
-            re += pr;
-            im += pi;
-        }
-    }
-    *out_re = re;
-    *out_im = im;
+    double *phi = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+    if (!phi)
+        return -2;
+    apply_pauli(psi, N, x, z, phi);
+    inner(psi, phi, d, out_re, out_im);
+    free(phi);
     return 0;
 }
 
-/* Brute force: sum over all 4^N Pauli strings of |<P>|^4, O(8^N).
- * Per-shift sums are kept and added in ascending shift order. */
+/* Brute force: sum over all 4^N Pauli strings of |<P>|^4 (Eq. 1), each
+ * expectation from the Pauli string applied to psi, O(N 8^N).  Per-shift sums
+ * are kept and added in ascending shift order. */
 int sre2o_brute_sum(const double *psi, int N, int nthreads, double *out_sum)
 {
     if (!psi || !out_sum || N < 0 || N > 12)
@@ -132,41 +161,55 @@ int sre2o_brute_sum(const double *psi, int N, int nthreads, double *out_sum)
     if (!per_x)
         return -2;
     set_threads(nthreads);
+    int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t x = 0; x < d; ++x) {
         double *q = (double *)malloc(sizeof(double) * (size_t)d);
-        for (int64_t z = 0; z < d; ++z) {
-            double re, im;
-            sre2o_pauli_expect(psi, N, (uint64_t)x, (uint64_t)z, &re, &im);
-            const double m = re * re + im * im;
-            q[z] = m * m;
+        double *phi = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        if (!q || !phi) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+            for (int64_t z = 0; z < d; ++z) {
+                double re, im;
+                apply_pauli(psi, N, (uint64_t)x, (uint64_t)z, phi);
+                inner(psi, phi, (uint64_t)d, &re, &im);
+                const double m = re * re + im * im;
+                q[z] = m * m;
+            }
+            per_x[x] = compensated_sum(q, d);
         }
-        per_x[x] = compensated_sum(q, d);
         free(q);
+        free(phi);
     }
-    *out_sum = compensated_sum(per_x, d);
+    if (!err)
+        *out_sum = compensated_sum(per_x, d);
     free(per_x);
-    return 0;
+    return err;
 }
 
-/* In-place unnormalised FWHT of an interleaved complex array of length 2^N.
- * Stage h = 1, 2, 4, ...: within each block of 2h, (u, v) -> (u + v, u - v)
- * (SI, fast WHT section: H_{2^N} = [[H, H], [H, -H]]). */
+/* In-place unnormalised Walsh-Hadamard transform of an interleaved complex
+ * array of length 2^N.  H_{2^N} is the Kronecker product of N copies of the
+ * one-qubit H_2 = [[1, 1], [1, -1]] (SI, fast WHT section), so it is applied
+ * as H_2 on qubit j for j = 0 .. N-1: the entries t and t + 2^j of every index
+ * t with bit j clear, (a, b), become (a + b, a - b). */
 int sre2o_fwht(double *a, int N)
 {
     if (!a || N < 0 || N > ORACLE_MAX_N)
         return -1;
-    const int64_t d = (int64_t)1 << N;
-    for (int64_t h = 1; h < d; h *= 2) {
-        for (int64_t i = 0; i < d; i += 2 * h) {
-            for (int64_t j = i; j < i + h; ++j) {
-                const double ur = a[2 * j], ui = a[2 * j + 1];
-                const double vr = a[2 * (j + h)], vi = a[2 * (j + h) + 1];
-                a[2 * j] = ur + vr;
-                a[2 * j + 1] = ui + vi;
-                a[2 * (j + h)] = ur - vr;
-                a[2 * (j + h) + 1] = ui - vi;
-            }
+    const uint64_t d = (uint64_t)1 << N;
+    for (int j = 0; j < N; ++j) {
+        const uint64_t m = (uint64_t)1 << j;
+        for (uint64_t t = 0; t < d; ++t) {
+            if (t & m)
+                continue;
+            const uint64_t u = t | m;
+            const double ar = a[2 * t], ai = a[2 * t + 1];
+            const double br = a[2 * u], bi = a[2 * u + 1];
+            a[2 * t] = ar + br;
+            a[2 * t + 1] = ai + bi;
+            a[2 * u] = ar - br;
+            a[2 * u + 1] = ai - bi;
         }
     }
     return 0;
@@ -383,8 +426,8 @@ int sre2o_alpha_sum(const double *psi, int N, double alpha, int kind, int nthrea
     return err;
 }
 
-/* The same sums over all 4^N Pauli strings by the direct expectation values,
- * O(8^N), N <= 12. */
+/* The same sums over all 4^N Pauli strings with every expectation value from
+ * the Pauli string applied to psi, O(N 8^N), N <= 12. */
 int sre2o_brute_alpha_sum(const double *psi, int N, double alpha, int kind, int nthreads,
                           double *out)
 {
@@ -395,20 +438,30 @@ int sre2o_brute_alpha_sum(const double *psi, int N, double alpha, int kind, int 
     if (!per_x)
         return -2;
     set_threads(nthreads);
+    int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t x = 0; x < d; ++x) {
         double *q = (double *)malloc(sizeof(double) * (size_t)d);
-        for (int64_t z = 0; z < d; ++z) {
-            double re, im;
-            sre2o_pauli_expect(psi, N, (uint64_t)x, (uint64_t)z, &re, &im);
-            q[z] = alpha_term(re * re + im * im, alpha, kind);
+        double *phi = (double *)malloc(sizeof(double) * 2 * (size_t)d);
+        if (!q || !phi) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+            for (int64_t z = 0; z < d; ++z) {
+                double re, im;
+                apply_pauli(psi, N, (uint64_t)x, (uint64_t)z, phi);
+                inner(psi, phi, (uint64_t)d, &re, &im);
+                q[z] = alpha_term(re * re + im * im, alpha, kind);
+            }
+            per_x[x] = compensated_sum(q, d);
         }
-        per_x[x] = compensated_sum(q, d);
         free(q);
+        free(phi);
     }
-    *out = compensated_sum(per_x, d);
+    if (!err)
+        *out = compensated_sum(per_x, d);
     free(per_x);
-    return 0;
+    return err;
 }
 
 /* Pauli-spectrum histogram: for every Pauli string, q = |W|^2 / n^2 goes to

@@ -151,9 +151,12 @@ def test_ising_snapshot_clifford_points_and_symmetries(oracle_mod):
 
 
 def test_stored_n20_snapshots_obey_the_reflections():
-    """The oracle's stored N = 20 snapshot values at t = 5 and 21 (computed
-    independently, hours apart) agree as M2(t) = M2(16 - t) = M2(32 - t)
-    requires: 21 -> 11 -> 5."""
+    """The oracle's stored N = 20 snapshot values at t = 5 and 21 agree as
+    M2(t) = M2(16 - t) = M2(32 - t) requires (21 -> 11 -> 5).  This is a
+    consistency check, not an independent value: with all-to-all +-1
+    couplings at N = 20 the energy h(k) is a sum of 190 odd terms, hence
+    even, so psi_21 = psi_5 times a diagonal of fourth roots of unity, i.e. a
+    phase Clifford, and Clifford invariance forces equality."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
@@ -162,6 +165,9 @@ def test_stored_n20_snapshots_obey_the_reflections():
         g = json.load(f)
     assert abs(g["ising20_t5"]["m2"] - g["ising20_t21"]["m2"]) < 1e-12
     assert g["ising20_t5"]["m2"] > 1.0
+    J = W.snapshot_couplings(20)
+    h = W.ising_energy(20, J)
+    assert np.all(np.asarray(h) % 2 == 0)  # the phase ratio is i^(h/2)
 
 
 def test_additivity(oracle_mod):
@@ -336,6 +342,48 @@ def test_spectrum_equals_textbook(oracle_mod, N):
         counts, _ = oracle_mod.spectrum(psi, 12)
         assert np.array_equal(counts, _brute_spectrum(psi, 12))
         assert counts.sum() == 4 ** N
+
+
+def _near_edges_textbook(psi, nbins, eps):
+    """Strings whose -log2 q (q from the textbook matrices, q > 0) lies within
+    eps of an edge b + 1/2 between bins b and b + 1, b = 0 .. nbins - 2."""
+    N = psi.size.bit_length() - 1
+    n = np.vdot(psi, psi).real
+    edges = np.arange(nbins - 1) + 0.5
+    near = 0
+    for x in range(1 << N):
+        for z in range(1 << N):
+            q = abs(np.vdot(psi, _pauli_matrix(N, x, z) @ psi)) ** 2 / n ** 2
+            if q > 1e-24 and np.min(np.abs(-np.log2(q) - edges)) <= eps:
+                near += 1
+    return near
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.05, 0.2, 0.45])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_spectrum_near_edge_equals_textbook(oracle_mod, N, eps):
+    for psi in (W.haar(N, 310 + N), W.haar(N, 320 + N), W.t_product(N)):
+        _, near = oracle_mod.spectrum(psi, 8, eps=eps)
+        assert near == _near_edges_textbook(psi, 8, eps), (N, eps)
+
+
+def test_spectrum_near_edge_closed_form(oracle_mod):
+    """One qubit cos(th/2)|0> + sin(th/2)|1>: q = 1 (I), sin^2 th (X),
+    cos^2 th (Z), 0 (Y).  With sin^2 th = 2^-(3/2 + 1/100), X sits 0.01 above
+    the edge 3/2 and Z at -log2(1 - 2^-1.51) = 0.62396..., 0.12396 above the
+    edge 1/2; I sits 1/2 below that edge."""
+    s2 = 2.0 ** -1.51
+    th = np.arcsin(np.sqrt(s2))
+    psi = np.array([np.cos(th / 2), np.sin(th / 2)], np.complex128)
+    dz = -np.log2(1.0 - s2) - 0.5
+    assert 0.1239 < dz < 0.1240
+    counts, _ = oracle_mod.spectrum(psi, 4, eps=0.0)
+    assert list(counts) == [1, 1, 1, 1]  # I in bin 0, Z in bin 1, X in bin 2, Y last
+    for eps, want in ((0.0, 0), (0.009, 0), (0.011, 1), (0.12, 1), (0.13, 2), (0.49, 2)):
+        assert oracle_mod.spectrum(psi, 4, eps=eps)[1] == want, eps
+    # X at 1.51 is also 0.99 from the edge 2.5, Z 0.876 from 1.5: only the
+    # nearest edge counts, so no string is counted twice
+    assert oracle_mod.spectrum(psi, 4, eps=0.999)[1] == 3  # I at distance 0.5 joins
 
 
 def test_spectrum_closed_forms(oracle_mod):
