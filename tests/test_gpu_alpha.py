@@ -9,6 +9,8 @@
 * Spectrum: exact counts for stabilizer and |T>-product states (their values
   sit at bin centres), total 4^N always, and Haar states within the number
   of oracle values near a bin edge.
+* N = 22 (FP32): the general kernels' half-LDS column tiles of pass 2 (ten
+  slab-row bits, 2^14-value tiles) on |T>^22 against both closed forms.
 """
 import functools
 
@@ -120,3 +122,23 @@ def test_spectrum_haar_matches_oracle(oracle_mod, form, N):
     diff = int(np.abs(counts - ref).sum())
     assert diff <= 2 * near, (diff, near)
 
+
+
+def test_general_kernels_half_lds_tiles_n22():
+    """At N = 22 the FP32 pass 2 holds ten row bits in 2^14-value tiles that
+    transpose through half the LDS; the general reductions take those tiles
+    too.  |T>^22: M_3 = 22 log2((1 + 2^-2)/2) / (1 - 3) and the spectrum
+    C(22, k) 2^k strings at q = 2^-k, 4^22 - 3^22 zeros (last bin)."""
+    from math import comb
+    N = 22
+    t = dev(W.t_product(N, np.complex64))
+    print("CASE alpha n22", flush=True)
+    r = sre2.sre(t, 3.0, form="fp32")
+    assert r.status == 0
+    assert abs(r.m2 - N * t_single(3.0)) <= TOL["fp32"], r.m2
+    print("CASE spectrum n22", flush=True)
+    counts, r = sre2.pauli_spectrum(t, N + 2, form="fp32")
+    assert r.status == 0
+    for k in range(N + 1):
+        assert counts[k] == comb(N, k) * 2 ** k, (k, counts[k])
+    assert counts[-1] == 4 ** N - 3 ** N

@@ -8,7 +8,12 @@ Tolerances (bars of the method's two precisions):
 The oracle always receives the exact bytes the GPU receives, upcast to FP64.
 Sizes: every N from 1 to 16 in full; N = 20 (the benchmark state) in full
 against the stored oracle M2 and per-shift sums; N = 22 and 24 on stored
-sampled shifts; N = 26 (the largest FP32 slab) on one shift computed here.
+sampled shifts and on one full default chunk (the launch shape of a full
+evaluation: shifts per chunk from the context's chunking, slab offsets over
+the whole chunk); N = 26 (the largest FP32 slab) on one shift computed here.
+
+A per-shift relative bar does not bound M2: |dM2| = |dS / S| / ln 2 to first
+order, so the sum over a chunk is held to the M2 bar times ln 2 as well.
 """
 import hashlib
 import json
@@ -30,6 +35,8 @@ TOL_M2 = {"fp32": 1e-5, "fp64": 1e-9, "fp32h": 1e-5, "fp64h": 1e-9, "split16": 1
 TOL_SX = {"fp32": 1e-4, "fp64": 1e-11, "fp32h": 1e-4, "fp64h": 1e-11, "split16": 1e-4,
           "splitbf16": 1e-4}
 FORMS = ["fp32", "fp64", "fp32h", "fp64h", "split16", "splitbf16"]
+# relative error of a sum of S_x that keeps its share of M2 within TOL_M2
+TOL_SUM = {f: TOL_M2[f] * np.log(2.0) for f in TOL_M2}
 # Closed forms on complex64 inputs: the amplitude rounding alone moves M2 by
 # < 1e-6; the split forms' 22-bit (FP16) and 16-bit (BF16) hi/lo values add
 # up to their 1e-5 bound.
@@ -215,16 +222,13 @@ def test_n20_full_size(oracle_mod, form):
     r = sre2.m2(d, form=form, partials=True)
     assert r.status == 0
     rec = g.get("haar20_sampled")
-    xs = rec["shifts"] if rec and rec["sha256"] == _sha(psi) else [0, 1, 12345, (1 << 20) - 1]
-    ref = np.array(rec["partials"]) if rec and rec["sha256"] == _sha(psi) else \
-        oracle_mod.partials(psi, xs)
+    assert rec and rec["sha256"] == _sha(psi), "stored N=20 sampled shifts missing or stale"
+    xs, ref = rec["shifts"], np.array(rec["partials"])
     got = r.partials.cpu().numpy()[xs]
     assert np.max(np.abs(got - ref) / ref) <= TOL_SX[form]
     full = g.get("haar20")
-    if full and full["sha256"] == _sha(psi):
-        assert abs(r.m2 - full["m2"]) <= TOL_M2[form], (r.m2, full["m2"])
-    else:
-        assert abs(r.m2 - (np.log2(2 ** 20 + 3) - 2)) < 1e-3  # Haar law (sanity)
+    assert full and full["sha256"] == _sha(psi), "stored N=20 oracle value missing or stale"
+    assert abs(r.m2 - full["m2"]) <= TOL_M2[form], (r.m2, full["m2"])
     psi_t, _ = W.graph_t(20, 10, W.SEED_N20 + 1, dtype=np.complex64)
     rt = sre2.m2(dev(psi_t), form=form)
     assert abs(rt.m2 - 10 * LOG43) <= closed_tol(form)
@@ -276,3 +280,56 @@ def _max_n_ref(x):
     if x not in _MAXN:
         _MAXN[x] = float(oracle.partials(_max_n_state(), [x], threads=1)[0])
     return _MAXN[x]
+
+
+def _popcount(v):
+    v = np.asarray(v, dtype=np.uint64)
+    c = np.zeros(v.shape, dtype=np.int64)
+    for b in range(64):
+        c += ((v >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return c
+
+
+_LARGE = {}
+
+
+def _large_state(kind, N, c128):
+    key = (kind, N, c128)
+    if key not in _LARGE:
+        dt = np.complex128 if c128 else np.complex64
+        _LARGE.clear()  # keep one large state resident on the host
+        _LARGE[key] = W.t_product(N, dt) if kind == "t" else W.haar(N, W.SEED_LARGE + 40 + N, dt)
+    return _LARGE[key]
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("N", [22, 24])
+def test_large_n_full_default_chunk(oracle_mod, N, form):
+    """One whole default chunk at x0 = 2^(N-1), exactly as a full evaluation
+    launches it (shifts per chunk from the context, one pass-1 and one pass-2
+    launch over the chunk, the 2^14-value half-LDS rows at N = 24).
+    |T>^N: by Eq. 1 per qubit, sum_z |<X^a Z^b>|^4 is 1 for a = 0 and
+    (1/2)^2 + (1/2)^2 = 1/2 for a = 1, so S_x = 2^-popcount(x) for every
+    shift.  Haar: in-chunk shifts against the oracle."""
+    c128 = is64(form)
+    ctx = sre2.Context(0)
+    try:
+        cs, _ = ctx.chunking(N, form)
+        assert cs == (1024 if N == 22 else 256) // (2 if c128 else 1) * (2 if form.endswith("h") else 1)
+        x0 = 1 << (N - 1)
+        xs = x0 + np.arange(cs, dtype=np.int64)
+        case_id("large-chunk-t", N, form, cs)
+        psi = _large_state("t", N, c128)
+        got = sre2.shift_partials(dev(psi), x0, cs, form=form, ctx=ctx).cpu().numpy()
+        ref = 2.0 ** (-_popcount(xs).astype(np.float64))
+        assert np.max(np.abs(got - ref) / ref) <= TOL_SX[form]
+        assert abs(got.sum() - ref.sum()) <= TOL_SUM[form] * ref.sum()
+        case_id("large-chunk-haar", N, form, cs)
+        psi = _large_state("haar", N, c128)
+        got = sre2.shift_partials(dev(psi), x0, cs, form=form, ctx=ctx).cpu().numpy()
+        pick = [0, 1, cs // 2 + 3, cs - 1]
+        ref = oracle_mod.partials(psi, xs[pick])
+        assert np.max(np.abs(got[pick] - ref) / ref) <= TOL_SX[form]
+        assert abs(got[pick].sum() - ref.sum()) <= TOL_SUM[form] * ref.sum()
+    finally:
+        ctx.close()

@@ -73,7 +73,7 @@ def wait_all(srv, tickets, timeout=300.0):
     return res
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp32h"])
+@pytest.mark.parametrize("form", ["fp32", "fp32h", "split16", "splitbf16"])
 def test_server_mix_equals_alone(oracle_mod, form):
     states = mixed_states(160, 23, 3, 18)
     print("CASE server-mix", form, flush=True)

@@ -79,17 +79,21 @@ def test_n16_batch(form):
             checked += 1
         else:
             rec = g.get(f"haar16_batch_{i}")
-            if rec and rec["sha256"] == sha(psi):
-                assert abs(r.m2 - rec["m2"]) <= 1e-5, name
-                checked += 1
-            else:
-                assert abs(r.m2 - (np.log2(2 ** 16 + 3) - 2)) < 2e-3  # Haar law
-    assert checked >= 8
+            assert rec and rec["sha256"] == sha(psi), f"stored oracle value missing for {name}"
+            assert abs(r.m2 - rec["m2"]) <= 1e-5, name
+            checked += 1
+    assert checked == len(inputs) == 40
 
 
-@pytest.mark.parametrize("form", ["fp32h", "fp32"])
+@pytest.mark.parametrize("form", ["fp32h", "fp32", "split16"])
 def test_n20_snapshot_sequence(form):
+    """Each result within the form's 1e-5 bar of the truth, so two results
+    that must be equal differ by at most twice the bar in the split forms
+    (their error is not the same function of the two states)."""
     print("CASE snapshots", form, flush=True)
+    tol = 1e-5
+    pair_tol = 2e-5 if form.startswith("split") else 1e-5
+    zero_tol = 1e-5 if form.startswith("split") else 1e-6
     N = 20
     J = W.snapshot_couplings(N)
     h = W.ising_energy(N, J)
@@ -105,9 +109,9 @@ def test_n20_snapshot_sequence(form):
         if t in (5, 21):  # stored oracle values (tests/golden)
             assert rec and rec["sha256"] == sha(psi), t
         if rec and rec["sha256"] == sha(psi):
-            assert abs(r.m2 - rec["m2"]) <= 1e-5, t
+            assert abs(r.m2 - rec["m2"]) <= tol, t
     for t in (0, 16, 32, 48):
-        assert abs(m[t]) <= 1e-6, (t, m[t])
+        assert abs(m[t]) <= zero_tol, (t, m[t])
     for a, b in ((5, 37), (5, 27), (21, 53), (27, 37)):
-        assert abs(m[a] - m[b]) <= 1e-5, (a, b, m[a], m[b])
+        assert abs(m[a] - m[b]) <= pair_tol, (a, b, m[a], m[b])
     assert m[5] > 1.0 and m[21] > 1.0  # non-trivial between Clifford angles
