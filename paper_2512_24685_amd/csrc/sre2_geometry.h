@@ -135,8 +135,11 @@ constexpr int fused_tb(int N) {
 #ifndef SRE2_F64_FUSED_HALF
 #define SRE2_F64_FUSED_HALF 1
 #endif
-#ifndef SRE2_FUSED_HALF_RB
-#define SRE2_FUSED_HALF_RB 1
+#ifndef SRE2_F32_FUSED_HALF_RB
+#define SRE2_F32_FUSED_HALF_RB 1
+#endif
+#ifndef SRE2_F64_FUSED_HALF_RB
+#define SRE2_F64_FUSED_HALF_RB 1
 #endif
 template <typename Real>
 constexpr bool fused_half(int N) {
@@ -146,7 +149,10 @@ constexpr bool fused_half(int N) {
 // Registers (log2) per fused thread for transforms of N bits.
 template <typename Real>
 constexpr int fused_rb(int N, bool split) {
-    return Tune<Real>::RBF + (!split && fused_half<Real>(N) ? SRE2_FUSED_HALF_RB : 0);
+    return Tune<Real>::RBF +
+           (!split && fused_half<Real>(N)
+                ? (sizeof(Real) == 4 ? SRE2_F32_FUSED_HALF_RB : SRE2_F64_FUSED_HALF_RB)
+                : 0);
 }
 template <typename Real>
 constexpr int pass2_tb(int H) {

@@ -150,6 +150,9 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #ifndef SRE2_FUSEDH_WAVES
 #define SRE2_FUSEDH_WAVES 2
 #endif
+#ifndef SRE2_F32_FUSEDH_WAVES
+#define SRE2_F32_FUSEDH_WAVES SRE2_FUSEDH_WAVES
+#endif
 #ifndef SRE2_HALF_WAVES
 #define SRE2_HALF_WAVES 4
 #endif
@@ -234,18 +237,13 @@ __device__ __forceinline__ uint32_t thread_base() {
     return b;
 }
 
-// LDS slot of register element i: swz(base | r) with r = pdep(i, REG).  The
-// swizzle is linear, and the bits of swz(r) at or above SB are tile bits of
-// REG, where swz(base) is zero, so swz(base) ^ swz(r) = (swz(base) ^ lo) + hi
-// with lo, hi the parts of swz(r) below and above bit SB: one XOR per
-// distinct lo, and hi becomes the instruction's constant offset.  Byte
-// offsets are formed once per thread.
+// LDS slot of register element i: pad(base | r) = pad(base) + pad(r) with
+// r = pdep(i, REG) (disjoint bits), so the thread's byte offset pb_bytes is
+// formed once and pad(r) becomes the instruction's constant offset.
 template <int SB, typename C>
 __device__ __forceinline__ C* lds_slot(C* lds, uint32_t pb_bytes, uint32_t r) {
-    const uint32_t e = swz<SB>(r);
-    const uint32_t lo = e & ((1u << SB) - 1u), hi = e & ~((1u << SB) - 1u);
-    return reinterpret_cast<C*>(reinterpret_cast<char*>(lds) + hi * (uint32_t)sizeof(C) +
-                                (pb_bytes ^ (lo * (uint32_t)sizeof(C))));
+    return reinterpret_cast<C*>(reinterpret_cast<char*>(lds) + pb_bytes +
+                                pad<SB>(r) * (uint32_t)sizeof(C));
 }
 
 // Registers v[OFF + i], i < 2^RB, hold the elements base | pdep(i, REG).
@@ -253,7 +251,7 @@ template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF =
           int NV>
 __device__ __forceinline__ void lds_put(C* lds, const C (&v)[NV]) {
     static_assert(OFF + (1 << RB) <= NV, "registers");
-    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
+    const uint32_t pb = pad<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i)
         *lds_slot<SB>(lds, pb, pdep((uint32_t)i, REG)) = v[OFF + i];
@@ -263,7 +261,7 @@ template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF =
           int NV>
 __device__ __forceinline__ void lds_get(const C* lds, C (&v)[NV]) {
     static_assert(OFF + (1 << RB) <= NV, "registers");
-    const uint32_t pb = swz<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
+    const uint32_t pb = pad<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i)
         v[OFF + i] = *lds_slot<SB>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
@@ -301,9 +299,11 @@ __host__ __device__ constexpr Plan plan_of() {
                                        : make_plan(TB, RB, SB, 0, PK - 1000);
 }
 
-// LDS values a kernel with plan P declares (1 when it has a single round).
+// LDS values (padded slots) a kernel with plan P declares (1 when it has a
+// single round).
 __host__ __device__ constexpr int lds_values(const Plan& P) {
-    return P.nrounds < 2 ? 1 : (P.half ? 1 << (P.tb - 1) : 1 << P.tb);
+    return P.nrounds < 2 ? 1
+                         : (int)pad_rt((P.half ? 1u << (P.tb - 1) : 1u << P.tb) - 1u, P.sb) + 1;
 }
 
 template <int TB, int RB, int PK>
@@ -568,8 +568,10 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
 template <typename Real, int NT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(SPLIT ? SRE2_FUSEDS_WAVES
-                                   : (fused_half<Real>(NT) ? SRE2_FUSEDH_WAVES
-                                                           : SRE2_FUSED_WAVES))))
+                                   : (fused_half<Real>(NT)
+                                          ? (sizeof(Real) == 4 ? SRE2_F32_FUSEDH_WAVES
+                                                               : SRE2_FUSEDH_WAVES)
+                                          : SRE2_FUSED_WAVES))))
 void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int64_t x_count,
              double* __restrict__ S_out, const int* __restrict__ scale_exp,
              const Pack pk, const Spec sp) {

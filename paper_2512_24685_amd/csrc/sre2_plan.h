@@ -10,9 +10,10 @@
 // WHT section: H_{2^N} = H_2^{(x)N}), and those per-bit stages commute, so any
 // order of bits across rounds gives the same transform.
 //
-// LDS addresses are XOR-swizzled: tile bit b feeds bank slot bit (b mod SB),
-// where a slot is one complex value (SB = 5 for 8-byte, 4 for 16-byte
-// values: 2^SB slots are 256 bytes, the 64 four-byte banks).  Measured
+// LDS addresses are padded: tile element e sits in slot pad(e) = e + (e >> SB)
+// + (e >> 2 SB) + ..., where a slot is one complex value (SB = 5 for 8-byte,
+// 4 for 16-byte values: 2^SB slots are 256 bytes, the 64 four-byte banks), so
+// tile bit b alone moves the slot by 2^(b mod SB) modulo 2^SB.  Measured
 // on gfx950 with rocprof's LDS bank-conflict counter, an access is free of
 // conflicts when each group of 2^SB lanes hits 2^SB distinct slots modulo
 // 2^SB and, inside it, each half group (128 bytes) hits distinct slots
@@ -20,6 +21,11 @@
 // order, but lane bit SB-1 must map onto slot bit SB-1.  So lane bit i of
 // every round sits on a tile bit of residue i mod SB (i < SB), or at least
 // lane bits 0..SB-2 on residues 0..SB-2 and lane bit SB-1 on residue SB-1.
+// Lane bits of distinct residues add distinct powers of two, and the wave
+// and register bits add the same amount to every lane, so each access is
+// free of conflicts.  pad is additive over disjoint bits (pad(a | b) =
+// pad(a) + pad(b) when a & b = 0: shifting a carry-free sum carries nothing),
+// so a register element's slot is the thread's slot plus a constant.
 //
 // Tiles above 64 KiB would leave one workgroup per CU (160 KiB of LDS); their
 // half-LDS plans keep the top tile bit in every round's registers, so each
@@ -68,6 +74,7 @@ constexpr int kMaxTileBits = 16;
 
 struct Plan {
     int tb = 0, rb = 0, nrounds = 0;
+    int sb = 5;  // slot bits of one value (LDS padding period)
     // half: every round holds the top tile bit in its top register-index
     // bit, so each LDS transpose runs in two phases (register halves with
     // that bit 0, then 1) through an LDS buffer of half the tile
@@ -113,16 +120,23 @@ __host__ __device__ constexpr uint32_t pext(uint32_t v, uint32_t mask) {
     return r;
 }
 
-// Bank swizzle: XOR the low SB bits with every higher SB-bit chunk (GF(2)-linear
-// and a bijection on any power-of-two range).
+// LDS slot of tile element e: pad(e) = sum over j >= 0 of (e >> SB j).
 template <int SB>
-__host__ __device__ constexpr uint32_t swz(uint32_t e) {
-    uint32_t h = e >> SB, f = 0;
-    while (h) {
-        f ^= h & ((1u << SB) - 1u);
-        h >>= SB;
+__host__ __device__ constexpr uint32_t pad(uint32_t e) {
+    uint32_t s = 0;
+    while (e) {
+        s += e;
+        e >>= SB;
     }
-    return e ^ f;
+    return s;
+}
+__host__ __device__ constexpr uint32_t pad_rt(uint32_t e, int sb) {
+    uint32_t s = 0;
+    while (e) {
+        s += e;
+        e >>= sb;
+    }
+    return s;
 }
 
 // Highest `count` set bits of `m`.
@@ -183,6 +197,7 @@ __host__ __device__ constexpr Plan make_plan(int tb, int rb, int sb, int lo, int
     Plan p{};
     p.tb = tb;
     p.rb = rb;
+    p.sb = sb;
     const uint32_t tmask = bits_range(lo, hi);
     const int n = hi - lo;
     uint32_t todo = tmask;
@@ -389,6 +404,7 @@ __host__ __device__ constexpr Plan make_split_plan(int tb, int rb, int sb, int l
     Plan p{};
     p.tb = tb;
     p.rb = rb;
+    p.sb = sb;
     const uint32_t tmask = bits_range(lo, hi);
     uint32_t todo = tmask, done = 0;
     int k = 0;

@@ -88,7 +88,7 @@ int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int kind, unsi
     return p.nrounds + (p.half ? 100 : 0);
 }
 
-unsigned probe_swz(int sb, unsigned e) {
-    return sb == 5 ? sre2::swz<5>(e) : sb == 4 ? sre2::swz<4>(e) : sre2::swz<3>(e);
+unsigned probe_pad(int sb, unsigned e) {
+    return sb == 5 ? sre2::pad<5>(e) : sb == 4 ? sre2::pad<4>(e) : sre2::pad<3>(e);
 }
 }

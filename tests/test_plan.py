@@ -4,7 +4,7 @@ The constexpr plan builder of the kernels (paper_2512_24685_amd/csrc/sre2_plan.h
 is compiled into a small host probe.  The tests then replay, with numpy, the
 exact index arithmetic of the kernels - global load mapping, register
 butterflies, the split form's H_16 factors in the matrix-core operand layout,
-swizzled LDS transposes between rounds, final mapping, two-pass scratch
+padded LDS transposes between rounds, final mapping, two-pass scratch
 layout - and compare with the Walsh-Hadamard transform over the same bits and
 with the oracle's per-shift sums.  They also check that every round's LDS
 accesses hit distinct bank slots within each group of 2^SB lanes.
@@ -29,7 +29,7 @@ def probe(tmp_path_factory):
     subprocess.run(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-o", so, SRC], check=True)
     lib = ctypes.CDLL(so)
     lib.probe_plan.restype = ctypes.c_int
-    lib.probe_swz.restype = ctypes.c_uint
+    lib.probe_pad.restype = ctypes.c_uint
     return lib
 
 
@@ -94,13 +94,14 @@ def pdep(v: np.ndarray, mask: int) -> np.ndarray:
     return r
 
 
-def swz_np(sb, e):
-    h = e >> sb
-    f = np.zeros_like(e)
+def pad_np(sb, e):
+    """LDS slot of tile element e: e + (e >> sb) + (e >> 2 sb) + ..."""
+    s = np.zeros_like(e)
+    h = np.array(e, copy=True)
     while np.any(h):
-        f ^= h & ((1 << sb) - 1)
+        s += h
         h >>= sb
-    return e ^ f
+    return s
 
 
 def mapping(rd, tb, rb):
@@ -175,9 +176,10 @@ def run_tile(X, rounds, tb, rb, sb):
     top, hr = 1 << (tb - 1), 1 << (rb - 1)
     for j in range(1, len(rounds)):
         if not half:
-            lds = np.full(X.shape[:-1] + (1 << tb,), np.nan + 0j)
-            lds[..., swz_np(sb, E[j - 1])] = V
-            V = round_math(lds[..., swz_np(sb, E[j])], rounds[j])
+            lds = np.full(X.shape[:-1] + (int(pad_np(sb, np.array([(1 << tb) - 1]))[0]) + 1,),
+                          np.nan + 0j)
+            lds[..., pad_np(sb, E[j - 1])] = V
+            V = round_math(lds[..., pad_np(sb, E[j])], rounds[j])
             continue
         W = np.empty_like(V)
         for h in (0, 1):
@@ -185,9 +187,10 @@ def run_tile(X, rounds, tb, rb, sb):
             # the register half holds exactly the elements with top bit h
             assert np.all((E[j - 1][:, regs] & top) == h * top)
             assert np.all((E[j][:, regs] & top) == h * top)
-            lds = np.full(X.shape[:-1] + (top,), np.nan + 0j)
-            lds[..., swz_np(sb, E[j - 1][:, regs] & (top - 1))] = V[..., regs]
-            W[..., regs] = lds[..., swz_np(sb, E[j][:, regs] & (top - 1))]
+            lds = np.full(X.shape[:-1] + (int(pad_np(sb, np.array([top - 1]))[0]) + 1,),
+                          np.nan + 0j)
+            lds[..., pad_np(sb, E[j - 1][:, regs] & (top - 1))] = V[..., regs]
+            W[..., regs] = lds[..., pad_np(sb, E[j][:, regs] & (top - 1))]
             assert not np.isnan(W[..., regs]).any()
         V = round_math(W, rounds[j])
     out = np.empty_like(X)
@@ -316,19 +319,28 @@ def test_half_lds_above_64_kib(probe):
             assert bool(probe.probe_half_lds(prec, tb)) == big, (prec, tb)
 
 
-def test_swizzle_bijective_and_linear(probe):
+def test_padding_injective_and_additive(probe):
+    """pad is strictly increasing (so injective), additive over disjoint bits
+    (the kernels add a register element's pad to the thread's), one tile bit
+    moves the slot by 2^(b mod sb) modulo 2^sb, and a 2^tb tile takes
+    pad(2^tb - 1) + 1 slots."""
     for sb in (3, 4, 5):
         e = np.arange(1 << 14, dtype=np.int64)
-        s = np.array([probe.probe_swz(sb, int(v)) for v in e[:4096]])
-        assert np.array_equal(s, swz_np(sb, e[:4096]))
-        full = swz_np(sb, e)
-        assert np.array_equal(np.sort(full), e)
-        a, b = 0x1234 & 0x3FFF, 0x0F0F & 0x3FFF
-        assert swz_np(sb, np.array([a ^ b]))[0] == swz_np(sb, np.array([a]))[0] ^ swz_np(sb, np.array([b]))[0]
+        s = np.array([probe.probe_pad(sb, int(v)) for v in e[:4096]])
+        assert np.array_equal(s, pad_np(sb, e[:4096]))
+        full = pad_np(sb, e)
+        assert np.all(np.diff(full) > 0)
+        rng = np.random.default_rng(sb)
+        for _ in range(200):
+            a = int(rng.integers(0, 1 << 14))
+            b = int(rng.integers(0, 1 << 14)) & ~a
+            assert full[a | b] == full[a] + full[b]
+        for b in range(14):
+            assert full[1 << b] % (1 << sb) == (1 << (b % sb)) % (1 << sb)
 
 
 def test_lds_bank_slots_distinct(probe):
-    """Every LDS access of a round hits 2^SB distinct slots modulo 2^SB in
+    """Every LDS access of a round (padded slots) hits 2^SB distinct slots modulo 2^SB in
     each group of 2^SB lanes (256 bytes) and distinct slots modulo 2^(SB-1)
     in each half group (128 bytes per LDS cycle).  Small split-form fused
     tiles (N <= 11) are exempt from the half-group rule and may share a slot
@@ -341,7 +353,7 @@ def test_lds_bank_slots_distinct(probe):
             continue
         for j, rd in enumerate(rounds):
             M = mapping(rd, tb, rb)
-            E = swz_np(sb, M & ((1 << (tb - 1)) - 1) if rounds.half else M)
+            E = pad_np(sb, M & ((1 << (tb - 1)) - 1) if rounds.half else M)
             slots = E & ((1 << sb) - 1)
             g = 1 << sb
             T = E.shape[0]
