@@ -1,23 +1,37 @@
-"""Throughput benchmark: Pauli strings per second of one exact M2 evaluation.
+"""Throughput benchmark: Pauli strings per second of one exact M2 evaluation,
+and every benchmark configuration as its own leg with its measured error.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32]
-                    [--also fp32h,fp64] [--N 20] [--no-cpu]
+                    [--also fp32h,split16,splitbf16,fp64,fp64h] [--N 20] [--no-cpu]
     python bench.py --copy-calibration MiB     (plain device copy, for counters)
+    python bench.py --form F --profile-chunks C (C two-pass chunks, for counters)
 
 One step = one full evaluation (every shift x, its FWHT, sum |W|^4, the final
 reduction and logarithm) of an N=20 Haar-random complex64 state that is
 already resident in device memory.  Pauli strings per step = 4^N.
 
 Printed (one JSON line on stdout): throughput of the headline form (plain
-FP32 XOR-FWHT), ms per step, the dominant kernel's roofline position (timed
-live with HIP events around every launch in the timed region), the other
-forms measured the same way, and the FP64 CPU oracle timed on this host's
-cores on a bounded sample of the same workload.
+FP32 XOR-FWHT) with |dM2| against the stored FP64 oracle value, ms per step,
+the dominant kernel's roofline position (timed live with HIP events around
+every launch in the timed region), the other forms measured the same way,
+and one leg per benchmark configuration:
+  * N = 10 complex128 states (Haar, |T>^10, graph state), every form, |dM2|
+    against the oracle and the closed forms;
+  * N = 16 batch (32 Haar + 8 graph+T, complex64) through the packed batched
+    path, |dM2| against stored oracle values and the closed forms;
+  * N = 20 Haar and graph+T (m = 10) in every form, |dM2| against the stored
+    oracle value and the closed form;
+  * the serving stream (N ~ U{8..18}) at saturating load (4096 requests) and
+    at 0.7 load, server against one-at-a-time calls;
+  * N = 22 / 24 two-pass chunks (HBM rates, partials checked against stored
+    oracle values) and a timed sample of the N = 20 Ising snapshot sequence;
+  * the FP64 CPU oracle timed on this host's cores on bounded samples.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
+import subprocess
 import re
 import json
 import os
@@ -129,7 +143,28 @@ def stored_traffic(kernel: str, N: int, form: str):
     return None
 
 
-def cpu_baseline(psi: np.ndarray, target_s: float):
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(psi: np.ndarray, target_s: float, n10=None, n16=None):
+    """The FP64 CPU oracle, as it stands, on this host's cores.
+
+    * Headline: random shifts x of the N = 20 state, one FP64 FWHT over 2^20
+      Pauli strings each (Algorithm 1's loop body), for about target_s, scaled
+      to Pauli strings per second.
+    * N = 10 states: one full oracle evaluation each (also the reference M2
+      of the N = 10 leg).
+    * N = 16: a full oracle evaluation of `n16` (sample states of the batch).
+    """
     import oracle
 
     N = psi.size.bit_length() - 1
@@ -145,10 +180,48 @@ def cpu_baseline(psi: np.ndarray, target_s: float):
         dt += time.perf_counter() - t0
         count += len(xs)
         pos += len(xs)
-    return {"value": count * float(1 << N) / dt, "unit": "Pauli strings/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{count} random shifts x of the N={N} state, each a full FP64 FWHT over "
-                      f"2^{N} Pauli strings (Algorithm 1 loop body), {dt:.1f} s on {cores} threads"}
+    rec = {"value": count * float(1 << N) / dt, "unit": "Pauli strings/s", "cores": cores,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{count} random shifts x of the N={N} state, each a full FP64 FWHT over "
+                     f"2^{N} Pauli strings (Algorithm 1 loop body), {dt:.1f} s on {cores} threads"}
+    refs = {}
+    per = {}
+    for name, p in (n10 or []):
+        t0 = time.perf_counter()
+        refs[name] = oracle.m2(p, threads=cores)
+        per[name] = time.perf_counter() - t0
+    if n10:
+        rec["n10_seconds_per_state"] = {k: round(v, 4) for k, v in per.items()}
+    if n16:
+        ts = []
+        for name, p in n16:
+            t0 = time.perf_counter()
+            S, n = oracle.total(p, threads=cores)
+            ts.append(time.perf_counter() - t0)
+            refs[name] = oracle.m2_from_total(S, n, p.size.bit_length() - 1)
+        rec["n16_seconds_per_state"] = round(float(np.mean(ts)), 3)
+        rec["n16_sample"] = f"{len(n16)} of the 40 batch states, full evaluation each"
+        rec["n16_pauli_per_s"] = float(4 ** 16) / float(np.mean(ts))
+    return rec, refs
+
+
+def golden():
+    """Stored FP64 oracle values (written by tests/golden/make_golden.py from
+    the oracle alone), keyed by case with the SHA-256 of their input bytes."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def sha256(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def stored_m2(g, name, psi):
+    rec = g.get(name)
+    return rec["m2"] if rec and rec.get("sha256") == sha256(psi) else None
 
 
 SCRATCH_LIMIT = 0  # bytes; 0 keeps the library default
@@ -206,25 +279,17 @@ def copy_calibration(mib: int):
     log(f"copied {mib} MiB ten times ({n * 4} bytes read and written per copy)")
 
 
-def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
-                      n_lo: int = 8, n_hi: int = 18):
-    """Poisson stream of `count` requests (N ~ U{n_lo..n_hi}, Haar or graph+T,
-    complex64 host states), replayed at the same arrival times against (a)
-    one-at-a-time sre2_m2 calls and (b) the continuous-batching server.
-    The arrival rate is `load` / (mean one-at-a-time service time)."""
-    reqs = W.serving_requests(count, n_min=n_lo, n_max=n_hi)
-    states = [W.build_request(r) for r in reqs]
-    log(f"serving: {count} requests generated")
-    # calibration of the one-at-a-time service time per N
-    t_n = {}
-    for N in sorted({r["N"] for r in reqs}):
-        psi = next(p for p, r in zip(states, reqs) if r["N"] == N)
-        best = 1e9
-        for _ in range(3):
-            t0 = time.perf_counter()
-            sre2.m2(torch.from_numpy(psi).to("cuda:0"), form=form)
-            best = min(best, time.perf_counter() - t0)
-        t_n[N] = best
+def serving_benchmark(sre2, torch, W, reqs, states, form: str, load: float,
+                      n_lo: int = 8, n_hi: int = 18, t_n=None):
+    """Poisson stream of the given requests (N ~ U{n_lo..n_hi}, Haar or
+    graph+T, complex64 host states), replayed at the same arrival times
+    against (a) one-at-a-time sre2_m2 calls and (b) the continuous-batching
+    server.  The arrival rate is `load` / (mean one-at-a-time service time):
+    load > 1 saturates the GPU, so throughput is GPU-bound.  Latency is from
+    the scheduled arrival to the result on the host."""
+    count = len(reqs)
+    if t_n is None:
+        t_n = service_times(sre2, torch, reqs, states, form)
     mean_service = float(np.mean([t_n[r["N"]] for r in reqs]))
     lam = load / mean_service
     arrivals = np.cumsum(np.random.default_rng(W.SEED_SERVING + 1).exponential(1 / lam, count))
@@ -246,9 +311,9 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
         base_lat.append(time.perf_counter() - (t0 + arrivals[i]))
         base_res.append(r)
         if (i + 1) % 512 == 0:
-            log(f"serving: one-at-a-time {i + 1}/{count}")
+            log(f"serving load {load}: one-at-a-time {i + 1}/{count}")
     base_makespan = time.perf_counter() - t0
-    log(f"serving: one-at-a-time done in {base_makespan:.1f} s")
+    log(f"serving load {load}: one-at-a-time done in {base_makespan:.1f} s")
 
     # (b) continuous batching
     srv = sre2.Server(form=form, hbm_budget=8 << 30, max_slots=2048)
@@ -271,20 +336,26 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
         lag.append(time.perf_counter() - (t0 + arrivals[i]))
         tickets.append(srv.submit(psi))
         if (i + 1) % 512 == 0:
-            log(f"serving: server {i + 1}/{count} submitted, {len(done)} done")
+            log(f"serving load {load}: server {i + 1}/{count} submitted, {len(done)} done")
     while len(done) < count:
         poll_some()
         time.sleep(0.0002)
     srv_makespan = time.perf_counter() - t0
     stats = srv.stats()
     srv.close()
-    log(f"serving: server done in {srv_makespan:.1f} s; stats={stats}")
+    log(f"serving load {load}: server done in {srv_makespan:.1f} s; stats={stats}")
     mismatch = sum(1 for j in range(count)
                    if done[j][1].m2 != base_res[j].m2 or done[j][1].S != base_res[j].S)
     srv_lat = [done[j][2] for j in range(count)]
+    fmax = 14 if not form.startswith("fp64") else 13
+    small = [j for j in range(count) if reqs[j]["N"] <= fmax]
+    large = [j for j in range(count) if reqs[j]["N"] > fmax]
 
     def pct(v, q):
-        return float(np.percentile(np.array(v) * 1e3, q))
+        return float(np.percentile(np.array(v) * 1e3, q)) if len(v) else None
+
+    def lane(lat, idx):
+        return {"p50_ms": pct([lat[j] for j in idx], 50), "p99_ms": pct([lat[j] for j in idx], 99)}
 
     return {
         "requests": count, "N_range": [n_lo, n_hi], "form": form,
@@ -292,52 +363,210 @@ def serving_benchmark(sre2, torch, W, count: int, form: str, load: float = 0.7,
         "pauli_strings": work,
         "server": {"throughput_pauli_per_s": work / srv_makespan,
                    "requests_per_s": count / srv_makespan, "makespan_s": srv_makespan,
-                   "p50_ms": pct(srv_lat, 50), "p99_ms": pct(srv_lat, 99), "stats": stats},
+                   "p50_ms": pct(srv_lat, 50), "p99_ms": pct(srv_lat, 99),
+                   "small_N": lane(srv_lat, small), "large_N": lane(srv_lat, large),
+                   "stats": stats},
         "one_at_a_time": {"throughput_pauli_per_s": work / base_makespan,
                           "requests_per_s": count / base_makespan,
                           "makespan_s": base_makespan,
-                          "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99)},
+                          "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99),
+                          "small_N": lane(base_lat, small), "large_N": lane(base_lat, large)},
         "results_bitwise_equal": mismatch == 0, "mismatches": mismatch,
     }
+
+
+def service_times(sre2, torch, reqs, states, form):
+    """Calibration: the best of three one-at-a-time service times per N."""
+    t_n = {}
+    for N in sorted({r["N"] for r in reqs}):
+        psi = next(p for p, r in zip(states, reqs) if r["N"] == N)
+        best = 1e9
+        for _ in range(3):
+            t0 = time.perf_counter()
+            sre2.m2(torch.from_numpy(psi).to("cuda:0"), form=form)
+            best = min(best, time.perf_counter() - t0)
+        t_n[N] = best
+    return t_n
+
+
+def serving_legs(sre2, torch, W, count_sat: int, count_07: int, form: str):
+    """The serving configuration: `count_sat` requests at 4x the one-at-a-time
+    service rate (saturating) and the first `count_07` at 0.7 of it."""
+    n = max(count_sat, count_07)
+    reqs = W.serving_requests(n)
+    states = [W.build_request(r) for r in reqs]
+    log(f"serving: {n} requests generated")
+    t_n = service_times(sre2, torch, reqs, states, form)
+    out = {}
+    if count_sat:
+        out["saturating"] = serving_benchmark(sre2, torch, W, reqs[:count_sat],
+                                              states[:count_sat], form, 4.0, t_n=t_n)
+    if count_07:
+        out["load_0.7"] = serving_benchmark(sre2, torch, W, reqs[:count_07],
+                                            states[:count_07], form, 0.7, t_n=t_n)
+    return out
 
 
 def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"),
                       work=2 ** 35):
     """Large slabs: whole two-pass chunks of the full-evaluation launch shape
-    (shifts from x = 2^(N-1)) per (N, form), `work` slab values in total
-    (about 0.14 s: a timed region of only a few launches reads low, because
-    the clocks ramp up after the host's synchronisation), with each pass's
-    algorithmic HBM rate and its fraction of the 8 TB/s peak, and the
-    full-evaluation time this implies."""
+    per (N, form), `work` slab values in total (about 0.14 s: a timed region
+    of only a few launches reads low, because the clocks ramp up after the
+    host's synchronisation), with each pass's algorithmic HBM rate and its
+    fraction of the 8 TB/s peak, and the full-evaluation time this implies.
+    The timed range is placed over stored oracle shifts of the same state
+    (tests/golden), and the partials computed there are checked against them
+    (relative 1e-4, the FP32 per-shift bar)."""
+    g = golden()
     out = {}
     for N in Ns:
-        psi = torch.from_numpy(W.haar(N, W.SEED_LARGE + (0 if N == 22 else 1), np.complex64))
-        d = psi.to("cuda:0")
+        name = f"haar{N}_sampled"
+        psi_np = W.haar(N, W.SEED_LARGE + (0 if N == 22 else 1), np.complex64)
+        rec = g.get(name)
+        ref = dict(zip(rec["shifts"], rec["partials"])) if rec and \
+            rec.get("sha256") == sha256(psi_np) else {}
+        d = torch.from_numpy(psi_np).to("cuda:0")
         for form in forms:
             ctx = new_context(sre2)
             cs, P = ctx.chunking(N, form)
             chunks = max(1, work // (cs << N))
-            x0 = 1 << (N - 1)
-            sre2.shift_partials(d, x0, cs, form=form, ctx=ctx)  # warm-up chunk
+            span = chunks * cs
+            # the chunk-aligned range of `span` shifts holding the most stored shifts
+            starts = sorted({(x // cs) * cs for x in ref if x >= 2 * cs})
+            best, x0 = -1, 1 << (N - 1)
+            for st in starts:
+                st = min(st, (1 << N) - span)
+                k = sum(1 for x in ref if st <= x < st + span)
+                if k > best:
+                    best, x0 = k, st
+            sre2.shift_partials(d, x0 - cs, cs, form=form, ctx=ctx)  # warm-up chunk
             torch.cuda.synchronize()
             ctx.set_timing(True)
             t0 = time.perf_counter()
-            sre2.shift_partials(d, x0 + cs, chunks * cs, form=form, ctx=ctx)
+            part = sre2.shift_partials(d, x0, span, form=form, ctx=ctx)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             kt = ctx.timing_read()
             ctx.close()
+            got = part.cpu().numpy()
+            xs = [x for x in ref if x0 <= x < x0 + span]
+            errs = [abs(got[x - x0] - ref[x]) / ref[x] for x in xs]
+            if errs and max(errs) > 1e-4:
+                raise RuntimeError(f"N={N} {form}: partials off the stored oracle values "
+                                   f"(max rel {max(errs):.3g})")
             by, _ = alg_units(N, form, "pass1", cs)
-            rec = {"shifts_per_chunk": cs, "chunks_timed": chunks,
-                   "row_bits": sre2.row_bits(N, form),
-                   "s_per_evaluation": dt / (chunks * cs) * (1 << N)}
+            r = {"shifts_per_chunk": cs, "chunks_timed": chunks, "x_begin": x0,
+                 "row_bits": sre2.row_bits(N, form),
+                 "s_per_evaluation": dt / span * (1 << N),
+                 "oracle_checked_shifts": len(xs),
+                 "max_rel_err_vs_oracle": max(errs) if errs else None}
             for k in ("pass1", "pass2"):
                 ms, n = kt[k]
                 gbs = by / (ms / 1e3 / n) / 1e9
-                rec[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_GBs": round(gbs, 1),
-                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
-            out[f"N{N}_{form}"] = rec
-            log(f"large N={N} {form}: {rec}")
+                r[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_GBs": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            out[f"N{N}_{form}"] = r
+            log(f"large N={N} {form}: {r}")
+    return out
+
+
+def n10_leg(sre2, torch, W, forms, reps=50):
+    """The N = 10 complex128 states (Haar, |T>^10, graph state) in every form:
+    mean device time per evaluation over `reps` back-to-back evaluations and
+    the M2 of each (compared with the oracle after the CPU leg)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for name, psi, closed in W.workload_inputs("n10_small"):
+        d = torch.from_numpy(psi).to("cuda:0")
+        for form in forms:
+            o, _ = sre2.m2_async(d, form=form)
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                o, _ = sre2.m2_async(d, form=form)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            m2 = o[0].item()
+            out.setdefault(name, {"closed_form": closed})[form] = {
+                "M2": m2, "ms_per_eval": round(ms, 4),
+                "pauli_per_s": float(4 ** 10) / (ms / 1e3),
+                "abs_dM2_vs_closed_form": abs(m2 - closed) if closed is not None else None}
+    return out
+
+
+def n16_leg(sre2, torch, W, forms, reps=3):
+    """The N = 16 batch (32 Haar + 8 graph+T, complex64) through the packed
+    batched path, per form: device time of one batch and the largest |dM2|
+    against the stored oracle values (Haar) and the closed forms (graph+T)."""
+    g = golden()
+    inputs = W.workload_inputs("n16_batch")
+    ds = [torch.from_numpy(p).to("cuda:0") for _, p, _ in inputs]
+    refs = [closed if closed is not None else stored_m2(g, f"haar16_batch_{i}", p)
+            for i, (_, p, closed) in enumerate(inputs)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for form in forms:
+        sre2.m2_batched(ds, form=form)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            res = sre2.m2_batched(ds, form=form)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        errs = [abs(r.m2 - ref) for r, ref in zip(res, refs) if ref is not None]
+        out[form] = {"states": len(ds), "ms_per_batch": round(ms, 3),
+                     "pauli_per_s": len(ds) * float(4 ** 16) / (ms / 1e3),
+                     "checked": len(errs), "max_abs_dM2": max(errs) if errs else None}
+        log(f"n16 batch {form}: {out[form]}")
+    return out
+
+
+def n20_graph_t_leg(sre2, torch, W, forms):
+    """The N = 20 graph + T state (m = 10), one evaluation per form, against
+    its closed form 10 log2(4/3) (Clifford invariance and additivity)."""
+    _, psi, closed = W.workload_inputs("n20_single")[1]
+    d = torch.from_numpy(psi).to("cuda:0")
+    out = {"closed_form": closed}
+    for form in forms:
+        t0 = time.perf_counter()
+        r = sre2.m2(d, form=form)
+        out[form] = {"M2": r.m2, "abs_dM2_vs_closed_form": abs(r.m2 - closed),
+                     "seconds": round(time.perf_counter() - t0, 3)}
+        log(f"graph+T N=20 {form}: {out[form]}")
+    return out
+
+
+def n20_snapshot_leg(sre2, torch, W, forms=("fp32", "fp32h"), ts=(5, 16, 21, 37)):
+    """A timed sample of the 64-snapshot N = 20 Ising sequence
+    psi_t = diag(exp(i pi t/64 h)) H^N |0>: seconds per snapshot, with
+    |dM2| against the stored oracle values (t = 5, 21), the Clifford point
+    (t = 16, M2 = 0) and the period (M2(37) = M2(5))."""
+    g = golden()
+    N = 20
+    J = W.snapshot_couplings(N)
+    h = W.ising_energy(N, J)
+    out = {}
+    for form in forms:
+        m, secs = {}, []
+        for t in ts:
+            psi = W.ising_snapshot(N, t, J, dtype=np.complex64, energy=h)
+            d = torch.from_numpy(psi).to("cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m[t] = sre2.m2(d, form=form).m2
+            secs.append(time.perf_counter() - t0)
+            ref = stored_m2(g, f"ising20_t{t}", psi)
+            if ref is not None:
+                m[f"abs_dM2_vs_oracle_t{t}"] = abs(m[t] - ref)
+        out[form] = {"M2": {str(k): v for k, v in m.items()},
+                     "seconds_per_snapshot": round(float(np.mean(secs)), 3),
+                     "snapshots_timed": len(ts),
+                     "abs_M2_clifford_t16": abs(m[16]) if 16 in m else None,
+                     "abs_dM2_period_t37_t5": abs(m[37] - m[5]) if 37 in m and 5 in m else None,
+                     "sequence_64_estimate_s": round(64 * float(np.mean(secs)), 1)}
+        log(f"snapshots {form}: {out[form]}")
     return out
 
 
@@ -382,14 +611,23 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="fp32")
-    ap.add_argument("--also", default="fp32h,split16,splitbf16", help="other forms, comma separated")
+    ap.add_argument("--also", default="fp32h,split16,splitbf16,fp64,fp64h",
+                    help="other forms at N = 20, comma separated")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of each other form")
     ap.add_argument("--N", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
-    ap.add_argument("--serving", type=int, default=160, metavar="R",
-                    help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--mall-probe", action="store_true",
+                    help="run the memory-hierarchy probe (L2 / MALL / HBM ping-pong)")
+    ap.add_argument("--serving", type=int, default=4096, metavar="R",
+                    help="requests of the saturating serving leg (0: skip)")
+    ap.add_argument("--serving-07", type=int, default=1024, metavar="R",
+                    help="requests of the serving leg at 0.7 load (0: skip)")
+    ap.add_argument("--serving-form", default="fp32h")
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="N = 10, N = 16 batch, N = 20 graph+T and snapshot legs (0: skip)")
     ap.add_argument("--dynamics", type=int, default=20, metavar="STEPS",
                     help="TFIM quench steps of the snapshot-pipeline measurement (0: skip)")
     ap.add_argument("--dynamics-N", type=int, default=16)
@@ -408,6 +646,11 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.mall_probe:
+        exe = os.path.join(ROOT, "paper_2512_24685_amd", "probe_mall")
+        if not os.path.exists(exe):
+            sys.exit("probe_mall is not built: run python -m paper_2512_24685_amd.build")
+        sys.exit(subprocess.run([exe]).returncode)
     global SCRATCH_LIMIT
     SCRATCH_LIMIT = int(args.scratch_gib * 2 ** 30)
 
@@ -416,8 +659,9 @@ def main():
     import paper_2512_24685_amd as sre2
     import workloads as W
 
+    t_start = time.perf_counter()
     if args.serving_only:
-        rec = serving_benchmark(sre2, torch, W, args.serving, "fp32")
+        rec = serving_legs(sre2, torch, W, args.serving, args.serving_07, args.serving_form)
         print(json.dumps({"metric": "serving stream: Pauli strings/s and p50/p99 latency",
                           "serving": rec}), flush=True)
         return
@@ -436,6 +680,8 @@ def main():
             log(f"profile chunk {c}: shifts [{x0 + c * cs}, {x0 + (c + 1) * cs})")
         return
 
+    g = golden()
+    ref20 = stored_m2(g, "haar20", psi) if N == 20 else None
     ms_per_step, m2, kt, cs, P = measure(sre2, torch, d_psi, args.form, args.steps, args.warmup)
     step_ms = LAST_STEPS
     value = float(4 ** N) / (ms_per_step / 1e3)
@@ -446,33 +692,56 @@ def main():
     roof["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
 
     forms = {}
-    for f in [x for x in args.also.split(",") if x and x != args.form]:
-        fsteps_n = max(3, args.steps // 2)
-        fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, fsteps_n, min(2, args.warmup))
+    all_forms = [args.form] + [x for x in args.also.split(",") if x and x != args.form]
+    for f in all_forms[1:]:
+        fsteps_n = max(1, args.form_steps)
+        fms, fm2, fkt, fcs, _ = measure(sre2, torch, d_psi, f, fsteps_n, 1)
         fsteps = LAST_STEPS
         fdom = max((k for k in fkt if k != "aux" and fkt[k][1] > 0), key=lambda k: fkt[k][0])
         fk = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[fdom]
         forms[f] = {"value": float(4 ** N) / (fms / 1e3), "ms_per_step": fms, "step_ms": fsteps,
                     "M2": fm2,
+                    "abs_dM2_vs_oracle": abs(fm2 - ref20) if ref20 is not None else None,
                     "abs_dM2_vs_headline": abs(fm2 - m2),
                     "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1], fcs,
                                          stored_traffic(fk, N, f),
                                          evals=fsteps_n),
                     "kernels_ms_per_step": {k: round(v[0] / fsteps_n, 3)
                                             for k, v in fkt.items()}}
-    serving = None
-    if args.serving:
-        serving = serving_benchmark(sre2, torch, W, args.serving, "fp32")
+        log(f"[{f}] {forms[f]['ms_per_step']:.1f} ms per step")
+    configs = {}
+    n10_inputs = n16_sample = None
+    if args.configs and N == 20:
+        configs["n20_graph_t_m10"] = n20_graph_t_leg(sre2, torch, W, all_forms)
+        configs["n10"] = n10_leg(sre2, torch, W, all_forms)
+        configs["n16_batch"] = n16_leg(sre2, torch, W,
+                                       ["fp32", "fp32h", "split16", "splitbf16", "fp64"])
+        configs["n20_snapshots"] = n20_snapshot_leg(sre2, torch, W)
+        n10_inputs = [(name, p) for name, p, _ in W.workload_inputs("n10_small")]
+        n16_sample = [(f"haar16_{i}", W.haar(16, W.SEED_N16_BATCH * 1000 + i, np.complex64))
+                      for i in (0, 1)]
     large = large_n_benchmark(sre2, torch, W) if args.large else None
+    serving = None
+    if args.serving or args.serving_07:
+        serving = serving_legs(sre2, torch, W, args.serving, args.serving_07, args.serving_form)
     dynamics = None
     if args.dynamics:
         dynamics = dynamics_benchmark(sre2, torch, W, args.dynamics_N, args.dynamics, "fp32")
         log(f"dynamics: {dynamics}")
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline: timing the FP64 oracle on a sample of shifts ...")
-        cpu = cpu_baseline(psi, args.cpu_seconds)
+        log("cpu baseline: timing the FP64 oracle on samples of the workloads ...")
+        cpu, refs = cpu_baseline(psi, args.cpu_seconds, n10_inputs, n16_sample)
         log(f"cpu baseline: {cpu}")
+        for name, rec in configs.get("n10", {}).items():
+            if name in refs:
+                rec["oracle_M2"] = refs[name]
+                for f in all_forms:
+                    rec[f]["abs_dM2_vs_oracle"] = abs(rec[f]["M2"] - refs[name])
+        if n16_sample:
+            cpu["n16_sample_matches_stored"] = all(
+                abs(refs[nm] - (stored_m2(g, f"haar16_batch_{nm.split('_')[1]}", p) or np.nan))
+                < 1e-12 for nm, p in n16_sample)
     rec = {
         "metric": METRIC,
         "value": value,
@@ -492,13 +761,17 @@ def main():
                                   if dom != "shift" else
                                   "whole transforms in one workgroup's LDS (fused kernel)"),
                    "N": N, "pauli_strings_per_step": 4 ** N, "form": args.form,
-                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2, "step_ms": step_ms},
+                   "shifts_per_chunk": cs, "column_groups": P, "M2": m2,
+                   "abs_dM2_vs_oracle": abs(m2 - ref20) if ref20 is not None else None,
+                   "step_ms": step_ms},
         "roofline": roof,
         "forms": forms,
+        "configs": configs,
         "serving": serving,
         "large_n": large,
         "dynamics": dynamics,
         "cpu_baseline": cpu,
+        "bench_seconds": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(rec), flush=True)
 

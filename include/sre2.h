@@ -181,14 +181,16 @@ int sre2_sre(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, double 
 int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int nbins,
                         void* stream, uint64_t* counts, double* out);
 
-/* Per-shift sums S_x for x in [x_begin, x_begin + x_count) only - the unit a
- * multi-GPU shard computes (shifts are independent; each GPU takes a range and
- * the totals add).  partials (device, x_count doubles) receives S_x in order.
+/* Per-shift sums S_x for x in [x_begin, x_begin + x_count) only: the body of
+ * Algorithm 1's loop over shifts for a sub-range of x.  The main text notes
+ * that the shifts are independent of each other, so a range is the unit a
+ * multi-GPU shard computes (each GPU takes a range and the totals add).  partials (device, x_count doubles) receives S_x in order.
  * Errors: as sre2_m2, plus SRE2_EINVAL for a range outside [0, 2^N). */
 int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
                   int64_t x_count, void* stream, double* partials);
 
-/* M2 of `count` states, each with its own N (mixed N allowed).
+/* M2 of `count` states, each with its own N (mixed N allowed): Algorithm 1
+ * applied to every state, the states sharing launches where they can.
  *   psi_list  HOST array of `count` device pointers
  *   N_list    HOST array of `count` qubit counts
  *   out       device, SRE2_OUT_LEN * count doubles (state i at out + 4 i)
@@ -230,15 +232,20 @@ int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int
 int sre2_row_bits(int N, int form);
 
 /* ---- serving loop (continuous batching) ------------------------------- */
-/* A server owns a worker thread, two HIP streams, a device arena of
- * hbm_budget_bytes and max_slots request slots.  Requests are admitted in FIFO
- * order while a slot is free and their state fits the arena (admission by HBM
- * footprint; a full arena is backpressure, later requests wait).  Newly
+/* The paper's shift loop consists of independent units (main text: the
+ * computation parallelises over shifts x), so evaluations of different
+ * states can share the device in any interleaving without changing a result.
+ * A server owns a worker thread, two HIP streams, a device arena of
+ * hbm_budget_bytes and max_slots request slots.  Requests wait in one of two
+ * FIFO lanes, small (N <= 14 in FP32 forms / 13 in FP64 forms) and large,
+ * and each lane admits in order while a slot is free and the state fits the
+ * arena (admission by HBM footprint; a full arena is backpressure).  Newly
  * admitted requests are enqueued at once, without waiting for running work:
- * requests with N <= 14 (FP32 forms) / 13 (FP64 forms) admitted together are
- * packed by N into shared launches on one stream, larger N run one by one on
- * a second stream, so their work overlaps on the device.  A request's result
- * is bitwise identical to a single sre2_m2 call on the same state and form. */
+ * small requests admitted together are packed by N into shared launches on
+ * one stream; large ones run on a second stream, at most two enqueued at a
+ * time, so a backlog of large requests waits in its lane and never delays a
+ * small one.  A request's result is bitwise identical to a single sre2_m2
+ * call on the same state and form. */
 typedef struct sre2_server sre2_server;
 
 #define SRE2_REQ_QUEUED 0    /* waiting for a slot / memory            */

@@ -9,6 +9,9 @@ fallback: if the library is not built, loading fails with an error.
     import torch, paper_2512_24685_amd as sre2
     psi = torch.randn(1 << 16, dtype=torch.complex64, device="cuda")
     r = sre2.m2(psi)            # r.m2, r.S, r.n
+
+Calls without an explicit ``ctx`` use a default context per (device, stream):
+a context's workspace serves one stream at a time.
     r3 = sre2.sre(psi, 3.0)     # any Renyi index: r3.m2 holds M_3
     counts, r = sre2.pauli_spectrum(psi, 32)
 """
@@ -167,13 +170,23 @@ class Context:
             pass
 
 
-_contexts: dict[int, Context] = {}
+_contexts: dict[tuple[int, int], Context] = {}
 
 
-def context(device: int = 0) -> Context:
-    if device not in _contexts:
-        _contexts[device] = Context(device)
-    return _contexts[device]
+def context(device: int = 0, stream: int = 0) -> Context:
+    """The default context of calls that pass no ctx: one per (device,
+    stream handle).  A context's workspace must not be used by two streams at
+    once (include/sre2.h), so calls on different streams never share one."""
+    key = (int(device), int(stream))
+    if key not in _contexts:
+        _contexts[key] = Context(device)
+    return _contexts[key]
+
+
+def _ctx_stream(t, ctx, stream):
+    """(context, stream handle) of a call on tensor t."""
+    sp = _stream_ptr(t, stream)
+    return (ctx or context(t.device.index or 0, sp)), sp
 
 
 @dataclass
@@ -226,11 +239,11 @@ def m2_async(psi, form: str = "fp32", partials: bool = False, ctx: Context | Non
     torch = _torch()
     psi = _prep(psi)
     N = _nqubits(psi)
-    ctx = ctx or context(psi.device.index or 0)
+    ctx, sp = _ctx_stream(psi, ctx, stream)
     out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
     part = torch.empty(1 << N, dtype=torch.float64, device=psi.device) if partials else None
     rc = lib().sre2_m2(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
-                       FORMS[form], ctypes.c_void_p(_stream_ptr(psi, stream)),
+                       FORMS[form], ctypes.c_void_p(sp),
                        ctypes.c_void_p(out.data_ptr()),
                        ctypes.c_void_p(part.data_ptr()) if part is not None else None)
     _check(rc, "sre2_m2")
@@ -257,10 +270,10 @@ def sre(psi, alpha: float = 2.0, form: str = "fp32", ctx: Context | None = None,
     torch = _torch()
     psi = _prep(psi)
     N = _nqubits(psi)
-    ctx = ctx or context(psi.device.index or 0)
+    ctx, sp = _ctx_stream(psi, ctx, stream)
     out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
     rc = lib().sre2_sre(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
-                        FORMS[form], float(alpha), ctypes.c_void_p(_stream_ptr(psi, stream)),
+                        FORMS[form], float(alpha), ctypes.c_void_p(sp),
                         ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_sre")
     return _result(out.cpu())
@@ -274,12 +287,12 @@ def pauli_spectrum(psi, nbins: int = 32, form: str = "fp32", ctx: Context | None
     torch = _torch()
     psi = _prep(psi)
     N = _nqubits(psi)
-    ctx = ctx or context(psi.device.index or 0)
+    ctx, sp = _ctx_stream(psi, ctx, stream)
     out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
     counts = torch.empty(int(nbins), dtype=torch.int64, device=psi.device)
     rc = lib().sre2_pauli_spectrum(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N,
                                    _dtype_code(psi), FORMS[form], int(nbins),
-                                   ctypes.c_void_p(_stream_ptr(psi, stream)),
+                                   ctypes.c_void_p(sp),
                                    ctypes.c_void_p(counts.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_pauli_spectrum")
@@ -292,10 +305,10 @@ def moments(psi, ctx: Context | None = None, stream=None):
     torch = _torch()
     psi = _prep(psi)
     N = _nqubits(psi)
-    ctx = ctx or context(psi.device.index or 0)
+    ctx, sp = _ctx_stream(psi, ctx, stream)
     out = torch.empty(3, dtype=torch.float64, device=psi.device)
     rc = lib().sre2_moments(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
-                            ctypes.c_void_p(_stream_ptr(psi, stream)),
+                            ctypes.c_void_p(sp),
                             ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_moments")
     n, ipr, bad = out.cpu().tolist()
@@ -310,11 +323,11 @@ def shift_partials(psi, x_begin: int = 0, x_count: int | None = None, form: str 
     N = _nqubits(psi)
     if x_count is None:
         x_count = (1 << N) - x_begin
-    ctx = ctx or context(psi.device.index or 0)
+    ctx, sp = _ctx_stream(psi, ctx, stream)
     out = torch.empty(max(int(x_count), 1), dtype=torch.float64, device=psi.device)
     rc = lib().sre2_partials(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N, _dtype_code(psi),
                              FORMS[form], int(x_begin), int(x_count),
-                             ctypes.c_void_p(_stream_ptr(psi, stream)),
+                             ctypes.c_void_p(sp),
                              ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_partials")
     return out
@@ -331,13 +344,13 @@ def m2_batched(psis, form: str = "fp32", ctx: Context | None = None, stream=None
         if _dtype_code(p) != dt:
             raise TypeError("all states of a batch must share one dtype")
     dev = psis[0].device
-    ctx = ctx or context(dev.index or 0)
+    ctx, sp = _ctx_stream(psis[0], ctx, stream)
     cnt = len(psis)
     ptrs = (ctypes.c_void_p * cnt)(*[p.data_ptr() for p in psis])
     Ns = (ctypes.c_int * cnt)(*[_nqubits(p) for p in psis])
     out = torch.empty(cnt * OUT_LEN, dtype=torch.float64, device=dev)
     rc = lib().sre2_m2_batched(ctx.handle, ptrs, Ns, cnt, dt, FORMS[form],
-                               ctypes.c_void_p(_stream_ptr(psis[0], stream)),
+                               ctypes.c_void_p(sp),
                                ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_m2_batched")
     o = out.cpu().reshape(cnt, OUT_LEN)

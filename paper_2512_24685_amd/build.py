@@ -15,7 +15,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsre2.so")
-SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip"]
+PROBE = os.path.join(HERE, "probe_mall")  # memory-hierarchy probe (bench.py --mall-probe)
+SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip",
+           "sre2_queries.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -50,6 +52,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
+    cmd = ["hipcc", *HIP_FLAGS, os.path.join(CSRC, "probe_mall.hip"), "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

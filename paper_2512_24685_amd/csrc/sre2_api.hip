@@ -137,7 +137,7 @@ struct Timed {
     size_t slot = 0;
     bool on = false;
     Timed(sre2_ctx* c, hipStream_t s, int k) : ctx(c), st(s), kind(k) {
-        if (!ctx->timing) return;
+        if (!ctx || !ctx->timing) return;
         slot = ctx->pending.size() * 2;
         while (ctx->events.size() < slot + 2) {
             hipEvent_t e;
@@ -163,135 +163,7 @@ int validate(const sre2_ctx* ctx, const void* psi, int N, int dtype, int form) {
     return SRE2_OK;
 }
 
-// Stage the input in the form's working precision; returns the pointer the
-// kernels read.
-int stage_input(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
-                const void** work) {
-    const int wd = work_dtype(form);
-    if (wd == dtype) {
-        *work = psi;
-        return SRE2_OK;
-    }
-    const int64_t n = int64_t(1) << N;
-    int rc = ensure(&ctx->psi_work, &ctx->psi_work_bytes, (size_t)n * elem_bytes(wd));
-    if (rc) return rc;
-    {
-        Timed tm(ctx, st, SRE2_KIND_AUX);
-        rc = hip_status(launch_convert(psi, dtype, ctx->psi_work, wd, n, st));
-    }
-    *work = ctx->psi_work;
-    return rc;
-}
-
-// Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian).
-int two_pass(sre2_ctx* ctx, const void* work, int N, int form, bool herm, int64_t x0, int64_t xc,
-             double* Sx, const int* se, const Spec* spec, size_t limit, hipStream_t st) {
-    const bool f64 = is_f64(form);
-    const int split = split_kind(form);
-    const Chunking ch = chunking(N, form, herm, xc, limit);
-    for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
-        // a short last chunk keeps the same column grouping
-        const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
-        hipError_t e;
-        {
-            Timed tm(ctx, st, SRE2_KIND_PASS1);
-            e = f64 ? launch_pass1<double>(work, N, herm, split, x0 + c0, cs, ctx->scratch, se, st)
-                    : launch_pass1<float>(work, N, herm, split, x0 + c0, cs, ctx->scratch, se, st);
-        }
-        if (e != hipSuccess) return SRE2_EHIP;
-        {
-            Timed tm(ctx, st, SRE2_KIND_PASS2);
-            e = f64 ? launch_pass2<double>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se,
-                                           spec, st)
-                    : launch_pass2<float>(ctx->scratch, N, herm, split, cs, ch.P, ctx->part, se,
-                                          spec, st);
-        }
-        if (e != hipSuccess) return SRE2_EHIP;
-        {
-            Timed tm(ctx, st, SRE2_KIND_AUX);
-            e = launch_group_sum(ctx->part, cs, ch.P, Sx + c0, st);
-        }
-        if (e != hipSuccess) return SRE2_EHIP;
-    }
-    return SRE2_OK;
-}
-
-// S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).  The Hermitian
-// forms route the shifts they cannot take (x = 0 fused, x < 2^L two-pass,
-// or N too small) through the plain kernels of the same precision.
-int shift_sums(sre2_ctx* ctx, const void* work, int N, int form, int64_t x0, int64_t xc,
-               double* Sx, const int* se, const Spec* spec, hipStream_t st) {
-    const bool f64 = is_f64(form);
-    const int sp = split_kind(form);
-    const int64_t x1 = x0 + xc;
-    if (N <= fused_max(form)) {
-        const bool herm = is_herm(form) && N >= herm_min(form);
-        const int64_t split = herm ? (x0 > 1 ? x0 : (x1 < 1 ? x1 : 1)) : x1;  // plain: [x0, split)
-        if (split > x0) {
-            Timed tm(ctx, st, SRE2_KIND_SHIFT);
-            const hipError_t e =
-                f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se,
-                                                  Pack{}, spec, st)
-                    : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se,
-                                                 Pack{}, spec, st);
-            if (e != hipSuccess) return SRE2_EHIP;
-        }
-        if (x1 > split) {
-            Timed tm(ctx, st, SRE2_KIND_SHIFT);
-            const hipError_t e =
-                f64 ? launch_shift_kernel<double>(work, N, true, false, split, x1 - split,
-                                                  Sx + (split - x0), se, Pack{}, spec, st)
-                    : launch_shift_kernel<float>(work, N, true, false, split, x1 - split,
-                                                 Sx + (split - x0), se, Pack{}, spec, st);
-            if (e != hipSuccess) return SRE2_EHIP;
-        }
-        return SRE2_OK;
-    }
-    const bool herm = is_herm(form);
-    // Hermitian-pair two-pass needs x >= 2^L of its own (N - 1)-bit slab
-    const int64_t lim = int64_t(1) << row_bits(form, N - 1);
-    const int64_t split = herm ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
-    // workspace for the larger of the two chunk shapes; when the device
-    // cannot hold it, the chunks shrink (halving the limit for this call)
-    // down to one shift per chunk.  Chunking never changes a result bit.
-    size_t limit = ctx->scratch_limit, need = 0, need_part = 0;
-    const int elem = elem_bytes(work_dtype(form));
-    int rc;
-    for (;;) {
-        need = 0;
-        need_part = 0;
-        int64_t cs_max = 0;
-        if (split > x0) {
-            const Chunking c = chunking(N, form, false, split - x0, limit);
-            need = (size_t)c.cs * (size_t(1) << N) * elem;
-            need_part = (size_t)c.cs * c.P;
-            cs_max = c.cs;
-        }
-        if (x1 > split) {
-            const Chunking c = chunking(N, form, true, x1 - split, limit);
-            const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
-            need = need > b ? need : b;
-            need_part = need_part > (size_t)c.cs * c.P ? need_part : (size_t)c.cs * c.P;
-            cs_max = cs_max > c.cs ? cs_max : c.cs;
-        }
-        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
-        if (rc != SRE2_ENOMEM || cs_max <= 1) break;
-        limit = need / 2;
-    }
-    if (rc) return rc;
-    rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
-    if (rc) return rc;
-    if (split > x0) {
-        rc = two_pass(ctx, work, N, form, false, x0, split - x0, Sx, se, spec, limit, st);
-        if (rc) return rc;
-    }
-    if (x1 > split)
-        rc = two_pass(ctx, work, N, form, true, split, x1 - split, Sx + (split - x0), se, spec,
-                      limit, st);
-    return rc;
-}
-
-// Workspace layout of ctx->red: norm partials, non-finite flags, S partials
+// Layout of Workspace::red: norm partials, non-finite flags, S partials
 // (kMaxRed doubles each), one int (the split form's scale exponent) in a
 // double, then n (the histogram's normalisation).
 struct Red {
@@ -302,21 +174,170 @@ struct Red {
     double* nrm;
 };
 
-int red_buffers(sre2_ctx* ctx, Red* r) {
-    const int rc = ensure((void**)&ctx->red, &ctx->red_bytes, (3 * kMaxRed + 2) * sizeof(double));
-    if (rc) return rc;
-    r->npart = ctx->red;
-    r->nflag = ctx->red + kMaxRed;
-    r->spart = ctx->red + 2 * kMaxRed;
-    r->se = reinterpret_cast<int*>(ctx->red + 3 * kMaxRed);
-    r->nrm = ctx->red + 3 * kMaxRed + 1;
+Red red_of(double* red) {
+    Red r;
+    r.npart = red;
+    r.nflag = red + kMaxRed;
+    r.spart = red + 2 * kMaxRed;
+    r.se = reinterpret_cast<int*>(red + 3 * kMaxRed);
+    r.nrm = red + 3 * kMaxRed + 1;
+    return r;
+}
+
+// Stage the input in the form's working precision (into ws.psi_work when
+// the dtype differs); returns the pointer the kernels read.
+int stage_input(sre2_ctx* tctx, const Workspace& ws, const void* psi, int N, int dtype, int form,
+                hipStream_t st, const void** work) {
+    const int wd = work_dtype(form);
+    if (wd == dtype) {
+        *work = psi;
+        return SRE2_OK;
+    }
+    Timed tm(tctx, st, SRE2_KIND_AUX);
+    *work = ws.psi_work;
+    return hip_status(launch_convert(psi, dtype, ws.psi_work, wd, int64_t(1) << N, st));
+}
+
+// Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian),
+// chunks sized by ws.limit.
+int two_pass(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int form, bool herm,
+             int64_t x0, int64_t xc, double* Sx, const int* se, const Spec* spec,
+             hipStream_t st) {
+    const bool f64 = is_f64(form);
+    const int split = split_kind(form);
+    const Chunking ch = chunking(N, form, herm, xc, ws.limit);
+    for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
+        // a short last chunk keeps the same column grouping
+        const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
+        hipError_t e;
+        {
+            Timed tm(tctx, st, SRE2_KIND_PASS1);
+            e = f64 ? launch_pass1<double>(work, N, herm, split, x0 + c0, cs, ws.scratch, se, st)
+                    : launch_pass1<float>(work, N, herm, split, x0 + c0, cs, ws.scratch, se, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+        {
+            Timed tm(tctx, st, SRE2_KIND_PASS2);
+            e = f64 ? launch_pass2<double>(ws.scratch, N, herm, split, cs, ch.P, ws.part, se,
+                                           spec, st)
+                    : launch_pass2<float>(ws.scratch, N, herm, split, cs, ch.P, ws.part, se,
+                                          spec, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+        {
+            Timed tm(tctx, st, SRE2_KIND_AUX);
+            e = launch_group_sum(ws.part, cs, ch.P, Sx + c0, st);
+        }
+        if (e != hipSuccess) return SRE2_EHIP;
+    }
     return SRE2_OK;
 }
 
-// Norm partials (and, for the split form, its scale exponent).
-int norm_stage(sre2_ctx* ctx, const void* work, int N, int form, const Red& r, int nb,
+// Two-pass workspace of the shifts [x0, x0 + xc) with this scratch limit:
+// *need = slab bytes and *need_part = column-group partials (doubles) for the
+// larger of the plain and Hermitian-pair chunk shapes, *split = the first
+// shift of the Hermitian-pair range (x1 for the plain forms).  Returns the
+// largest chunk (shifts).
+int64_t slab_need(int N, int form, int64_t x0, int64_t xc, size_t limit, size_t* need,
+                  size_t* need_part, int64_t* split) {
+    const int64_t x1 = x0 + xc;
+    // Hermitian-pair two-pass needs x >= 2^L of its own (N - 1)-bit slab
+    const int64_t lim = int64_t(1) << row_bits(form, N - 1);
+    *split = is_herm(form) ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
+    const int elem = elem_bytes(work_dtype(form));
+    *need = 0;
+    *need_part = 0;
+    int64_t cs_max = 0;
+    if (*split > x0) {
+        const Chunking c = chunking(N, form, false, *split - x0, limit);
+        *need = (size_t)c.cs * (size_t(1) << N) * elem;
+        *need_part = (size_t)c.cs * c.P;
+        cs_max = c.cs;
+    }
+    if (x1 > *split) {
+        const Chunking c = chunking(N, form, true, x1 - *split, limit);
+        const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
+        *need = *need > b ? *need : b;
+        *need_part = *need_part > (size_t)c.cs * c.P ? *need_part : (size_t)c.cs * c.P;
+        cs_max = cs_max > c.cs ? cs_max : c.cs;
+    }
+    return cs_max;
+}
+
+// Grow the context's two-pass slab and partials for the shifts [x0, x0 + xc)
+// and set ws.scratch, ws.part and ws.limit.  When the device cannot hold the
+// slab, the chunks shrink (halving the limit for this call) down to one
+// shift per chunk.  Chunking never changes a result bit.
+int ctx_two_pass_ws(sre2_ctx* ctx, int N, int form, int64_t x0, int64_t xc, Workspace* ws) {
+    if (N <= fused_max(form)) return SRE2_OK;
+    size_t limit = ctx->scratch_limit, need = 0, need_part = 0;
+    int64_t split = 0;
+    int rc;
+    for (;;) {
+        const int64_t cs_max = slab_need(N, form, x0, xc, limit, &need, &need_part, &split);
+        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
+        if (rc != SRE2_ENOMEM || cs_max <= 1) break;
+        limit = need / 2;
+    }
+    if (rc) return rc;
+    rc = ensure((void**)&ctx->part, &ctx->part_bytes, need_part * sizeof(double));
+    if (rc) return rc;
+    ws->scratch = ctx->scratch;
+    ws->part = ctx->part;
+    ws->limit = limit;
+    return SRE2_OK;
+}
+
+// S_x for x in [x0, x0 + xc) into Sx (device, xc doubles).  The Hermitian
+// forms route the shifts they cannot take (x = 0 fused, x < 2^L two-pass,
+// or N too small) through the plain kernels of the same precision.
+int shift_sums(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int form,
+               int64_t x0, int64_t xc, double* Sx, const int* se, const Spec* spec,
                hipStream_t st) {
-    Timed tm(ctx, st, SRE2_KIND_AUX);
+    const bool f64 = is_f64(form);
+    const int sp = split_kind(form);
+    const int64_t x1 = x0 + xc;
+    if (N <= fused_max(form)) {
+        const bool herm = is_herm(form) && N >= herm_min(form);
+        const int64_t split = herm ? (x0 > 1 ? x0 : (x1 < 1 ? x1 : 1)) : x1;  // plain: [x0, split)
+        if (split > x0) {
+            Timed tm(tctx, st, SRE2_KIND_SHIFT);
+            const hipError_t e =
+                f64 ? launch_shift_kernel<double>(work, N, false, false, x0, split - x0, Sx, se,
+                                                  Pack{}, spec, st)
+                    : launch_shift_kernel<float>(work, N, false, sp, x0, split - x0, Sx, se,
+                                                 Pack{}, spec, st);
+            if (e != hipSuccess) return SRE2_EHIP;
+        }
+        if (x1 > split) {
+            Timed tm(tctx, st, SRE2_KIND_SHIFT);
+            const hipError_t e =
+                f64 ? launch_shift_kernel<double>(work, N, true, false, split, x1 - split,
+                                                  Sx + (split - x0), se, Pack{}, spec, st)
+                    : launch_shift_kernel<float>(work, N, true, false, split, x1 - split,
+                                                 Sx + (split - x0), se, Pack{}, spec, st);
+            if (e != hipSuccess) return SRE2_EHIP;
+        }
+        return SRE2_OK;
+    }
+    size_t need = 0, need_part = 0;
+    int64_t split = x1;
+    slab_need(N, form, x0, xc, ws.limit, &need, &need_part, &split);
+    int rc = SRE2_OK;
+    if (split > x0) {
+        rc = two_pass(tctx, ws, work, N, form, false, x0, split - x0, Sx, se, spec, st);
+        if (rc) return rc;
+    }
+    if (x1 > split)
+        rc = two_pass(tctx, ws, work, N, form, true, split, x1 - split, Sx + (split - x0), se,
+                      spec, st);
+    return rc;
+}
+
+// Norm partials (and, for the split form, its scale exponent).
+int norm_stage(sre2_ctx* tctx, const void* work, int N, int form, const Red& r, int nb,
+               hipStream_t st) {
+    Timed tm(tctx, st, SRE2_KIND_AUX);
     int rc = hip_status(launch_norm(work, work_dtype(form), int64_t(1) << N, nb, r.npart, r.nflag,
                                     Pack{}, st));
     if (!rc && is_split(form))
@@ -324,47 +345,75 @@ int norm_stage(sre2_ctx* ctx, const void* work, int N, int form, const Red& r, i
     return rc;
 }
 
-// M2 (spec == nullptr), or the general reduction of spec: M_alpha / M_1 in
-// out, or the Pauli-spectrum counts in spec->hist (cleared here first).
-int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st, double* out,
-           double* partials, const Spec* spec = nullptr) {
+// The launch sequence of one evaluation on the buffers of ws: M2
+// (spec == nullptr), or the general reduction of spec: M_alpha / M_1 in out,
+// or the Pauli-spectrum counts in spec->hist (cleared here first).  S_x goes
+// to `partials` when given, else to ws.sx.  tctx (may be null) only records
+// per-launch timing.
+int m2_launch(sre2_ctx* tctx, const Workspace& ws, const void* psi, int N, int dtype, int form,
+              hipStream_t st, double* out, double* partials, const Spec* spec) {
     const void* work = nullptr;
-    int rc = stage_input(ctx, psi, N, dtype, form, st, &work);
+    int rc = stage_input(tctx, ws, psi, N, dtype, form, st, &work);
     if (rc) return rc;
     const int64_t n = int64_t(1) << N;
-    Red r;
-    rc = red_buffers(ctx, &r);
-    if (rc) return rc;
+    const Red r = red_of(ws.red);
     const int nb = red_blocks(n);
-    rc = norm_stage(ctx, work, N, form, r, nb, st);
+    rc = norm_stage(tctx, work, N, form, r, nb, st);
     if (rc) return rc;
-    double* Sx = partials;
-    if (!Sx) {
-        rc = ensure((void**)&ctx->sx, &ctx->sx_bytes, (size_t)n * sizeof(double));
-        if (rc) return rc;
-        Sx = ctx->sx;
-    }
+    double* Sx = partials ? partials : ws.sx;
     Spec sp{};
     if (spec) {
         sp = *spec;
         if (sp.kind == kRedHist) {
-            Timed tm(ctx, st, SRE2_KIND_AUX);
+            Timed tm(tctx, st, SRE2_KIND_AUX);
             rc = hip_status(launch_norm_total(r.npart, nb, r.nrm, st));
             if (!rc) rc = hip_status(launch_zero_u64(sp.hist, sp.nbins, st));
             if (rc) return rc;
             sp.nrm = r.nrm;
         }
     }
-    rc = shift_sums(ctx, work, N, form, 0, n, Sx, r.se, spec ? &sp : nullptr, st);
+    rc = shift_sums(tctx, ws, work, N, form, 0, n, Sx, r.se, spec ? &sp : nullptr, st);
     if (rc) return rc;
     {
-        Timed tm(ctx, st, SRE2_KIND_AUX);
+        Timed tm(tctx, st, SRE2_KIND_AUX);
         rc = hip_status(launch_sum(Sx, n, 1, nb, r.spart, nullptr, Pack{}, st));
     }
     if (rc) return rc;
-    Timed tm(ctx, st, SRE2_KIND_AUX);
+    Timed tm(tctx, st, SRE2_KIND_AUX);
     return hip_status(launch_final(r.spart, nb, r.npart, r.nflag, nb, N, out, Pack{},
                                    spec ? sp.kind : kRedQuartic, spec ? sp.alpha : 2.0, st));
+}
+
+// Grow the context's input copy and reduction buffers (and S_x when the
+// caller passes no partials buffer) for a call of this shape.
+int ctx_common_ws(sre2_ctx* ctx, int N, int dtype, int form, bool need_sx, Workspace* ws) {
+    const int64_t n = int64_t(1) << N;
+    const int wd = work_dtype(form);
+    int rc;
+    if (wd != dtype) {
+        rc = ensure(&ctx->psi_work, &ctx->psi_work_bytes, (size_t)n * elem_bytes(wd));
+        if (rc) return rc;
+        ws->psi_work = ctx->psi_work;
+    }
+    rc = ensure((void**)&ctx->red, &ctx->red_bytes, red_doubles() * sizeof(double));
+    if (rc) return rc;
+    ws->red = ctx->red;
+    if (need_sx) {
+        rc = ensure((void**)&ctx->sx, &ctx->sx_bytes, (size_t)n * sizeof(double));
+        if (rc) return rc;
+        ws->sx = ctx->sx;
+    }
+    return SRE2_OK;
+}
+
+// One evaluation on the context's workspace (grown as needed).
+int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st, double* out,
+           double* partials, const Spec* spec = nullptr) {
+    Workspace ws;
+    int rc = ctx_common_ws(ctx, N, dtype, form, partials == nullptr, &ws);
+    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, 0, int64_t(1) << N, &ws);
+    if (rc) return rc;
+    return m2_launch(ctx, ws, psi, N, dtype, form, st, out, partials, spec);
 }
 
 // Up to kMaxPack states of one N <= fused_max(form) in packed launches: the
@@ -518,13 +567,15 @@ int sre2_row_bits(int N, int form) {
 
 size_t sre2_workspace_bytes(int N, int dtype, int form) {
     if (N < 1 || N > SRE2_MAX_N || !dtype_ok(dtype) || !form_ok(form)) return 0;
+    if (N > (is_f64(form) ? max_n<double>() : max_n<float>())) return 0;
     const size_t n = size_t(1) << N;
-    size_t b = (3 * kMaxRed + 2) * sizeof(double) + n * sizeof(double);
+    size_t b = red_doubles() * sizeof(double) + n * sizeof(double);
     if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
-    const Chunking ch = chunking(N, form, false, (int64_t)n, size_t(4) << 30);
-    if (ch.cs) {
-        b += (size_t)ch.cs * n * (size_t)elem_bytes(work_dtype(form));
-        b += (size_t)ch.cs * ch.P * sizeof(double);
+    if (N > fused_max(form)) {
+        size_t slab = 0, part = 0;
+        int64_t split = 0;
+        slab_need(N, form, 0, (int64_t)n, kDefaultScratchLimit, &slab, &part, &split);
+        b += slab + part * sizeof(double);
     }
     return b;
 }
@@ -574,8 +625,7 @@ int sre2_moments(sre2_ctx* ctx, const void* psi, int N, int dtype, void* stream,
     if (!dtype_ok(dtype)) return SRE2_EDTYPE;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return SRE2_EHIP;
-    Red r;
-    const int rc = red_buffers(ctx, &r);
+    const int rc = ensure((void**)&ctx->red, &ctx->red_bytes, red_doubles() * sizeof(double));
     if (rc) return rc;
     const int64_t n = int64_t(1) << N;
     Timed tm(ctx, (hipStream_t)stream, SRE2_KIND_AUX);
@@ -593,17 +643,19 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return SRE2_EHIP;
     const hipStream_t st = (hipStream_t)stream;
+    Workspace ws;
+    rc = ctx_common_ws(ctx, N, dtype, form, false, &ws);
+    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, x_begin, x_count, &ws);
+    if (rc) return rc;
     const void* work = nullptr;
-    rc = stage_input(ctx, psi, N, dtype, form, st, &work);
+    rc = stage_input(ctx, ws, psi, N, dtype, form, st, &work);
     if (rc) return rc;
-    Red r;
-    rc = red_buffers(ctx, &r);
-    if (rc) return rc;
+    const Red r = red_of(ws.red);
     if (is_split(form)) {
         rc = norm_stage(ctx, work, N, form, r, red_blocks(n), st);
         if (rc) return rc;
     }
-    return shift_sums(ctx, work, N, form, x_begin, x_count, partials, r.se, nullptr, st);
+    return shift_sums(ctx, ws, work, N, form, x_begin, x_count, partials, r.se, nullptr, st);
 }
 
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,

@@ -7,9 +7,16 @@
 
 #include <vector>
 
+#include "sre2_internal.h"
+
+namespace sre2 {
+// Default upper bound of the two-pass slab of a context (sre2_set_scratch_limit).
+constexpr size_t kDefaultScratchLimit = size_t(32) << 30;
+}  // namespace sre2
+
 struct sre2_ctx {
     int device = 0;
-    size_t scratch_limit = size_t(32) << 30;  // halved on allocation failure, per call
+    size_t scratch_limit = sre2::kDefaultScratchLimit;  // halved on allocation failure, per call
     void* psi_work = nullptr;
     size_t psi_work_bytes = 0;
     double* sx = nullptr;  // S_x when the caller passes no partials buffer
@@ -31,6 +38,22 @@ struct sre2_ctx {
 };
 
 namespace sre2 {
+// Device buffers of one evaluation (the context grows them with hipMalloc).
+// Nothing in them needs to start at zero: every kernel writes each entry it
+// later reads.
+struct Workspace {
+    void* psi_work = nullptr;  // input in the form's precision (when the dtype differs)
+    double* red = nullptr;     // norm partials, flags, S partials, scale, n (red_doubles())
+    double* sx = nullptr;      // S_x of every shift (when the caller passes none)
+    void* scratch = nullptr;   // two-pass slab
+    double* part = nullptr;    // two-pass column-group partials of one chunk
+    size_t limit = 0;          // slab bytes available: sets the chunk size
+};
+constexpr size_t red_doubles() { return 3 * (size_t)kMaxRed + 2; }
+
+// Host-side argument check of (N, dtype, form), as sre2_m2 does it.
+int ctx_validate_form(int N, int dtype, int form);
+
 // One full evaluation of one state (sre2_m2 without partials).
 int ctx_m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
                double* out);
@@ -41,6 +64,4 @@ int ctx_fused_max(int form);
 // Grow the packed-launch workspace for every N up to `N` (so that it never
 // has to be reallocated while packed work is in flight).
 int ctx_reserve_pack(sre2_ctx* ctx, int N, int form);
-// Host-side argument check of (N, dtype, form), as sre2_m2 does it.
-int ctx_validate_form(int N, int dtype, int form);
 }  // namespace sre2

@@ -237,34 +237,50 @@ __device__ __forceinline__ uint32_t thread_base() {
     return b;
 }
 
-// LDS slot of register element i: pad(base | r) = pad(base) + pad(r) with
-// r = pdep(i, REG) (disjoint bits), so the thread's byte offset pb_bytes is
-// formed once and pad(r) becomes the instruction's constant offset.
-template <int SB, typename C>
+// LDS slot of register element i, r = pdep(i, REG), for a thread whose own
+// slot offset (bytes) is pb_bytes:
+//  padded buffer: pad(base | r) = pad(base) + pad(r) (disjoint bits), so
+//    pad(r) becomes the instruction's constant offset;
+//  swizzled buffer: the bits of swz(r) at or above SB are tile bits of REG,
+//    where swz(base) is zero, so swz(base) ^ swz(r) = (swz(base) ^ lo) + hi
+//    with lo, hi the parts of swz(r) below and above bit SB: one XOR per
+//    distinct lo, and hi is the constant offset.
+template <int SB, bool PADDED>
+__device__ __forceinline__ uint32_t thread_slot(uint32_t base) {
+    return PADDED ? pad<SB>(base) : swz<SB>(base);
+}
+template <int SB, bool PADDED, typename C>
 __device__ __forceinline__ C* lds_slot(C* lds, uint32_t pb_bytes, uint32_t r) {
-    return reinterpret_cast<C*>(reinterpret_cast<char*>(lds) + pb_bytes +
-                                pad<SB>(r) * (uint32_t)sizeof(C));
+    char* b = reinterpret_cast<char*>(lds);
+    if constexpr (PADDED) {
+        return reinterpret_cast<C*>(b + pb_bytes + pad<SB>(r) * (uint32_t)sizeof(C));
+    } else {
+        const uint32_t e = swz<SB>(r);
+        const uint32_t lo = e & ((1u << SB) - 1u), hi = e & ~((1u << SB) - 1u);
+        return reinterpret_cast<C*>(b + hi * (uint32_t)sizeof(C) +
+                                    (pb_bytes ^ (lo * (uint32_t)sizeof(C))));
+    }
 }
 
 // Registers v[OFF + i], i < 2^RB, hold the elements base | pdep(i, REG).
-template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0, typename C,
-          int NV>
+template <int SB, bool PADDED, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0,
+          typename C, int NV>
 __device__ __forceinline__ void lds_put(C* lds, const C (&v)[NV]) {
     static_assert(OFF + (1 << RB) <= NV, "registers");
-    const uint32_t pb = pad<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
+    const uint32_t pb = thread_slot<SB, PADDED>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i)
-        *lds_slot<SB>(lds, pb, pdep((uint32_t)i, REG)) = v[OFF + i];
+        *lds_slot<SB, PADDED>(lds, pb, pdep((uint32_t)i, REG)) = v[OFF + i];
 }
 
-template <int SB, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0, typename C,
-          int NV>
+template <int SB, bool PADDED, int RB, uint32_t REG, uint32_t LPERM, uint32_t WAVE, int OFF = 0,
+          typename C, int NV>
 __device__ __forceinline__ void lds_get(const C* lds, C (&v)[NV]) {
     static_assert(OFF + (1 << RB) <= NV, "registers");
-    const uint32_t pb = pad<SB>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
+    const uint32_t pb = thread_slot<SB, PADDED>(thread_base<LPERM, WAVE>()) * (uint32_t)sizeof(C);
 #pragma unroll
     for (int i = 0; i < (1 << RB); ++i)
-        v[OFF + i] = *lds_slot<SB>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
+        v[OFF + i] = *lds_slot<SB, PADDED>(const_cast<C*>(lds), pb, pdep((uint32_t)i, REG));
 }
 
 // Plan selector (PK encodes the kind so that plans stay constexpr):
@@ -299,12 +315,6 @@ __host__ __device__ constexpr Plan plan_of() {
                                        : make_plan(TB, RB, SB, 0, PK - 1000);
 }
 
-// LDS values (padded slots) a kernel with plan P declares (1 when it has a
-// single round).
-__host__ __device__ constexpr int lds_values(const Plan& P) {
-    return P.nrounds < 2 ? 1
-                         : (int)pad_rt((P.half ? 1u << (P.tb - 1) : 1u << P.tb) - 1u, P.sb) + 1;
-}
 
 template <int TB, int RB, int PK>
 __host__ __device__ constexpr bool plan_has_mf() {
@@ -431,6 +441,7 @@ struct RoundRunner {
     using C = typename CT<Real>::T;
     static constexpr Plan P = plan_of<Real, TB, RB, PK>();
     static constexpr int SB = Prec<Real>::SB;
+    static constexpr bool PADDED = lds_padded(P);
     __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB], const op8 amat) {
         if constexpr (J < P.nrounds) {
             constexpr Round prev = P.r[J - 1];
@@ -443,18 +454,18 @@ struct RoundRunner {
                 constexpr int HR = 1 << (RB - 1);
                 static_assert((prev.reg >> (TB - 1)) & (cur.reg >> (TB - 1)) & 1u, "half plan");
                 __syncthreads();  // previous readers of the LDS buffer are done
-                lds_put<SB, RB - 1, prev.reg & low, prev.lperm, prev.wave, 0>(lds, v);
+                lds_put<SB, PADDED, RB - 1, prev.reg & low, prev.lperm, prev.wave, 0>(lds, v);
                 __syncthreads();
-                lds_get<SB, RB - 1, cur.reg & low, cur.lperm, cur.wave, 0>(lds, v);
+                lds_get<SB, PADDED, RB - 1, cur.reg & low, cur.lperm, cur.wave, 0>(lds, v);
                 __syncthreads();
-                lds_put<SB, RB - 1, prev.reg & low, prev.lperm, prev.wave, HR>(lds, v);
+                lds_put<SB, PADDED, RB - 1, prev.reg & low, prev.lperm, prev.wave, HR>(lds, v);
                 __syncthreads();
-                lds_get<SB, RB - 1, cur.reg & low, cur.lperm, cur.wave, HR>(lds, v);
+                lds_get<SB, PADDED, RB - 1, cur.reg & low, cur.lperm, cur.wave, HR>(lds, v);
             } else {
                 __syncthreads();  // previous readers of the LDS tile are done
-                lds_put<SB, RB, prev.reg, prev.lperm, prev.wave>(lds, v);
+                lds_put<SB, PADDED, RB, prev.reg, prev.lperm, prev.wave>(lds, v);
                 __syncthreads();
-                lds_get<SB, RB, cur.reg, cur.lperm, cur.wave>(lds, v);
+                lds_get<SB, PADDED, RB, cur.reg, cur.lperm, cur.wave>(lds, v);
             }
             round_math<Real, TB, RB, PK, J>(v, amat);
             RoundRunner<Real, TB, RB, PK, J + 1>::run(lds, v, amat);
@@ -1044,48 +1055,8 @@ hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, do
     return e;
 }
 
-template <typename Real, int... Hs>
-int pass2_tb_rt(int HT, std::integer_sequence<int, Hs...>) {
-    int tb = 0;
-    ((HT == Hs + 1 ? (tb = pass2_tb<Real>(Hs + 1), 0) : 0), ...);
-    return tb;
-}
 
 }  // namespace
-
-template <typename Real>
-int max_n() {
-    return max_n_of<Real>();
-}
-template <typename Real>
-int fused_max_n() {
-    return Tune<Real>::FMAX;
-}
-template <typename Real>
-int pass1_row_bits(int NS) {
-    return row_bits_of<Real>(NS);
-}
-template <typename Real>
-int herm_min_n() {
-    return Tune<Real>::RBF + 1;
-}
-template <typename Real>
-int64_t pass2_col_tiles(int N, bool herm) {
-    const int NS = N - (herm ? 1 : 0);
-    const int HT = NS - row_bits_of<Real>(NS);
-    const int tb = pass2_tb_rt<Real>(HT, std::make_integer_sequence<int, Prec<Real>::MAXTB>{});
-    return tb > 0 ? (int64_t)1 << (NS - tb) : 0;
-}
-template int max_n<float>();
-template int max_n<double>();
-template int fused_max_n<float>();
-template int fused_max_n<double>();
-template int pass1_row_bits<float>(int);
-template int pass1_row_bits<double>(int);
-template int herm_min_n<float>();
-template int herm_min_n<double>();
-template int64_t pass2_col_tiles<float>(int, bool);
-template int64_t pass2_col_tiles<double>(int, bool);
 
 template <typename Real, bool GEN>
 hipError_t shift_kernel_gen(const void* psi, int N, bool herm, int split, int64_t x0,

@@ -10,10 +10,13 @@
 // WHT section: H_{2^N} = H_2^{(x)N}), and those per-bit stages commute, so any
 // order of bits across rounds gives the same transform.
 //
-// LDS addresses are padded: tile element e sits in slot pad(e) = e + (e >> SB)
-// + (e >> 2 SB) + ..., where a slot is one complex value (SB = 5 for 8-byte,
-// 4 for 16-byte values: 2^SB slots are 256 bytes, the 64 four-byte banks), so
-// tile bit b alone moves the slot by 2^(b mod SB) modulo 2^SB.  Measured
+// LDS addresses: tile element e sits in slot pad(e) = e + (e >> SB) +
+// (e >> 2 SB) + ..., or, where that padded buffer would not fit 64 KiB, in
+// slot swz(e) = e with its low SB bits XORed with every higher SB-bit chunk
+// (a bijection, no growth).  A slot is one complex value (SB = 5 for 8-byte,
+// 4 for 16-byte values: 2^SB slots are 256 bytes, the 64 four-byte banks).
+// Under either map tile bit b alone moves the slot by 2^(b mod SB) modulo
+// 2^SB.  Measured
 // on gfx950 with rocprof's LDS bank-conflict counter, an access is free of
 // conflicts when each group of 2^SB lanes hits 2^SB distinct slots modulo
 // 2^SB and, inside it, each half group (128 bytes) hits distinct slots
@@ -21,11 +24,15 @@
 // order, but lane bit SB-1 must map onto slot bit SB-1.  So lane bit i of
 // every round sits on a tile bit of residue i mod SB (i < SB), or at least
 // lane bits 0..SB-2 on residues 0..SB-2 and lane bit SB-1 on residue SB-1.
-// Lane bits of distinct residues add distinct powers of two, and the wave
-// and register bits add the same amount to every lane, so each access is
+// Lane bits of distinct residues contribute distinct powers of two, and the
+// wave and register bits the same amount to every lane, so each access is
 // free of conflicts.  pad is additive over disjoint bits (pad(a | b) =
 // pad(a) + pad(b) when a & b = 0: shifting a carry-free sum carries nothing),
-// so a register element's slot is the thread's slot plus a constant.
+// so a register element's slot is the thread's slot plus a constant, the
+// instruction's immediate offset; the swizzle needs one XOR per element.
+// ds_read / ds_write offsets are 16 bits, so a padded buffer above 64 KiB
+// would need address registers instead, which costs the largest tiles more
+// than the XOR: those keep the swizzle.
 //
 // Tiles above 64 KiB would leave one workgroup per CU (160 KiB of LDS); their
 // half-LDS plans keep the top tile bit in every round's registers, so each
@@ -120,6 +127,18 @@ __host__ __device__ constexpr uint32_t pext(uint32_t v, uint32_t mask) {
     return r;
 }
 
+// Bank swizzle: XOR the low SB bits with every higher SB-bit chunk (GF(2)-linear
+// and a bijection on any power-of-two range).
+template <int SB>
+__host__ __device__ constexpr uint32_t swz(uint32_t e) {
+    uint32_t h = e >> SB, f = 0;
+    while (h) {
+        f ^= h & ((1u << SB) - 1u);
+        h >>= SB;
+    }
+    return e ^ f;
+}
+
 // LDS slot of tile element e: pad(e) = sum over j >= 0 of (e >> SB j).
 template <int SB>
 __host__ __device__ constexpr uint32_t pad(uint32_t e) {
@@ -137,6 +156,20 @@ __host__ __device__ constexpr uint32_t pad_rt(uint32_t e, int sb) {
         e >>= sb;
     }
     return s;
+}
+
+// LDS layout of a plan: the tile bits held in LDS (a half-LDS plan keeps the
+// top bit in registers), whether the buffer is padded (when the padded buffer
+// fits 64 KiB) or swizzled, and the values it declares (1 when the plan has a
+// single round and no transpose).
+__host__ __device__ constexpr int lds_bits(const Plan& P) { return P.half ? P.tb - 1 : P.tb; }
+__host__ __device__ constexpr bool lds_padded(const Plan& P) {
+    return (pad_rt((1u << lds_bits(P)) - 1u, P.sb) + 1u) * (256u >> P.sb) <= 65536u;
+}
+__host__ __device__ constexpr int lds_values(const Plan& P) {
+    return P.nrounds < 2 ? 1
+                         : (lds_padded(P) ? (int)pad_rt((1u << lds_bits(P)) - 1u, P.sb) + 1
+                                          : 1 << lds_bits(P));
 }
 
 // Highest `count` set bits of `m`.

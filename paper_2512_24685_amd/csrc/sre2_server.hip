@@ -1,11 +1,17 @@
 // sre2_server.hip - continuous-batching serving loop of libsre2 (C ABI in
 // include/sre2.h, sre2_server_*).
 //
-// Requests (one state each, mixed N) arrive from any host thread.  A worker
-// thread owned by the server:
-//   * admits queued requests in FIFO order while a request slot is free and
-//     the state fits the device arena (the HBM budget): the arena and the
-//     slots are the admission control, a full arena is backpressure;
+// Requests (one state each, mixed N) arrive from any host thread and wait in
+// one of two FIFO lanes: small (N <= 14 in FP32 forms / 13 in FP64 forms,
+// whole transforms in one workgroup) and large (two-pass).  A worker thread
+// owned by the server:
+//   * admits requests of each lane in FIFO order while a request slot is free
+//     and the state fits the device arena (the HBM budget): the arena and the
+//     slots are the admission control, a full arena is backpressure; the
+//     large lane also keeps at most kLargeInFlight evaluations enqueued on the
+//     device at a time, so a backlog of large requests waits in its host
+//     lane (where the worker is never blocked by a deep device queue) and
+//     small requests never wait behind it;
 //   * copies every newly admitted state into its arena block and enqueues its
 //     evaluation at once, without waiting for earlier work to finish: states
 //     with N <= 14 (FP32 forms) / 13 (FP64 forms) that were admitted together
@@ -139,6 +145,10 @@ struct Flight {
     std::vector<ReqP> reqs;
 };
 
+// Large-lane evaluations enqueued at once: two keep the large stream busy
+// (the next one is queued while one runs) without a deep device queue.
+constexpr int kLargeInFlight = 2;
+
 }  // namespace
 
 struct sre2_server {
@@ -155,7 +165,8 @@ struct sre2_server {
 
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<ReqP> queue;
+    std::deque<ReqP> queue[2];  // lanes: 0 small N, 1 large N
+    int large_inflight = 0;     // admitted large-lane requests not yet retired
     std::map<uint64_t, ReqP> live;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -241,8 +252,11 @@ struct sre2_server {
         if (!f.ev || hipEventRecord(f.ev, st) != hipSuccess) sticky = SRE2_EHIP;
     }
 
+    bool queues_empty() const { return queue[0].empty() && queue[1].empty(); }
+    int lane_of(int N) const { return N <= ctx_fused_max(form) ? 0 : 1; }
+
     // Retire completed flights in stream order (worker only, lock held).
-    bool retire(std::deque<Flight>& q) {
+    bool retire(std::deque<Flight>& q, bool large) {
         bool any = false;
         while (!q.empty()) {
             Flight& f = q.front();
@@ -264,6 +278,7 @@ struct sre2_server {
                 r->staged = nullptr;
                 stat[SRE2_SERVER_STAT_COMPLETED] += 1;
                 --inflight;
+                if (large) --large_inflight;
             }
             if (f.ev) ev_pool.push_back(f.ev);
             q.pop_front();
@@ -276,31 +291,36 @@ struct sre2_server {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            // admission
+            // admission, lane by lane
             std::vector<ReqP> batch;
-            while (!queue.empty()) {
-                ReqP r = queue.front();
-                if (r->cancel) {
-                    r->state = SRE2_REQ_CANCELLED;
-                    r->t_done = now_s();
-                    if (r->staged) staging.free(r->staged);
-                    r->staged = nullptr;
-                    queue.pop_front();
-                    continue;
+            for (int lane = 0; lane < 2; ++lane) {
+                std::deque<ReqP>& q = queue[lane];
+                while (!q.empty()) {
+                    ReqP r = q.front();
+                    if (r->cancel) {
+                        r->state = SRE2_REQ_CANCELLED;
+                        r->t_done = now_s();
+                        if (r->staged) staging.free(r->staged);
+                        r->staged = nullptr;
+                        q.pop_front();
+                        continue;
+                    }
+                    if (free_slots.empty()) break;
+                    if (lane == 1 && large_inflight >= kLargeInFlight) break;
+                    void* p = arena.alloc(r->bytes);
+                    if (!p) break;  // backpressure: wait for memory
+                    r->d_psi = p;
+                    r->slot = free_slots.back();
+                    free_slots.pop_back();
+                    r->state = SRE2_REQ_RUNNING;
+                    q.pop_front();
+                    batch.push_back(r);
+                    ++inflight;
+                    if (lane == 1) ++large_inflight;
+                    stat[SRE2_SERVER_STAT_ADMITTED] += 1;
+                    stat[SRE2_SERVER_STAT_PEAK_INFLIGHT] =
+                        std::max<int64_t>(stat[SRE2_SERVER_STAT_PEAK_INFLIGHT], inflight);
                 }
-                if (free_slots.empty()) break;
-                void* p = arena.alloc(r->bytes);
-                if (!p) break;  // backpressure: wait for memory
-                r->d_psi = p;
-                r->slot = free_slots.back();
-                free_slots.pop_back();
-                r->state = SRE2_REQ_RUNNING;
-                queue.pop_front();
-                batch.push_back(r);
-                ++inflight;
-                stat[SRE2_SERVER_STAT_ADMITTED] += 1;
-                stat[SRE2_SERVER_STAT_PEAK_INFLIGHT] =
-                    std::max<int64_t>(stat[SRE2_SERVER_STAT_PEAK_INFLIGHT], inflight);
             }
             if (!batch.empty()) {
                 lk.unlock();
@@ -311,13 +331,13 @@ struct sre2_server {
                 stat[SRE2_SERVER_STAT_PACKED_STATES] += counts[1];
                 stat[SRE2_SERVER_STAT_SINGLES] += counts[2];
             }
-            const bool done_small = retire(fl_small);  // retire both lists
-            const bool done_large = retire(fl_large);
+            const bool done_small = retire(fl_small, false);  // retire both lists
+            const bool done_large = retire(fl_large, true);
             const bool done_any = done_small || done_large;
             stat[SRE2_SERVER_STAT_PEAK_BYTES] = (int64_t)arena.peak();
             if (done_any) cv.notify_all();
             const bool busy = !fl_small.empty() || !fl_large.empty();
-            if (stop && queue.empty() && !busy) break;
+            if (stop && queues_empty() && !busy) break;
             if (busy) {
                 lk.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -415,7 +435,7 @@ int sre2_server_submit(sre2_server* s, const void* psi, int N, int dtype, int ps
         return SRE2_EBUSY;
     }
     r->ticket = s->next_ticket++;
-    s->queue.push_back(r);
+    s->queue[s->lane_of(N)].push_back(r);
     s->live[r->ticket] = r;
     s->stat[SRE2_SERVER_STAT_SUBMITTED] += 1;
     *ticket = r->ticket;
@@ -456,9 +476,9 @@ int sre2_server_drain(sre2_server* s, double timeout_s) {
     std::unique_lock<std::mutex> lk(s->mu);
     const auto deadline = std::chrono::steady_clock::now() +
                           std::chrono::microseconds((int64_t)(timeout_s * 1e6));
-    while (!(s->queue.empty() && s->inflight == 0)) {
+    while (!(s->queues_empty() && s->inflight == 0)) {
         if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout &&
-            !(s->queue.empty() && s->inflight == 0))
+            !(s->queues_empty() && s->inflight == 0))
             return SRE2_EBUSY;
     }
     return s->sticky;

@@ -66,7 +66,8 @@ int probe_pass1_rb(int precision, int tb, int split) {
 // split-FP16 plan with tail split - 1 (0 none, 1 store round, 2 registers
 // inside [0, hi) at the end); half-LDS plans for the two-pass tiles above
 // 64 KiB and the fused tiles of fused_half.  Returns the round count, plus
-// 100 for a half-LDS plan.
+// 100 for a half-LDS plan, plus 1000 when its LDS buffer is padded (else
+// swizzled).
 int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int kind, unsigned* out) {
     const bool f32 = sb == 5;
     const bool big = f32 ? sre2::half_lds<float>(tb) : sre2::half_lds<double>(tb);
@@ -85,10 +86,30 @@ int probe_plan(int tb, int rb, int sb, int lo, int hi, int split, int kind, unsi
         out[6 * j + 4] = p.r[j].lperm;
         out[6 * j + 5] = p.r[j].mf;
     }
-    return p.nrounds + (p.half ? 100 : 0);
+    return p.nrounds + (p.half ? 100 : 0) + (sre2::lds_padded(p) ? 1000 : 0);
+}
+
+// LDS values a kernel with this plan declares.
+int probe_lds_values(int tb, int rb, int sb, int lo, int hi, int split, int kind) {
+    unsigned out[48];
+    (void)out;
+    const bool f32 = sb == 5;
+    const bool big = f32 ? sre2::half_lds<float>(tb) : sre2::half_lds<double>(tb);
+    const bool half =
+        kind == 0 ? !split && (f32 ? sre2::fused_half<float>(hi) : sre2::fused_half<double>(hi))
+                  : big && hi == tb && lo < tb - 1;
+    const sre2::Plan p =
+        split ? (half ? sre2::make_split_plan_half(tb, rb, sb, lo, split - 1)
+                      : sre2::make_split_plan(tb, rb, sb, lo, hi, split - 1))
+              : (half ? sre2::make_plan_half(tb, rb, sb, lo) : sre2::make_plan(tb, rb, sb, lo, hi));
+    return sre2::lds_values(p);
 }
 
 unsigned probe_pad(int sb, unsigned e) {
     return sb == 5 ? sre2::pad<5>(e) : sb == 4 ? sre2::pad<4>(e) : sre2::pad<3>(e);
+}
+
+unsigned probe_swz(int sb, unsigned e) {
+    return sb == 5 ? sre2::swz<5>(e) : sb == 4 ? sre2::swz<4>(e) : sre2::swz<3>(e);
 }
 }

@@ -166,3 +166,34 @@ def test_row_bits_query(L):
     assert L.sre2_row_bits(22, f["fp64"]) == 12 and L.sre2_row_bits(24, f["fp64"]) == 13
     assert L.sre2_row_bits(0, f["fp32"]) == -1 and L.sre2_row_bits(20, 99) == -1
     assert L.sre2_row_bits(25, f["fp64"]) == -1  # beyond the FP64 maximum
+
+
+def test_workspace_bytes_covers_default_chunks(L):
+    """sre2_workspace_bytes sizes the slab with the default scratch limit of a
+    fresh context: at least the slab of one default chunk (shifts per chunk
+    from sre2_chunking) for the plain and the Hermitian-pair forms."""
+    ctx = sre2.Context(0)
+    try:
+        for form, herm in (("fp32", False), ("fp32h", True), ("split16", False),
+                           ("fp64", False), ("fp64h", True)):
+            elem = 16 if form.startswith("fp64") else 8
+            for N in (15, 18, 20, 22, 24):
+                if N > 24 and form.startswith("fp64"):
+                    continue
+                cs, P = ctx.chunking(N, form)
+                ns = N - (1 if herm else 0)
+                slab = cs * (1 << ns) * elem
+                got = L.sre2_workspace_bytes(N, sre2.C64, sre2.FORMS[form])
+                assert got >= slab + cs * P * 8 + (1 << N) * 8, (form, N, got, slab)
+                # and no more than a full default scratch limit beyond the rest
+                assert got <= (32 << 30) + (1 << N) * 8 * 4 + (1 << 20), (form, N, got)
+    finally:
+        ctx.close()
+
+
+def test_default_context_per_stream():
+    """Calls without a ctx on different streams get different contexts."""
+    a = sre2.context(0, 111)
+    b = sre2.context(0, 222)
+    assert a is not b
+    assert sre2.context(0, 111) is a

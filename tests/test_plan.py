@@ -4,7 +4,7 @@ The constexpr plan builder of the kernels (paper_2512_24685_amd/csrc/sre2_plan.h
 is compiled into a small host probe.  The tests then replay, with numpy, the
 exact index arithmetic of the kernels - global load mapping, register
 butterflies, the split form's H_16 factors in the matrix-core operand layout,
-padded LDS transposes between rounds, final mapping, two-pass scratch
+padded or swizzled LDS transposes between rounds, final mapping, two-pass scratch
 layout - and compare with the Walsh-Hadamard transform over the same bits and
 with the oracle's per-shift sums.  They also check that every round's LDS
 accesses hit distinct bank slots within each group of 2^SB lanes.
@@ -30,6 +30,7 @@ def probe(tmp_path_factory):
     lib = ctypes.CDLL(so)
     lib.probe_plan.restype = ctypes.c_int
     lib.probe_pad.restype = ctypes.c_uint
+    lib.probe_swz.restype = ctypes.c_uint
     return lib
 
 
@@ -50,8 +51,10 @@ def geo(lib, precision, kind, param=0):
 class Rounds(list):
     """A plan's rounds; half = True for a half-LDS plan (the top tile bit is
     the top register-index bit of every round and each transpose moves the
-    register halves with that bit 0, then 1, through half the tile)."""
+    register halves with that bit 0, then 1, through half the tile);
+    padded = True when its LDS slots are padded, else swizzled."""
     half = False
+    padded = False
 
 
 KINDS = {"fused": 0, "pass1": 1, "pass2": 2}
@@ -65,7 +68,8 @@ def plan(lib, tb, rb, sb, lo, hi, split=0, kind="pass1"):
     out = (ctypes.c_uint * 48)()
     n = lib.probe_plan(tb, rb, sb, lo, hi, split, KINDS[kind], out)
     r = Rounds(tuple(out[6 * j:6 * j + 6]) for j in range(n % 100))
-    r.half = n >= 100
+    r.half = (n % 1000) >= 100
+    r.padded = n >= 1000
     return r
 
 
@@ -95,13 +99,32 @@ def pdep(v: np.ndarray, mask: int) -> np.ndarray:
 
 
 def pad_np(sb, e):
-    """LDS slot of tile element e: e + (e >> sb) + (e >> 2 sb) + ..."""
+    """Padded LDS slot of tile element e: e + (e >> sb) + (e >> 2 sb) + ..."""
     s = np.zeros_like(e)
     h = np.array(e, copy=True)
     while np.any(h):
         s += h
         h >>= sb
     return s
+
+
+def swz_np(sb, e):
+    """Swizzled LDS slot: the low sb bits XORed with every higher sb-bit chunk."""
+    h = e >> sb
+    f = np.zeros_like(e)
+    while np.any(h):
+        f ^= h & ((1 << sb) - 1)
+        h >>= sb
+    return e ^ f
+
+
+def slot_np(rounds, sb, e):
+    return pad_np(sb, e) if rounds.padded else swz_np(sb, e)
+
+
+def lds_slots(rounds, sb, t):
+    """Slots of the LDS buffer of a tile with t bits in LDS."""
+    return int(pad_np(sb, np.array([(1 << t) - 1]))[0]) + 1 if rounds.padded else 1 << t
 
 
 def mapping(rd, tb, rb):
@@ -176,10 +199,9 @@ def run_tile(X, rounds, tb, rb, sb):
     top, hr = 1 << (tb - 1), 1 << (rb - 1)
     for j in range(1, len(rounds)):
         if not half:
-            lds = np.full(X.shape[:-1] + (int(pad_np(sb, np.array([(1 << tb) - 1]))[0]) + 1,),
-                          np.nan + 0j)
-            lds[..., pad_np(sb, E[j - 1])] = V
-            V = round_math(lds[..., pad_np(sb, E[j])], rounds[j])
+            lds = np.full(X.shape[:-1] + (lds_slots(rounds, sb, tb),), np.nan + 0j)
+            lds[..., slot_np(rounds, sb, E[j - 1])] = V
+            V = round_math(lds[..., slot_np(rounds, sb, E[j])], rounds[j])
             continue
         W = np.empty_like(V)
         for h in (0, 1):
@@ -187,10 +209,9 @@ def run_tile(X, rounds, tb, rb, sb):
             # the register half holds exactly the elements with top bit h
             assert np.all((E[j - 1][:, regs] & top) == h * top)
             assert np.all((E[j][:, regs] & top) == h * top)
-            lds = np.full(X.shape[:-1] + (int(pad_np(sb, np.array([top - 1]))[0]) + 1,),
-                          np.nan + 0j)
-            lds[..., pad_np(sb, E[j - 1][:, regs] & (top - 1))] = V[..., regs]
-            W[..., regs] = lds[..., pad_np(sb, E[j][:, regs] & (top - 1))]
+            lds = np.full(X.shape[:-1] + (lds_slots(rounds, sb, tb - 1),), np.nan + 0j)
+            lds[..., slot_np(rounds, sb, E[j - 1][:, regs] & (top - 1))] = V[..., regs]
+            W[..., regs] = lds[..., slot_np(rounds, sb, E[j][:, regs] & (top - 1))]
             assert not np.isnan(W[..., regs]).any()
         V = round_math(W, rounds[j])
     out = np.empty_like(X)
@@ -339,6 +360,36 @@ def test_padding_injective_and_additive(probe):
             assert full[1 << b] % (1 << sb) == (1 << (b % sb)) % (1 << sb)
 
 
+def test_swizzle_bijective_and_linear(probe):
+    for sb in (3, 4, 5):
+        e = np.arange(1 << 14, dtype=np.int64)
+        s = np.array([probe.probe_swz(sb, int(v)) for v in e[:4096]])
+        assert np.array_equal(s, swz_np(sb, e[:4096]))
+        full = swz_np(sb, e)
+        assert np.array_equal(np.sort(full), e)
+        a, b = 0x1234 & 0x3FFF, 0x0F0F & 0x3FFF
+        assert swz_np(sb, np.array([a ^ b]))[0] == swz_np(sb, np.array([a]))[0] ^ swz_np(sb, np.array([b]))[0]
+
+
+def test_lds_layout_per_plan(probe):
+    """A plan's LDS is padded exactly when the padded buffer fits 64 KiB (the
+    reach of the ds instructions' 16-bit offsets), and the kernel declares
+    pad(2^t - 1) + 1 values then, else 2^t (t = the tile bits in LDS)."""
+    seen = set()
+    for prec, kind, par, args in all_plans(probe):
+        tb, rb, sb, lo, hi, split = args
+        rounds = plan(probe, *args, kind=kind)
+        if len(rounds) < 2:
+            continue
+        t = tb - 1 if rounds.half else tb
+        padded_bytes = (int(pad_np(sb, np.array([(1 << t) - 1]))[0]) + 1) * (256 >> sb)
+        assert rounds.padded == (padded_bytes <= 65536), (prec, kind, par, args)
+        want = padded_bytes // (256 >> sb) if rounds.padded else 1 << t
+        assert probe.probe_lds_values(*args, KINDS[kind]) == want
+        seen.add(rounds.padded)
+    assert seen == {True, False}
+
+
 def test_lds_bank_slots_distinct(probe):
     """Every LDS access of a round (padded slots) hits 2^SB distinct slots modulo 2^SB in
     each group of 2^SB lanes (256 bytes) and distinct slots modulo 2^(SB-1)
@@ -353,7 +404,7 @@ def test_lds_bank_slots_distinct(probe):
             continue
         for j, rd in enumerate(rounds):
             M = mapping(rd, tb, rb)
-            E = pad_np(sb, M & ((1 << (tb - 1)) - 1) if rounds.half else M)
+            E = slot_np(rounds, sb, M & ((1 << (tb - 1)) - 1) if rounds.half else M)
             slots = E & ((1 << sb) - 1)
             g = 1 << sb
             T = E.shape[0]
