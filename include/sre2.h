@@ -59,6 +59,7 @@ extern "C" {
 #define SRE2_EBUSY (-7)      /* serving: no free slot or HBM budget right now */
 #define SRE2_ECANCELLED (-8) /* serving: request was cancelled */
 #define SRE2_ENOTFOUND (-9)  /* serving: unknown ticket */
+#define SRE2_ESCRATCH (-10)  /* allocation-free call: problem larger than its fixed scratch */
 
 /* ---- element types ----------------------------------------------------- */
 #define SRE2_C64 0  /* complex64: float32 (re, im) */
@@ -200,6 +201,37 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
  * result is bitwise identical to a single sre2_m2 call. */
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,
                     int dtype, int form, void* stream, double* out);
+
+/* ---- allocation-free evaluation ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * sre2_m2 without a context: the same launch sequence and kernels (results
+ * bitwise equal to sre2_m2 on the same psi, N, dtype and form), with every
+ * intermediate buffer carved out of one fixed device array of
+ * SRE2_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends.  The call never allocates or frees device
+ * memory (no hipMalloc, hipFree or allocating library routine).  The array's
+ * device address is looked up once per device, on the first call there
+ * (with that device current).
+ *   hip_device  device to run on (made current for the call)
+ *   psi, N, dtype, form, stream, out, partials: as sre2_m2
+ * Two-pass shapes (N >= 15 in FP32 forms, 14 in FP64 forms) run in chunks
+ * of as many shifts as the array holds, so large N is slower than sre2_m2.
+ * Limit: the call is accepted when the input copy (dtype != the form's
+ * precision), S_x (when partials == NULL), the reduction buffers and one
+ * shift's slab fit the array - N <= 20 in the FP32 forms and N <= 19 in
+ * the FP64 forms for complex64 input without a partials buffer; larger
+ * problems return SRE2_ESCRATCH before any work is enqueued.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (two host threads, or two streams whose work overlaps)
+ * race and corrupt each other's results.  No part of the array needs to
+ * start at zero (each kernel writes every entry it later reads).
+ * Errors: SRE2_EINVAL (hip_device < 0, null psi or out, N out of range),
+ * SRE2_EDTYPE, SRE2_EFORM, SRE2_ESCRATCH, SRE2_EHIP. */
+#define SRE2_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sre2_m2_noalloc(int hip_device, const void* psi, int N, int dtype, int form, void* stream,
+                    double* out, double* partials);
 
 /* ---- measurement ------------------------------------------------------- */
 /* Kernel classes for per-launch timing. */

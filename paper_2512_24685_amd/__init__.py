@@ -26,8 +26,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsre2.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sre2.h")
 
-OK, EINVAL, EDTYPE, EFORM, ENORM, ENOMEM, EHIP, EBUSY, ECANCELLED, ENOTFOUND = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+OK, EINVAL, EDTYPE, EFORM, ENORM, ENOMEM, EHIP, EBUSY, ECANCELLED, ENOTFOUND, ESCRATCH = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10)
+NOALLOC_SCRATCH_BYTES = 32 << 20
 C64, C128 = 0, 1
 FORMS = {"fp32": 0, "split16": 1, "splitbf16": 2, "fp64": 3, "fp32h": 4, "fp64h": 5}
 MAX_N = 26
@@ -64,6 +65,7 @@ def lib():
         "sre2_set_scratch_limit": ([vp, sz], c_int),
         "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
+        "sre2_m2_noalloc": ([c_int, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_partials": ([vp, vp, c_int, c_int, c_int, i64, i64, vp, vp], c_int),
         "sre2_moments": ([vp, vp, c_int, c_int, vp, vp], c_int),
         "sre2_sre": ([vp, vp, c_int, c_int, c_int, ctypes.c_double, vp, vp], c_int),
@@ -248,6 +250,23 @@ def m2_async(psi, form: str = "fp32", partials: bool = False, ctx: Context | Non
                        ctypes.c_void_p(part.data_ptr()) if part is not None else None)
     _check(rc, "sre2_m2")
     return out, part
+
+
+def m2_noalloc_async(psi, out, form: str = "fp32", partials=None, stream=None):
+    """sre2_m2_noalloc: one evaluation into the caller's `out` (float64
+    device tensor of 4) and optional `partials` (float64 device tensor of
+    2^N), with no device allocation by the library (its intermediate buffers
+    live in a fixed device array shared by every such call on the device)."""
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    rc = lib().sre2_m2_noalloc(psi.device.index or 0, ctypes.c_void_p(psi.data_ptr()), N,
+                               _dtype_code(psi), FORMS[form],
+                               ctypes.c_void_p(_stream_ptr(psi, stream)),
+                               ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(partials.data_ptr()) if partials is not None
+                               else None)
+    _check(rc, "sre2_m2_noalloc")
+    return out
 
 
 def _result(out_row, part=None) -> Result:

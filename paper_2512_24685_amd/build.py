@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsre2.so")
 PROBE = os.path.join(HERE, "probe_mall")  # memory-hierarchy probe (bench.py --mall-probe)
 SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip",
-           "sre2_queries.hip"]
+           "sre2_noalloc.hip", "sre2_queries.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

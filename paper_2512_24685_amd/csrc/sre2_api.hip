@@ -479,6 +479,43 @@ int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, 
 }  // namespace
 
 namespace sre2 {
+int ws_m2(const Workspace& ws, const void* psi, int N, int dtype, int form, hipStream_t st,
+          double* out, double* partials) {
+    return m2_launch(nullptr, ws, psi, N, dtype, form, st, out, partials, nullptr);
+}
+int ws_layout(int N, int dtype, int form, bool need_sx, size_t bytes, size_t* psi_work_off,
+              size_t* sx_off, size_t* part_off, size_t* slab_off, size_t* limit) {
+    const size_t n = size_t(1) << N;
+    const auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t off = up(red_doubles() * sizeof(double));
+    *psi_work_off = *sx_off = *part_off = *slab_off = 0;
+    *limit = 0;
+    if (work_dtype(form) != dtype) {
+        *psi_work_off = off;
+        off = up(off + n * (size_t)elem_bytes(work_dtype(form)));
+    }
+    if (need_sx) {
+        *sx_off = off;
+        off = up(off + n * sizeof(double));
+    }
+    if (off > bytes) return SRE2_ESCRATCH;
+    if (N <= fused_max(form)) return SRE2_OK;
+    // the largest chunks whose slab and partials fit what is left
+    size_t lim = bytes - off, need = 0, need_part = 0;
+    int64_t split = 0;
+    for (;;) {
+        const int64_t cs = slab_need(N, form, 0, (int64_t)n, lim, &need, &need_part, &split);
+        const size_t pb = up(need_part * sizeof(double));
+        if (off + pb + need <= bytes) {
+            *part_off = off;
+            *slab_off = off + pb;
+            *limit = need;
+            return SRE2_OK;
+        }
+        if (cs <= 1) return SRE2_ESCRATCH;
+        lim = need / 2;
+    }
+}
 int ctx_m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream_t st,
                double* out) {
     return m2_one(ctx, psi, N, dtype, form, st, out, nullptr);
@@ -521,6 +558,9 @@ const char* sre2_strerror(int status) {
         case SRE2_EBUSY: return "no free slot or memory budget";
         case SRE2_ECANCELLED: return "request cancelled";
         case SRE2_ENOTFOUND: return "unknown ticket";
+        case SRE2_ESCRATCH:
+            return "problem needs more device memory than the fixed scratch of the "
+                   "allocation-free entry point";
         default: return "unknown status code";
     }
 }

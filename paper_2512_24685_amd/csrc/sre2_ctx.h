@@ -38,9 +38,10 @@ struct sre2_ctx {
 };
 
 namespace sre2 {
-// Device buffers of one evaluation (the context grows them with hipMalloc).
-// Nothing in them needs to start at zero: every kernel writes each entry it
-// later reads.
+// Device buffers of one evaluation.  The context path grows them with
+// hipMalloc; the allocation-free entry point carves them out of a fixed
+// device array.  Nothing in them needs to start at zero: every kernel writes
+// each entry it later reads.
 struct Workspace {
     void* psi_work = nullptr;  // input in the form's precision (when the dtype differs)
     double* red = nullptr;     // norm partials, flags, S partials, scale, n (red_doubles())
@@ -51,6 +52,15 @@ struct Workspace {
 };
 constexpr size_t red_doubles() { return 3 * (size_t)kMaxRed + 2; }
 
+// sre2_m2 on the buffers of ws (no allocation, no timing).
+int ws_m2(const Workspace& ws, const void* psi, int N, int dtype, int form, hipStream_t st,
+          double* out, double* partials);
+// Byte offsets of the parts of a Workspace inside one buffer of `bytes`
+// (reduction buffer at 0, every part 256-byte aligned) and the slab bytes
+// (limit) for a call of this shape; SRE2_ESCRATCH when even one shift per
+// chunk does not fit.
+int ws_layout(int N, int dtype, int form, bool need_sx, size_t bytes, size_t* psi_work_off,
+              size_t* sx_off, size_t* part_off, size_t* slab_off, size_t* limit);
 // Host-side argument check of (N, dtype, form), as sre2_m2 does it.
 int ctx_validate_form(int N, int dtype, int form);
 

@@ -64,7 +64,21 @@ int main() {
             int64_t cs = 0;
             int P = 0;
             (void)sre2_chunking(ctx, N, form, &cs, &P);
+            // the allocation-free call lays out its array for every shape and
+            // rejects what it cannot hold; the rest reaches the (absent) device
+            for (int dt = 0; dt <= 1; ++dt) {
+                const int rc = sre2_m2_noalloc(0, fake, N, dt, form, NULL, fout, NULL);
+                EXPECT(rc == SRE2_EINVAL || rc == SRE2_EFORM || rc == SRE2_ESCRATCH ||
+                           rc == SRE2_EHIP,
+                       1);
+            }
         }
+    EXPECT(sre2_m2_noalloc(0, fake, 21, SRE2_C64, SRE2_FORM_FP32, NULL, fout, NULL),
+           SRE2_ESCRATCH);
+    EXPECT(sre2_m2_noalloc(0, fake, 26, SRE2_C128, SRE2_FORM_FP32_HERM, NULL, fout, NULL),
+           SRE2_ESCRATCH);
+    EXPECT(sre2_m2_noalloc(-1, fake, 10, SRE2_C64, SRE2_FORM_FP32, NULL, fout, NULL),
+           SRE2_EINVAL);
     EXPECT(sre2_workspace_bytes(20, SRE2_C64, SRE2_FORM_FP32) > (size_t(32) << 30), 1);
     EXPECT(sre2_destroy(ctx), SRE2_OK);
     EXPECT(sre2_destroy(NULL), SRE2_OK);

@@ -31,7 +31,7 @@ def test_exports_every_header_function(L):
 
 def test_version_and_strerror(L):
     assert L.sre2_version() >= 100
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         s = L.sre2_strerror(code)
         assert s and s != b"unknown status code"
     assert L.sre2_strerror(12345) == b"unknown status code"
@@ -197,3 +197,20 @@ def test_default_context_per_stream():
     b = sre2.context(0, 222)
     assert a is not b
     assert sre2.context(0, 111) is a
+
+
+def test_noalloc_argument_validation(L):
+    """sre2_m2_noalloc rejects bad arguments and problems larger than its
+    fixed scratch on the host, before touching a device."""
+    f = sre2.FORMS
+    assert L.sre2_m2_noalloc(-1, FAKE, 10, 0, 0, None, FAKE, None) == sre2.EINVAL
+    assert L.sre2_m2_noalloc(0, None, 10, 0, 0, None, FAKE, None) == sre2.EINVAL
+    assert L.sre2_m2_noalloc(0, FAKE, 10, 0, 0, None, None, None) == sre2.EINVAL
+    assert L.sre2_m2_noalloc(0, FAKE, 0, 0, 0, None, FAKE, None) == sre2.EINVAL
+    assert L.sre2_m2_noalloc(0, FAKE, 10, 5, 0, None, FAKE, None) == sre2.EDTYPE
+    assert L.sre2_m2_noalloc(0, FAKE, 10, 0, 99, None, FAKE, None) == sre2.EFORM
+    # beyond the documented limits (complex64 input, no partials buffer)
+    assert L.sre2_m2_noalloc(0, FAKE, 21, sre2.C64, f["fp32"], None, FAKE, None) == sre2.ESCRATCH
+    assert L.sre2_m2_noalloc(0, FAKE, 20, sre2.C64, f["fp64"], None, FAKE, None) == sre2.ESCRATCH
+    assert L.sre2_m2_noalloc(0, FAKE, 26, sre2.C64, f["fp32h"], None, FAKE, None) == sre2.ESCRATCH
+    assert L.sre2_strerror(sre2.ESCRATCH) != b"unknown status code"

@@ -3,8 +3,8 @@
 * The FP64 oracle (oracle/sre2_oracle.c) with gcc's AddressSanitizer and
   UndefinedBehaviorSanitizer (leak checks on), driven over every entry point
   on small states and its argument checks (tests/sanitize/oracle_driver.c).
-* The host code of libsre2 (argument checks, workspace sizing, contexts,
-  server and simulator setup) built with the
+* The host code of libsre2 (argument checks, workspace sizing, contexts, the
+  allocation-free call's layout, server and simulator setup) built with the
   host sanitizers only (every -fsanitize= behind -Xarch_host; device code is
   not instrumented), linked against test stand-ins for the kernel launchers
   (tests/sanitize/stub_launchers.hip) and driven by
@@ -48,8 +48,8 @@ def test_host_abi_under_asan_ubsan(tmp_path):
                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
     flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    srcs = [os.path.join(CSRC, f) for f in ("sre2_api.hip", "sre2_server.hip", "sre2_sim.hip",
-                                            "sre2_queries.hip")]
+    srcs = [os.path.join(CSRC, f) for f in ("sre2_api.hip", "sre2_noalloc.hip", "sre2_server.hip",
+                                            "sre2_sim.hip", "sre2_queries.hip")]
     srcs += [os.path.join(SAN, "stub_launchers.hip"), os.path.join(SAN, "abi_driver.cpp")]
     procs, objs = [], []
     for s in srcs:
