@@ -144,18 +144,25 @@ __device__ __forceinline__ Real hist_lnorm2(const Spec& sp) {
 #ifndef SRE2_FUSEDS_WAVES
 #define SRE2_FUSEDS_WAVES 2
 #endif
-// Half-LDS two-pass tiles: four waves per SIMD, i.e. at most 128 registers,
-// so that two 512-thread workgroups share a CU; the half-LDS fused tile (256
-// threads of 64 values) needs two waves per SIMD for two workgroups.
+// Half-LDS tiles: two workgroups share a CU.  Two-pass tiles ask for the
+// waves per SIMD that takes (half_waves: four for 512-thread FP32 tiles, i.e.
+// at most 128 registers, two for 256-thread FP64 tiles); the half-LDS fused
+// tile (256 threads of 64 values) needs two waves per SIMD.
 #ifndef SRE2_FUSEDH_WAVES
 #define SRE2_FUSEDH_WAVES 2
 #endif
 #ifndef SRE2_F32_FUSEDH_WAVES
 #define SRE2_F32_FUSEDH_WAVES SRE2_FUSEDH_WAVES
 #endif
-#ifndef SRE2_HALF_WAVES
-#define SRE2_HALF_WAVES 4
+#ifndef SRE2_HALF_WGS
+#define SRE2_HALF_WGS 2  // workgroups per CU that half-LDS two-pass tiles aim for
 #endif
+// Waves per SIMD that SRE2_HALF_WGS workgroups of 2^(TB - RB) threads need
+// (four SIMDs per CU, 64 lanes per wave): the register budget per wave.
+__host__ __device__ constexpr int half_waves(int tb, int rb) {
+    const int w = SRE2_HALF_WGS * (1 << (tb - rb)) / 256;
+    return w < 1 ? 1 : w;
+}
 // Slab traffic: streamed through the caches (no reuse until the other pass).
 #ifndef SRE2_NT_SLAB
 #define SRE2_NT_SLAB 1
@@ -692,12 +699,13 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // Two-pass, pass 1: row transform over k_lo (TB = L bits) of f_x for a chunk
 // of shifts; the slab of one shift holds 2^NS values (NS = N, or N - 1 in the
 // Hermitian-pair form, which needs x >= 2^L so that the dropped bit hb is a
-// row bit and only rows with that bit clear are built).  Block b -> slab row
-// b / cs, shift slot b % cs, so neighbouring blocks read the same psi rows.
+// row bit and only rows with that bit clear are built).  Grid (cs, rows):
+// block (s, r) takes shift slot s of slab row r; blocks are dispatched with
+// x fastest, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
 template <typename Real, int TB, int RB, bool HERM, int SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? SRE2_HALF_WAVES
+__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? half_waves(TB, RB)
                                    : (SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES))))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
              typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
@@ -708,9 +716,9 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     constexpr Round rl = P.r[P.nrounds - 1];
     __shared__ C lds[lds_values(P)];
 
-    const int64_t b = blockIdx.x;
-    const uint32_t srow = (uint32_t)(b / cs);  // row within the slab
-    const int64_t s = b % cs;
+    (void)cs;
+    const uint32_t srow = blockIdx.y;  // row within the slab
+    const int64_t s = blockIdx.x;      // shift slot in the chunk
     const uint64_t x = (uint64_t)(x0 + s);
     uint32_t row = srow;
     if constexpr (HERM) row = insert0(srow, (63u - (uint32_t)__clzll(x)) - TB);
@@ -756,7 +764,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // ---------------------------------------------------------------------------
 template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
 __global__ __launch_bounds__(1 << (TB - RB))
-__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? SRE2_HALF_WAVES
+__attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? half_waves(TB, RB)
                                    : (SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES))))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
@@ -1107,7 +1115,8 @@ hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, int split, int64_
     using C = typename CT<Real>::T;
     constexpr int RB = pass1_rb<Real>(TB, false), RBS = pass1_rb<Real>(TB, true);
     const int64_t rows = (int64_t)1 << (NS - TB);
-    const dim3 grid((unsigned)(rows * cs)), block(1 << (TB - RB)), blocks(1 << (TB - RBS));
+    if (cs < 1 || rows > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)cs, (unsigned)rows), block(1 << (TB - RB)), blocks(1 << (TB - RBS));
     if (herm)
         hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
                            NS, x0, cs, (C*)scratch, se);
