@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsre2.so")
 PROBE = os.path.join(HERE, "probe_mall")  # memory-hierarchy probe (bench.py --mall-probe)
+PROBE_LDS = os.path.join(HERE, "probe_lds")  # LDS bank-conflict probe (run under rocprofv3)
 SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip",
            "sre2_noalloc.hip", "sre2_queries.hip"]
 ARCH = "gfx950"
@@ -52,11 +53,12 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
-    cmd = ["hipcc", *HIP_FLAGS, os.path.join(CSRC, "probe_mall.hip"), "-o", PROBE + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(PROBE + ".tmp", PROBE)
+    for src, exe in (("probe_mall.hip", PROBE), ("probe_lds.hip", PROBE_LDS)):
+        cmd = ["hipcc", *HIP_FLAGS, os.path.join(CSRC, src), "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(exe + ".tmp", exe)
     return LIB
 
 

@@ -185,25 +185,36 @@ __device__ __forceinline__ void slab_store(double2* p, double2 v) {
         *p = v;
     }
 }
-// NT = false keeps the line in the caches (for tiles that read only part of
-// a 128-byte line per row: the next column tile takes the rest).
-template <bool NT = SRE2_NT_SLAB>
-__device__ __forceinline__ float2 slab_load(const float2* p) {
-    if constexpr (NT) {
-        const f32x2v w = __builtin_nontemporal_load(reinterpret_cast<const f32x2v*>(p));
-        return make_float2(w.x, w.y);
-    } else {
-        return *p;
-    }
+// Reads through a buffer resource (base, size in bytes): an address is the
+// resource base + a per-thread vector offset + a scalar offset, so a gather
+// whose per-element part is uniform across the wave (the register element's
+// part of an index) keeps that part in a scalar register and runs no
+// per-element address arithmetic on the VALU.  Offsets are 32-bit: psi and
+// one shift's slab hold at most 2^26 complex128 values (1 GiB).  AUX is the
+// cache policy; 2 marks a streaming (non-temporal) read.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    // word 3 = 0x00020000: raw (unformatted) 32-bit dword access on gfx9
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
 }
-template <bool NT = SRE2_NT_SLAB>
-__device__ __forceinline__ double2 slab_load(const double2* p) {
-    if constexpr (NT) {
-        const f64x2v w = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p));
-        return make_double2(w.x, w.y);
-    } else {
-        return *p;
-    }
+template <int AUX>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
+                                         float2& v) {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, AUX);
+    __builtin_memcpy(&v, &w, sizeof(v));
+}
+template <int AUX>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
+                                         double2& v) {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, AUX);
+    __builtin_memcpy(&v, &w, sizeof(v));
+}
+// Element vidx + sidx of the resource, vidx per thread, sidx uniform.
+template <typename C, int AUX = 0>
+__device__ __forceinline__ C load_at(__amdgpu_buffer_rsrc_t rs, uint32_t vidx, uint32_t sidx) {
+    C v;
+    buf_load<AUX>(rs, vidx * (uint32_t)sizeof(C), sidx * (uint32_t)sizeof(C), v);
+    return v;
 }
 
 // Insert a zero bit at position `hb` of `v`.
@@ -254,7 +265,7 @@ __device__ __forceinline__ uint32_t thread_base() {
 //    distinct lo, and hi is the constant offset.
 template <int SB, bool PADDED>
 __device__ __forceinline__ uint32_t thread_slot(uint32_t base) {
-    return PADDED ? pad<SB>(base) : swz<SB>(base);
+    return PADDED ? pad16<SB>(base) : swz<SB>(base);
 }
 template <int SB, bool PADDED, typename C>
 __device__ __forceinline__ C* lds_slot(C* lds, uint32_t pb_bytes, uint32_t r) {
@@ -321,7 +332,6 @@ __host__ __device__ constexpr Plan plan_of() {
     return fused_half<Real>(PK - 1000) ? make_plan_half(TB, RB, SB, 0)
                                        : make_plan(TB, RB, SB, 0, PK - 1000);
 }
-
 
 template <int TB, int RB, int PK>
 __host__ __device__ constexpr bool plan_has_mf() {
@@ -449,6 +459,7 @@ struct RoundRunner {
     static constexpr Plan P = plan_of<Real, TB, RB, PK>();
     static constexpr int SB = Prec<Real>::SB;
     static constexpr bool PADDED = lds_padded(P);
+    static_assert(TB <= 16, "tile slots are formed for elements below 2^16");
     __device__ __forceinline__ static void run(C* lds, C (&v)[1 << RB], const op8 amat) {
         if constexpr (J < P.nrounds) {
             constexpr Round prev = P.r[J - 1];
@@ -633,10 +644,11 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
             const uint32_t x = (uint32_t)x0;
             const uint32_t base = thread_base<r0.lperm, r0.wave>();
             const uint32_t vb = base ^ (x & ~r0.reg), xr = x & r0.reg;
+            const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << NT);
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) {
                 const uint32_t r = pdep((uint32_t)i, r0.reg);
-                v[i] = cmul_conj_a((psi + (r ^ xr))[vb], (psi + r)[base]);
+                v[i] = cmul_conj_a(load_at<C>(rs, vb, r ^ xr), load_at<C>(rs, base, r));
                 if constexpr (SPLIT) {
                     v[i].x *= sc;
                     v[i].y *= sc;
@@ -722,14 +734,14 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     const uint64_t x = (uint64_t)(x0 + s);
     uint32_t row = srow;
     if constexpr (HERM) row = insert0(srow, (63u - (uint32_t)__clzll(x)) - TB);
-    const uint64_t rowbase = (uint64_t)row << TB;
-    const uint64_t prow = rowbase ^ (x & ~(uint64_t)((1u << TB) - 1u));  // partner row
+    const uint32_t rowbase = row << TB;
+    const uint32_t prow = rowbase ^ (uint32_t)(x & ~(uint64_t)((1u << TB) - 1u));  // partner row
     const uint32_t xlo = (uint32_t)(x & ((1u << TB) - 1u));
-    const C* __restrict__ pa = psi + rowbase;
-    const C* __restrict__ pb = psi + prow;
+    const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << (NS + (HERM ? 1 : 0)));
     C v[1 << RB];
     {
-        // element e = base | r (disjoint bits): psi[e] = (pa + r)[base], and
+        // element e = base | r (disjoint bits): psi[rowbase + e] takes the
+        // thread part base as vector and rowbase + r as scalar offset, and
         // e ^ xlo = (base ^ (xlo outside REG)) + (r ^ (xlo inside REG)), so
         // the per-element parts are uniform and the per-thread parts are
         // formed once
@@ -738,7 +750,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t r = pdep((uint32_t)i, r0.reg);
-            v[i] = cmul_conj_a((pb + (r ^ xr))[vb], (pa + r)[base]);
+            v[i] = cmul_conj_a(load_at<C>(rs, vb, prow + (r ^ xr)), load_at<C>(rs, base, rowbase + r));
         }
         if constexpr (SPLIT) {
             const Real sc = ldexpf(1.0f, *scale_exp);
@@ -792,20 +804,20 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     const int L = NS - HT;  // row bits of pass 1
     const int ntile = 1 << (L - CB);  // column tiles per shift
     const int per = ntile / P;
-    const C* __restrict__ slab = scratch + ((uint64_t)s << NS);
+    const auto rs = buf_rsrc(scratch + ((uint64_t)s << NS), (uint32_t)sizeof(C) << NS);
+    // tile element e -> slab offset (e >> CB) * 2^L + (e & CMASK), which adds
+    // over disjoint bits: the thread's part once, the register element's part
+    // (and the column tile's) as a uniform offset
+    const uint32_t base = thread_base<r0.lperm, r0.wave>();
+    const uint32_t vb = ((base >> CB) << L) + (base & CMASK);
     double acc = 0.0;
     for (int ct = g * per; ct < (g + 1) * per; ++ct) {
-        const C* __restrict__ src = slab + ((uint64_t)ct << CB);
+        const uint32_t cto = (uint32_t)ct << CB;
         C v[1 << RB];
-        // tile element e -> slab offset (e >> CB) * 2^L + (e & CMASK), which
-        // adds over disjoint bits: the thread's part once, the register
-        // element's part as a uniform offset
-        const uint32_t base = thread_base<r0.lperm, r0.wave>();
-        const uint64_t vb = ((uint64_t)(base >> CB) << L) + (base & CMASK);
 #pragma unroll
         for (int i = 0; i < (1 << RB); ++i) {
             const uint32_t r = pdep((uint32_t)i, r0.reg);
-            v[i] = slab_load<NT>((src + (((uint64_t)(r >> CB) << L) + (r & CMASK))) + vb);
+            v[i] = load_at<C, NT ? 2 : 0>(rs, vb, cto + ((r >> CB) << L) + (r & CMASK));
         }
         run_transform<Real, TB, RB, PK>(lds, v);
         if constexpr (GEN) {

@@ -10,29 +10,36 @@
 // WHT section: H_{2^N} = H_2^{(x)N}), and those per-bit stages commute, so any
 // order of bits across rounds gives the same transform.
 //
-// LDS addresses: tile element e sits in slot pad(e) = e + (e >> SB) +
-// (e >> 2 SB) + ..., or, where that padded buffer would not fit 64 KiB, in
-// slot swz(e) = e with its low SB bits XORed with every higher SB-bit chunk
-// (a bijection, no growth).  A slot is one complex value (SB = 5 for 8-byte,
-// 4 for 16-byte values: 2^SB slots are 256 bytes, the 64 four-byte banks).
-// Under either map tile bit b alone moves the slot by 2^(b mod SB) modulo
-// 2^SB.  Measured
-// on gfx950 with rocprof's LDS bank-conflict counter, an access is free of
-// conflicts when each group of 2^SB lanes hits 2^SB distinct slots modulo
-// 2^SB and, inside it, each half group (128 bytes) hits distinct slots
-// modulo 2^(SB-1): lane bits 0..SB-2 may map onto slot bits 0..SB-2 in any
-// order, but lane bit SB-1 must map onto slot bit SB-1.  So lane bit i of
-// every round sits on a tile bit of residue i mod SB (i < SB), or at least
-// lane bits 0..SB-2 on residues 0..SB-2 and lane bit SB-1 on residue SB-1.
-// Lane bits of distinct residues contribute distinct powers of two, and the
-// wave and register bits the same amount to every lane, so each access is
-// free of conflicts.  pad is additive over disjoint bits (pad(a | b) =
-// pad(a) + pad(b) when a & b = 0: shifting a carry-free sum carries nothing),
-// so a register element's slot is the thread's slot plus a constant, the
+// LDS addresses: a slot is one complex value (SB = 5 for 8-byte, 4 for
+// 16-byte values: 2^SB slots are 256 bytes, the 64 four-byte banks).
+// 8-byte values sit in slot pad(e) = e + (e >> SB) + (e >> 2 SB) + ... of
+// tile element e, or, where that padded buffer would not fit 64 KiB, in slot
+// swz(e) = e with its low SB bits XORed with every higher SB-bit chunk (a
+// bijection, no growth); 16-byte values always take swz.  Under either map
+// tile bit b alone moves the slot by 2^(b mod SB) modulo 2^SB.  Measured on
+// gfx950 with rocprof's LDS bank-conflict counter:
+//  - an 8-byte access is free of conflicts when each group of 32 lanes hits
+//    32 distinct slots modulo 32 and, inside it, each half group (128 bytes)
+//    distinct slots modulo 16: lane bits 0..3 may map onto slot bits 0..3 in
+//    any order, but lane bit 4 must map onto slot bit 4;
+//  - a 16-byte read is served eight lanes (128 bytes) at a time: each
+//    eight-lane group must hit eight distinct slots of one 128-byte half of
+//    the bank row (slot bits 0..2 distinct, bit 3 equal), and consecutive
+//    groups must alternate between the halves, i.e. slot bit 3 must follow
+//    lane bit 3 and no other lane bit.  (16-byte writes showed no such
+//    constraint.)
+// So lane bit i of every round sits on a tile bit of residue i mod SB
+// (i < SB), and with SB = 4 the lane bits above 3 avoid residue 3.  Lane bits
+// of distinct residues contribute distinct powers of two, and the wave and
+// register bits the same amount to every lane, so each access is free of
+// conflicts.  pad is additive over disjoint bits (pad(a | b) = pad(a) +
+// pad(b) when a & b = 0: shifting a carry-free sum carries nothing), so a
+// register element's slot is the thread's slot plus a constant, the
 // instruction's immediate offset; the swizzle needs one XOR per element.
-// ds_read / ds_write offsets are 16 bits, so a padded buffer above 64 KiB
-// would need address registers instead, which costs the largest tiles more
-// than the XOR: those keep the swizzle.
+// Additive padding cannot meet the 16-byte read rule: the lane bits' sums
+// carry into slot bit 3.  ds_read / ds_write offsets are 16 bits, so a
+// padded buffer above 64 KiB would need address registers instead, which
+// costs the largest tiles more than the XOR: those keep the swizzle.
 //
 // Tiles above 64 KiB would leave one workgroup per CU (160 KiB of LDS); their
 // half-LDS plans keep the top tile bit in every round's registers, so each
@@ -149,6 +156,14 @@ __host__ __device__ constexpr uint32_t pad(uint32_t e) {
     }
     return s;
 }
+// The same sum for e < 2^16 (every tile here has at most 2^14 elements) as a
+// fixed, branch-free sequence of shifts and adds, for slots formed at run time.
+template <int SB>
+__host__ __device__ constexpr uint32_t pad16(uint32_t e) {
+    uint32_t s = e;
+    for (int j = SB; j < 16; j += SB) s += e >> j;
+    return s;
+}
 __host__ __device__ constexpr uint32_t pad_rt(uint32_t e, int sb) {
     uint32_t s = 0;
     while (e) {
@@ -159,12 +174,12 @@ __host__ __device__ constexpr uint32_t pad_rt(uint32_t e, int sb) {
 }
 
 // LDS layout of a plan: the tile bits held in LDS (a half-LDS plan keeps the
-// top bit in registers), whether the buffer is padded (when the padded buffer
-// fits 64 KiB) or swizzled, and the values it declares (1 when the plan has a
-// single round and no transpose).
+// top bit in registers), whether the buffer is padded (8-byte values, when the
+// padded buffer fits 64 KiB) or swizzled, and the values it declares (1 when
+// the plan has a single round and no transpose).
 __host__ __device__ constexpr int lds_bits(const Plan& P) { return P.half ? P.tb - 1 : P.tb; }
 __host__ __device__ constexpr bool lds_padded(const Plan& P) {
-    return (pad_rt((1u << lds_bits(P)) - 1u, P.sb) + 1u) * (256u >> P.sb) <= 65536u;
+    return P.sb >= 5 && (pad_rt((1u << lds_bits(P)) - 1u, P.sb) + 1u) * (256u >> P.sb) <= 65536u;
 }
 __host__ __device__ constexpr int lds_values(const Plan& P) {
     return P.nrounds < 2 ? 1
@@ -204,8 +219,14 @@ __host__ __device__ constexpr Round make_round(int tb, int sb, uint32_t reg, uin
         }
     }
     // lane-id bit i takes the matched bit of residue i, the lowest remaining
-    // bits fill the rest
-    const uint32_t fill = low_bits(free_bits, 6 - popc(matched));
+    // bits fill the rest; with 16-byte slots (sb = 4) the fill avoids residue
+    // 3 where it can, so that slot bit 3 follows lane bit 3 alone
+    const int nfill = 6 - popc(matched);
+    uint32_t off_top = 0;
+    for (int b = 0; b < tb; ++b)
+        if (((free_bits >> b) & 1u) && !(sb == 4 && b % sb == sb - 1)) off_top |= 1u << b;
+    uint32_t fill = low_bits(off_top, nfill);
+    if (popc(fill) < nfill) fill |= low_bits(free_bits & ~fill, nfill - popc(fill));
     uint32_t lp = 0;
     int nl = 0;
     for (int i = 0; i < sb && i < 6; ++i)
