@@ -584,6 +584,12 @@ __global__ __launch_bounds__(64) void k_tiny(const typename CT<Real>::T* __restr
     S_out[idx] = s;
 }
 
+// Fused tiles that hold one shift and keep psi[k] in registers (see k_fused).
+template <typename Real>
+__host__ __device__ constexpr bool fused_keeps_psi(int NT, bool herm) {
+    return sizeof(Real) == 4 && !herm && fused_tb<Real>(NT) == NT;
+}
+
 // ---------------------------------------------------------------------------
 // Fused: whole transforms of NT bits in a 2^TB tile of SPT = 2^(TB-NT) shifts.
 //  HERM = false: NT = N, the tile element (slot j, k) is f_x(k), x = x0 + j.
@@ -634,21 +640,33 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     const Real sc = SPLIT ? ldexpf(1.0f, se) : Real(1);
     const double unscale = SPLIT ? ldexp(1.0, -4 * se) : 1.0;
     const int64_t ntiles = (x_count + SPT - 1) / SPT;
+    // one shift per tile: k = e = base | r (disjoint bits) does not depend on
+    // the tile, so FP32 tiles read psi[k] once per workgroup and keep it in
+    // registers over the tiles the workgroup takes (FP64 tiles have no
+    // registers left for it)
+    constexpr bool ONE = SPT == 1 && !HERM;
+    constexpr bool KEEP = fused_keeps_psi<Real>(NT, HERM);
+    const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << NT);
+    C psik[KEEP ? (1 << RB) : 1];
+    if constexpr (KEEP) {
+        const uint32_t base = thread_base<r0.lperm, r0.wave>();
+#pragma unroll
+        for (int i = 0; i < (1 << RB); ++i) psik[i] = load_at<C>(rs, base, pdep((uint32_t)i, r0.reg));
+    }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t x0 = x_begin + tile * SPT;  // first shift of the tile
         C v[1 << RB];
-        if constexpr (SPT == 1 && !HERM) {
-            // one shift per tile, k = e = base | r (disjoint bits): as in
-            // pass 1, k ^ x = (base ^ (x outside REG)) + (r ^ (x inside REG)),
-            // so the per-element address parts are uniform
+        if constexpr (ONE) {
+            // as in pass 1, k ^ x = (base ^ (x outside REG)) + (r ^ (x inside
+            // REG)), so the per-element address parts are uniform
             const uint32_t x = (uint32_t)x0;
             const uint32_t base = thread_base<r0.lperm, r0.wave>();
             const uint32_t vb = base ^ (x & ~r0.reg), xr = x & r0.reg;
-            const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << NT);
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) {
                 const uint32_t r = pdep((uint32_t)i, r0.reg);
-                v[i] = cmul_conj_a(load_at<C>(rs, vb, r ^ xr), load_at<C>(rs, base, r));
+                v[i] = cmul_conj_a(load_at<C>(rs, vb, r ^ xr),
+                                   KEEP ? psik[KEEP ? i : 0] : load_at<C>(rs, base, r));
                 if constexpr (SPLIT) {
                     v[i].x *= sc;
                     v[i].y *= sc;
@@ -1004,6 +1022,18 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 namespace {
 
+// Workgroups of `threads` threads of `kernel` the current device holds at
+// once (CUs x occupancy); 32768 if the runtime cannot say.
+int64_t resident_workgroups(const void* kernel, int threads) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        cus < 1 || per < 1)
+        return 32768;
+    return (int64_t)cus * per;
+}
+
 template <typename Real, int N, bool GEN>
 hipError_t launch_tiny_n(const void* psi, int64_t x0, int64_t xc, double* S,
                          const Pack& pk, const Spec& sp, hipStream_t st) {
@@ -1021,7 +1051,17 @@ hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, c
     constexpr int TB = fused_tb<Real>(NT), RB = fused_rb<Real>(NT, SPLIT != 0);
     constexpr int SPT = 1 << (TB - NT);
     const int64_t ntiles = (xc + SPT - 1) / SPT;
-    const int64_t grid = ntiles < 65536 ? ntiles : 65536;
+    // Tiles that keep psi[k] in registers amortise its reads over the tiles a
+    // workgroup takes: their grid is twice the workgroups the GPU holds at
+    // once (queried once per kernel; measured at N = 14, 0.58 -> 0.44 ms),
+    // the others take one tile per workgroup up to 65536 workgroups.
+    int64_t cap = 65536;
+    if constexpr (fused_keeps_psi<Real>(NT, HERM)) {
+        static const int64_t resident = resident_workgroups(
+            reinterpret_cast<const void*>(&k_fused<Real, NT, TB, RB, HERM, SPLIT, GEN>), 1 << (TB - RB));
+        cap = 2 * resident;
+    }
+    const int64_t grid = ntiles < cap ? ntiles : cap;
     hipLaunchKernelGGL((k_fused<Real, NT, TB, RB, HERM, SPLIT, GEN>), dim3((unsigned)grid, (unsigned)(pk.count ? pk.count : 1)),
                        dim3(1 << (TB - RB)), 0, st, (const C*)psi, x0, xc, S, se, pk, sp);
     return hipGetLastError();
