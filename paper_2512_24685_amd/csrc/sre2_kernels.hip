@@ -12,6 +12,8 @@
 //  k_tiny      N < RB: one thread per shift, whole transform in registers.
 //  k_fused     RB <= N <= TB: a workgroup holds 2^(TB-N) complete shifts in a
 //              2^TB tile; rounds of register butterflies with LDS transposes.
+//              Workgroups loop over tiles; FP32 one-shift tiles keep psi[k]
+//              in registers across them.
 //  k_pass1     N > TB: row transform over the low TB bits of k, f_x built on
 //              the fly from psi, written to a scratch slab.
 //  k_pass2     N > TB: column transform over the high N-TB bits, |W|^4 and a
