@@ -144,15 +144,24 @@ def stored_traffic(kernel: str, N: int, form: str):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    """The host CPU's model name, family / model numbers and logical CPU count
+    (from /proc/cpuinfo, as lscpu reports them)."""
+    fields = {}
+    count = 0
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key == "processor":
+                    count += 1
+                elif key in ("model name", "cpu family", "model") and key not in fields:
+                    fields[key] = val.strip()
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = fields.get("model name", "unknown")
+    return (f"{name} (family {fields.get('cpu family', '?')}, model {fields.get('model', '?')}; "
+            f"{count} logical CPUs on the host)")
 
 
 def cpu_baseline(psi: np.ndarray, target_s: float, n10=None, n16=None):
