@@ -8,6 +8,9 @@
 namespace sre2 {
 
 constexpr int kMaxN = 26;
+// Kernels read psi and one shift's slab through buffer resources with 32-bit
+// byte offsets: 2^kMaxN complex128 values must stay below 4 GiB.
+static_assert((16ull << kMaxN) < (1ull << 32), "psi and a shift's slab need 32-bit offsets");
 
 constexpr int kMaxRed = 1024;  // upper bound of reduction blocks per state
 constexpr int kMaxPack = 64;   // states per packed launch
