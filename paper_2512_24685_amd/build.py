@@ -17,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsre2.so")
 PROBE = os.path.join(HERE, "probe_mall")  # memory-hierarchy probe (bench.py --mall-probe)
 PROBE_LDS = os.path.join(HERE, "probe_lds")  # LDS bank-conflict probe (run under rocprofv3)
+PROBE_STORE = os.path.join(HERE, "probe_store")  # HBM store-rate probe of slab layouts
 SOURCES = ["sre2_kernels.hip", "sre2_api.hip", "sre2_server.hip", "sre2_sim.hip",
            "sre2_noalloc.hip", "sre2_queries.hip"]
 ARCH = "gfx950"
@@ -53,7 +54,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
-    for src, exe in (("probe_mall.hip", PROBE), ("probe_lds.hip", PROBE_LDS)):
+    for src, exe in (("probe_mall.hip", PROBE), ("probe_lds.hip", PROBE_LDS),
+                     ("probe_store.hip", PROBE_STORE)):
         cmd = ["hipcc", *HIP_FLAGS, os.path.join(CSRC, src), "-o", exe + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
