@@ -648,7 +648,7 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
     // registers left for it)
     constexpr bool ONE = SPT == 1 && !HERM;
     constexpr bool KEEP = fused_keeps_psi<Real>(NT, HERM);
-    const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << NT);
+    const auto rs = buf_rsrc(psi, (uint32_t)sizeof(C) << (NT + (HERM ? 1 : 0)));
     C psik[KEEP ? (1 << RB) : 1];
     if constexpr (KEEP) {
         const uint32_t base = thread_base<r0.lperm, r0.wave>();
@@ -673,6 +673,22 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
                     v[i].x *= sc;
                     v[i].y *= sc;
                 }
+            }
+        } else if constexpr (SPT == 1 && HERM) {
+            // one shift per tile, k = insert0(e, hb), hb the top set bit of x:
+            // insert0 maps disjoint bits to disjoint bits, so k = kb + kr with
+            // kb = insert0(base, hb) and kr = insert0(r, hb), and k ^ x splits
+            // the same way over R = insert0(REG, hb): the per-element parts
+            // stay uniform
+            const uint32_t x = (uint32_t)x0;
+            const uint32_t hb = 31u - __clz(x);
+            const uint32_t R = insert0(r0.reg, hb);
+            const uint32_t kb = insert0(thread_base<r0.lperm, r0.wave>(), hb);
+            const uint32_t vb = kb ^ (x & ~R), xr = x & R;
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                const uint32_t kr = insert0(pdep((uint32_t)i, r0.reg), hb);
+                v[i] = cmul_conj_a(load_at<C>(rs, vb, kr ^ xr), load_at<C>(rs, kb, kr));
             }
         } else {
             const uint32_t base = thread_base<r0.lperm, r0.wave>();

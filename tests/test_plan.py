@@ -452,6 +452,37 @@ def reduce4(v, herm):
     return np.sum(np.abs(v) ** 4)
 
 
+def test_gather_address_decomposition(probe):
+    """The gathers of f_x split each index into a per-thread and a uniform
+    per-register-element part: with e = base | r (disjoint bits, r inside the
+    first round's register mask REG), e ^ x = (base ^ (x & ~REG)) +
+    (r ^ (x & REG)); in the Hermitian one-shift tiles k = insert0(e, hb) =
+    insert0(base, hb) + insert0(r, hb) and k ^ x splits the same way over
+    R = insert0(REG, hb).  Checked on every first round of the fused and
+    pass-1 plans, for random shifts."""
+    rng = np.random.default_rng(7)
+    for prec, kind, par, args in all_plans(probe):
+        if kind == "pass2":
+            continue
+        tb, rb, sb, lo, hi, split = args
+        rd = plan(probe, *args, kind=kind)[0]
+        reg = rd[0] & ((1 << tb) - 1)
+        M = mapping(rd, tb, rb)
+        base = M[:, :1]
+        r = pdep(np.arange(1 << rb, dtype=np.int64), reg)[None, :]
+        assert np.all((base & r) == 0) and np.all((base | r) == M)
+        for x in rng.integers(1, 1 << (tb + 1), size=12):
+            x = int(x)
+            xl = x & ((1 << tb) - 1)
+            assert np.array_equal(M ^ xl, (base ^ (xl & ~reg)) + (r ^ (xl & reg)))
+            hb = x.bit_length() - 1  # Hermitian tiles: shifts of tb + 1 bits
+            R = insert0(reg, hb)
+            kb, kr = insert0(base, hb), insert0(r, hb)
+            k = insert0(M, hb)
+            assert np.array_equal(k, kb + kr)
+            assert np.array_equal(k ^ x, (kb ^ (x & ~R)) + (kr ^ (x & R)))
+
+
 def emulate_fused_partials(probe, psi, prec, herm=False, x_begin=0, split=0):
     """Per-shift sums exactly as k_fused indexes them (tile of 2^(TB-NT) shifts)."""
     N = psi.size.bit_length() - 1
