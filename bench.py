@@ -13,7 +13,9 @@ already resident in device memory.  Pauli strings per step = 4^N.
 Printed (one JSON line on stdout): throughput of the headline form (plain
 FP32 XOR-FWHT) with |dM2| against the stored FP64 oracle value, ms per step,
 the dominant kernel's roofline position (timed live with HIP events around
-every launch in the timed region), the other forms measured the same way,
+every launch in the timed region; for pass 1 also against the rate a
+store-only kernel with its row layout reaches on the same GPU), the other
+forms measured the same way,
 and one leg per benchmark configuration:
   * N = 10 complex128 states (Haar, |T>^10, graph state), every form, |dM2|
     against the oracle and the closed forms;
@@ -141,6 +143,25 @@ def stored_traffic(kernel: str, N: int, form: str):
                 return None
             return r["hbm_bytes_per_launch"]
     return None
+
+
+def store_ceiling():
+    """Rate of a store-only kernel with pass 1's exact row layout (32 KiB per
+    256-thread workgroup, 8-byte non-temporal stores in pass 1's lane order:
+    `probe_store` pattern A), measured now on this GPU in a child process;
+    the median of three rounds in GB/s, or None if the probe is not built or
+    fails."""
+    exe = os.path.join(ROOT, "paper_2512_24685_amd", "probe_store")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe, "A", "3"], capture_output=True, text=True, timeout=120)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    rates = [float(m) for m in re.findall(r"pattern A\s+\S+ ms per 4 GiB, ([0-9.]+) TB/s", out.stdout)]
+    if out.returncode != 0 or not rates:
+        return None
+    return round(1000.0 * sorted(rates)[len(rates) // 2], 1)
 
 
 def cpu_model() -> str:
@@ -699,6 +720,12 @@ def main():
     roof = roofline(N, args.form, dom, kt[dom][0], kt[dom][1], cs,
                     stored_traffic(kname, N, args.form), evals=args.steps)
     roof["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
+    if kname == "k_pass1" and args.form in ("fp32", "fp32h", "split16", "splitbf16"):
+        ceil = store_ceiling()
+        if ceil:
+            roof["store_ceiling"] = {"what": "store-only kernel with pass 1's row layout "
+                                             "(probe_store pattern A, this GPU, now)",
+                                     "GBs": ceil, "frac": round(roof["achieved"] / ceil, 4)}
 
     forms = {}
     all_forms = [args.form] + [x for x in args.also.split(",") if x and x != args.form]

@@ -13,12 +13,14 @@
 //   E4, E8, E16  A's order inside the workgroup, but the 32 KiB row cut into
 //      8 pieces of 4 KiB interleaved with those of the G - 1 neighbouring
 //      workgroups in dispatch order (G = 4, 8, 16).
-// Every store stays inside the buffer (the workgroup count is a multiple of
-// every G; checked on the host before the launches); the kernels have no
-// waits.
+// Arguments: [patterns [rounds]], e.g. `probe_store A 1` (default: all
+// patterns, three rounds).  Every store stays inside the buffer (the
+// workgroup count is a multiple of every G; checked on the host before the
+// launches); the kernels have no waits.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #define CHECK(x)                                                                  \
     do {                                                                          \
@@ -92,7 +94,13 @@ __global__ __launch_bounds__(256) void k_rowE(f2* out) {
     }
 }
 
-int main() {
+int main(int argc, char** argv) {
+    const char* only = argc > 1 ? argv[1] : nullptr;  // comma-separated pattern names
+    const int rounds = argc > 2 ? atoi(argv[2]) : 3;
+    if (rounds < 1 || rounds > 100) {
+        printf("rounds must be in [1, 100]\n");
+        return 1;
+    }
     void* buf = nullptr;
     CHECK(hipMalloc(&buf, kBytes));
     const unsigned wgs = (unsigned)(kBytes / (kRowValues * sizeof(f2)));
@@ -104,8 +112,19 @@ int main() {
     CHECK(hipEventCreate(&a));
     CHECK(hipEventCreate(&b));
     const char* names[] = {"A", "B", "C", "D", "E4", "E8", "E16"};
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < rounds; ++rep) {
         for (int k = 0; k < 7; ++k) {
+            if (only) {
+                bool want = false;
+                const size_t n = strlen(names[k]);
+                for (const char* p = only; *p;) {
+                    const char* q = strchr(p, ',');
+                    const size_t len = q ? (size_t)(q - p) : strlen(p);
+                    want = want || (len == n && strncmp(p, names[k], n) == 0);
+                    p = q ? q + 1 : p + len;
+                }
+                if (!want) continue;
+            }
             for (int timed = 0; timed < 2; ++timed) {  // one untimed round first
                 CHECK(hipEventRecord(a));
                 for (int it = 0; it < 5; ++it) {
