@@ -190,6 +190,22 @@ int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int fo
 int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
                   int64_t x_count, void* stream, double* partials);
 
+/* M2 from per-shift sums computed earlier: the end of Algorithm 1 (the sum
+ * over shifts and the logarithm) on S_x that the caller gathered, e.g. from
+ * sre2_partials over shift ranges that were checkpointed and resumed, or
+ * computed on several GPUs (the shifts are independent, main text).  The
+ * norm n is computed from psi as in sre2_m2, and the sum over x runs in the
+ * same fixed order, so S_x equal to those of sre2_m2 give a bitwise equal
+ * result.
+ *   psi       device, 2^N values of dtype (the state the S_x belong to)
+ *   form      the form the S_x were computed in (it fixes the precision of
+ *             the staged input and so of n)
+ *   partials  device, 2^N doubles: S_x for x = 0 .. 2^N - 1, read only
+ *   out       device, SRE2_OUT_LEN doubles: M2, S, n, status (as sre2_m2)
+ * Errors: as sre2_m2; SRE2_EINVAL for null partials or out. */
+int sre2_m2_from_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form,
+                          const double* partials, void* stream, double* out);
+
 /* M2 of `count` states, each with its own N (mixed N allowed): Algorithm 1
  * applied to every state, the states sharing launches where they can.
  *   psi_list  HOST array of `count` device pointers

@@ -67,6 +67,7 @@ def lib():
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_m2_noalloc": ([c_int, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_partials": ([vp, vp, c_int, c_int, c_int, i64, i64, vp, vp], c_int),
+        "sre2_m2_from_partials": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_moments": ([vp, vp, c_int, c_int, vp, vp], c_int),
         "sre2_sre": ([vp, vp, c_int, c_int, c_int, ctypes.c_double, vp, vp], c_int),
         "sre2_pauli_spectrum": ([vp, vp, c_int, c_int, c_int, c_int, vp, vp, vp], c_int),
@@ -350,6 +351,28 @@ def shift_partials(psi, x_begin: int = 0, x_count: int | None = None, form: str 
                              ctypes.c_void_p(out.data_ptr()))
     _check(rc, "sre2_partials")
     return out
+
+
+def m2_from_partials(psi, partials, form: str = "fp32", ctx: Context | None = None,
+                     stream=None) -> Result:
+    """M2 of `psi` from all its S_x (float64 device tensor of 2^N, e.g.
+    gathered from shift_partials over ranges): the norm, the fixed-order sum
+    and the logarithm of sre2_m2 (synchronises to read the result)."""
+    torch = _torch()
+    psi = _prep(psi)
+    N = _nqubits(psi)
+    if (not isinstance(partials, torch.Tensor) or partials.dtype != torch.float64
+            or partials.device != psi.device or partials.numel() != (1 << N)):
+        raise ValueError("partials must be a float64 tensor of 2^N values on psi's device")
+    partials = partials.contiguous()
+    ctx, sp = _ctx_stream(psi, ctx, stream)
+    out = torch.empty(OUT_LEN, dtype=torch.float64, device=psi.device)
+    rc = lib().sre2_m2_from_partials(ctx.handle, ctypes.c_void_p(psi.data_ptr()), N,
+                                     _dtype_code(psi), FORMS[form],
+                                     ctypes.c_void_p(partials.data_ptr()), ctypes.c_void_p(sp),
+                                     ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "sre2_m2_from_partials")
+    return _result(out.cpu())
 
 
 def m2_batched(psis, form: str = "fp32", ctx: Context | None = None, stream=None) -> list[Result]:

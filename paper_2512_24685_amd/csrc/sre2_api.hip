@@ -348,10 +348,11 @@ int norm_stage(sre2_ctx* tctx, const void* work, int N, int form, const Red& r, 
 // The launch sequence of one evaluation on the buffers of ws: M2
 // (spec == nullptr), or the general reduction of spec: M_alpha / M_1 in out,
 // or the Pauli-spectrum counts in spec->hist (cleared here first).  S_x goes
-// to `partials` when given, else to ws.sx.  tctx (may be null) only records
-// per-launch timing.
+// to `partials` when given, else to ws.sx; with sx_given the caller's
+// `partials` already hold every S_x and only the norm, the fixed-order sum
+// and the logarithm run.  tctx (may be null) only records per-launch timing.
 int m2_launch(sre2_ctx* tctx, const Workspace& ws, const void* psi, int N, int dtype, int form,
-              hipStream_t st, double* out, double* partials, const Spec* spec) {
+              hipStream_t st, double* out, double* partials, const Spec* spec, bool sx_given) {
     const void* work = nullptr;
     int rc = stage_input(tctx, ws, psi, N, dtype, form, st, &work);
     if (rc) return rc;
@@ -372,8 +373,10 @@ int m2_launch(sre2_ctx* tctx, const Workspace& ws, const void* psi, int N, int d
             sp.nrm = r.nrm;
         }
     }
-    rc = shift_sums(tctx, ws, work, N, form, 0, n, Sx, r.se, spec ? &sp : nullptr, st);
-    if (rc) return rc;
+    if (!sx_given) {
+        rc = shift_sums(tctx, ws, work, N, form, 0, n, Sx, r.se, spec ? &sp : nullptr, st);
+        if (rc) return rc;
+    }
     {
         Timed tm(tctx, st, SRE2_KIND_AUX);
         rc = hip_status(launch_sum(Sx, n, 1, nb, r.spart, nullptr, Pack{}, st));
@@ -413,7 +416,7 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
     int rc = ctx_common_ws(ctx, N, dtype, form, partials == nullptr, &ws);
     if (!rc) rc = ctx_two_pass_ws(ctx, N, form, 0, int64_t(1) << N, &ws);
     if (rc) return rc;
-    return m2_launch(ctx, ws, psi, N, dtype, form, st, out, partials, spec);
+    return m2_launch(ctx, ws, psi, N, dtype, form, st, out, partials, spec, false);
 }
 
 // Up to kMaxPack states of one N <= fused_max(form) in packed launches: the
@@ -481,7 +484,7 @@ int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, 
 namespace sre2 {
 int ws_m2(const Workspace& ws, const void* psi, int N, int dtype, int form, hipStream_t st,
           double* out, double* partials) {
-    return m2_launch(nullptr, ws, psi, N, dtype, form, st, out, partials, nullptr);
+    return m2_launch(nullptr, ws, psi, N, dtype, form, st, out, partials, nullptr, false);
 }
 int ws_layout(int N, int dtype, int form, bool need_sx, size_t bytes, size_t* psi_work_off,
               size_t* sx_off, size_t* part_off, size_t* slab_off, size_t* limit) {
@@ -696,6 +699,20 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
         if (rc) return rc;
     }
     return shift_sums(ctx, ws, work, N, form, x_begin, x_count, partials, r.se, nullptr, st);
+}
+
+int sre2_m2_from_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form,
+                          const double* partials, void* stream, double* out) {
+    int rc = validate(ctx, psi, N, dtype, form);
+    if (rc) return rc;
+    if (!partials || !out) return SRE2_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return SRE2_EHIP;
+    Workspace ws;
+    rc = ctx_common_ws(ctx, N, dtype, form, false, &ws);
+    if (rc) return rc;
+    return m2_launch(ctx, ws, psi, N, dtype, form, (hipStream_t)stream, out,
+                     const_cast<double*>(partials), nullptr, true);
 }
 
 int sre2_m2_batched(sre2_ctx* ctx, const void* const* psi_list, const int* N_list, int count,
