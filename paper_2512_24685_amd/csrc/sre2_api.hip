@@ -40,6 +40,11 @@ struct DeviceGuard {
     }
 };
 
+// Fault injection for tests of the error paths, from the host only (no
+// kernel is made to fail): SRE2_FAULT=alloc (every workspace allocation
+// fails), alloc_4g (allocations above 4 GiB fail), launch (the transform
+// launches of an evaluation report a launch error after the staging and norm
+// kernels were enqueued).
 int fault_injected(const char* what) {
     const char* f = getenv("SRE2_FAULT");
     return f && strcmp(f, what) == 0;
@@ -294,6 +299,7 @@ int ctx_two_pass_ws(sre2_ctx* ctx, int N, int form, int64_t x0, int64_t xc, Work
 int shift_sums(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int form,
                int64_t x0, int64_t xc, double* Sx, const int* se, const Spec* spec,
                hipStream_t st) {
+    if (fault_injected("launch")) return SRE2_EHIP;
     const bool f64 = is_f64(form);
     const int sp = split_kind(form);
     const int64_t x1 = x0 + xc;

@@ -204,6 +204,25 @@ def test_scratch_fallback_when_allocation_fails(monkeypatch):
     assert launches == (1 << 18) // 2048  # 4 GiB chunks of 2048 shifts
 
 
+@pytest.mark.parametrize("N", [12, 16])
+def test_launch_failure_leaves_the_context_usable(monkeypatch, N):
+    """A transform launch that reports an error (forced from the host, after
+    the staging and norm kernels were enqueued; no kernel fails) fails the
+    call with SRE2_EHIP, and the next call on the same context is exact."""
+    psi = dev(W.haar(N, 7, np.complex64))
+    case_id("launch-fault", N)
+    ref = sre2.m2(psi)
+    ctx = sre2.Context(0)
+    monkeypatch.setenv("SRE2_FAULT", "launch")
+    with pytest.raises(sre2.SRE2Error) as err:
+        sre2.m2(psi, ctx=ctx)
+    assert err.value.code == sre2.EHIP
+    monkeypatch.delenv("SRE2_FAULT")
+    b = sre2.m2(psi, ctx=ctx)
+    ctx.close()
+    assert b.status == 0 and b.m2 == ref.m2 and b.S == ref.S
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         return {}
