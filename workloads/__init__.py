@@ -6,6 +6,8 @@ workloads use.  Both the CPU oracle and the GPU path consume its output;
 neither is imported from here.
 """
 from .states import (  # noqa: F401
+    CONFIGS,
+    CONFIG_FILE,
     BASE_SEED,
     SEED_N10,
     SEED_N16_BATCH,

@@ -14,14 +14,30 @@ Conventions
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 
-BASE_SEED = 2512_24685
-SEED_N10 = BASE_SEED + 1        # small single states, N = 10 (complex128)
-SEED_N16_BATCH = BASE_SEED + 2  # batch of 40 states, N = 16
-SEED_N20 = BASE_SEED + 3        # single state, N = 20 (the throughput workload)
-SEED_SERVING = BASE_SEED + 4    # serving request stream, N = 8..18
-SEED_LARGE = BASE_SEED + 5      # N = 22 / 24 states and the N = 20 Ising snapshots
+# The benchmark configurations (seeds, sizes) live in configs.json.
+CONFIG_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs.json")
+with open(CONFIG_FILE) as _f:
+    CONFIGS = json.load(_f)
+
+
+def _seed(name: str) -> int:
+    for c in CONFIGS["configs"]:
+        if c["name"] == name:
+            return CONFIGS["base_seed"] + c["seed_offset"]
+    raise KeyError(name)
+
+
+BASE_SEED = CONFIGS["base_seed"]
+SEED_N10 = _seed("n10_small")        # small single states, N = 10 (complex128)
+SEED_N16_BATCH = _seed("n16_batch")  # batch of 40 states, N = 16
+SEED_N20 = _seed("n20_single")       # single state, N = 20 (the throughput workload)
+SEED_SERVING = _seed("serving")      # serving request stream, N = 8..18
+SEED_LARGE = _seed("n22_n24_large")  # N = 22 / 24 states and the N = 20 Ising snapshots
 
 
 def _indices(N: int) -> np.ndarray:
