@@ -753,13 +753,23 @@ def main():
         configs["n16_batch"] = n16_leg(sre2, torch, W,
                                        ["fp32", "fp32h", "split16", "splitbf16", "fp64"])
         configs["n20_snapshots"] = n20_snapshot_leg(sre2, torch, W)
+        # configuration ids and seeds (workloads/configs.json) of the legs
+        for leg, name in (("n10", "n10_small"), ("n16_batch", "n16_batch"),
+                          ("n20_graph_t_m10", "n20_single"), ("n20_snapshots", "n22_n24_large")):
+            if isinstance(configs.get(leg), dict):
+                c = next(c for c in W.CONFIGS["configs"] if c["name"] == name)
+                configs[leg]["config_id"] = c["id"]
+                configs[leg]["seed"] = W.CONFIGS["base_seed"] + c["seed_offset"]
         n10_inputs = [(name, p) for name, p, _ in W.workload_inputs("n10_small")]
         n16_sample = [(f"haar16_{i}", W.haar(16, W.SEED_N16_BATCH * 1000 + i, np.complex64))
                       for i in (0, 1)]
     large = large_n_benchmark(sre2, torch, W) if args.large else None
+    if large is not None:
+        large.update(config_id=5, seed=W.SEED_LARGE)
     serving = None
     if args.serving or args.serving_07:
         serving = serving_legs(sre2, torch, W, args.serving, args.serving_07, args.serving_form)
+        serving.update(config_id=4, seed=W.SEED_SERVING)
     dynamics = None
     if args.dynamics:
         dynamics = dynamics_benchmark(sre2, torch, W, args.dynamics_N, args.dynamics, "fp32")
@@ -796,6 +806,7 @@ def main():
                                + ("two-pass row/column transform through an HBM slab"
                                   if dom != "shift" else
                                   "whole transforms in one workgroup's LDS (fused kernel)"),
+                   "config_id": 3, "seed": W.SEED_N20,
                    "N": N, "pauli_strings_per_step": 4 ** N, "form": args.form,
                    "shifts_per_chunk": cs, "column_groups": P, "M2": m2,
                    "abs_dM2_vs_oracle": abs(m2 - ref20) if ref20 is not None else None,
