@@ -463,6 +463,7 @@ int m2_pack(sre2_ctx* ctx, const void* const* psi, int count, int N, int dtype, 
         if (launch_norm(nullptr, wd, n, nb, nullptr, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
         if (sp && launch_split_scale(nullptr, nb, nullptr, pk, st) != hipSuccess) return SRE2_EHIP;
     }
+    if (fault_injected("launch")) return SRE2_EHIP;
     {
         Timed tm(ctx, st, SRE2_KIND_SHIFT);
         const int64_t plain_end = herm ? 1 : n;

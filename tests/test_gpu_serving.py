@@ -130,6 +130,26 @@ def test_server_backpressure_cancel_and_bad_inputs():
     srv.close()
 
 
+def test_server_launch_failure_fails_requests_without_hanging(monkeypatch):
+    """Transform launches that report an error (forced from the host; no
+    kernel fails): every request of the small and the large lane still
+    completes, as failed, and drain and destroy report the HIP error."""
+    print("CASE server-launch-fault", flush=True)
+    srv = sre2.Server(form="fp32", hbm_budget=64 << 20, max_slots=16)
+    monkeypatch.setenv("SRE2_FAULT", "launch")
+    states = [W.haar(N, 950 + N, np.complex64) for N in (8, 12, 16, 17)]
+    tickets = [srv.submit(p) for p in states]
+    res = wait_all(srv, tickets)
+    assert all(res[t][0] == sre2.REQ_FAILED for t in tickets)
+    with pytest.raises(sre2.SRE2Error) as e:
+        srv.drain(60.0)
+    assert e.value.code == sre2.EHIP
+    monkeypatch.delenv("SRE2_FAULT")
+    with pytest.raises(sre2.SRE2Error) as e:
+        srv.close()
+    assert e.value.code == sre2.EHIP
+
+
 def test_server_device_inputs_and_zero_state():
     print("CASE server-device", flush=True)
     srv = sre2.Server(form="fp32h", hbm_budget=256 << 20, max_slots=16)
