@@ -185,7 +185,10 @@ int sre2_pauli_spectrum(sre2_ctx* ctx, const void* psi, int N, int dtype, int fo
 /* Per-shift sums S_x for x in [x_begin, x_begin + x_count) only: the body of
  * Algorithm 1's loop over shifts for a sub-range of x.  The main text notes
  * that the shifts are independent of each other, so a range is the unit a
- * multi-GPU shard computes (each GPU takes a range and the totals add).  partials (device, x_count doubles) receives S_x in order.
+ * multi-GPU shard computes (each GPU takes a range and the totals add), and
+ * the unit a checkpointed evaluation stores (sre2_m2_from_partials finishes
+ * it).
+ *   partials  device, x_count doubles: S_x in order of x
  * Errors: as sre2_m2, plus SRE2_EINVAL for a range outside [0, 2^N). */
 int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, int64_t x_begin,
                   int64_t x_count, void* stream, double* partials);
