@@ -50,7 +50,7 @@ def _write_meta(meta_path: str, meta: dict) -> None:
 
 def m2_checkpointed(psi, path: str, form: str = "fp32", segment: int | None = None,
                     ctx=None, stop_after: int | None = None, remove: bool = False,
-                    partials_fn=None, finish_fn=None):
+                    partials_fn=None, finish_fn=None, progress=None):
     """M2 of `psi` (complex64/complex128 device tensor of 2^N values) with
     its S_x checkpointed under `path` after every `segment` shifts.
 
@@ -60,7 +60,8 @@ def m2_checkpointed(psi, path: str, form: str = "fp32", segment: int | None = No
     files after a finished evaluation.  `partials_fn(x_begin, x_count)` (host
     float64 array of S_x) and `finish_fn(sx)` (Result from all S_x as a host
     array) replace the library calls; by default they are `shift_partials`
-    and `m2_from_partials` on psi's device.
+    and `m2_from_partials` on psi's device.  `progress(done, total)` is called
+    after every stored range.
     """
     n_values = psi.size if isinstance(psi, np.ndarray) else psi.numel()
     N = int(n_values).bit_length() - 1
@@ -123,6 +124,8 @@ def m2_checkpointed(psi, path: str, form: str = "fp32", segment: int | None = No
         meta["done"] = x
         _write_meta(meta_path, meta)
         ranges += 1
+        if progress is not None:
+            progress(x, d)
 
     res = finish_fn(np.array(sx))
     del sx

@@ -52,8 +52,11 @@ def test_stop_and_resume_gives_the_same_result(tmp_path, oracle_mod, psi):
     with open(checkpoint_files(path)[1]) as f:
         assert json.load(f)["done"] == 96
     calls.clear()
-    m = m2_checkpointed(psi, path, segment=32, partials_fn=pf, finish_fn=ff)
+    seen = []
+    m = m2_checkpointed(psi, path, segment=32, partials_fn=pf, finish_fn=ff,
+                        progress=lambda done, total: seen.append((done, total)))
     assert calls[0] == (96, 32)  # resumed at the first range not stored
+    assert seen == [(128, 256), (160, 256), (192, 256), (224, 256), (256, 256)]
     ref = m2_checkpointed(psi, str(tmp_path / "ref"), segment=256, partials_fn=pf,
                           finish_fn=ff)
     assert m == ref
