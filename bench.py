@@ -75,42 +75,72 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def alg_units(N: int, form: str, kind: str, cs: int):
-    """Algorithmic bytes and VALU ops per launch of one kernel class.
-
-    Two-pass slab: every complex value of a shift's (half-)slab is written once
-    by pass 1 and read once by pass 2: 8 B (FP32) / 16 B (FP64) per value,
-    2^N values per shift (2^(N-1) in the Hermitian-pair forms).
-    VALU ops per slab value: pass 1 = 4 (conj product) + 2 per butterfly stage
-    over the L row bits; pass 2 = 2 per stage over the remaining bits + 5
-    (|W|^2, square in FP64, FP64 add); Hermitian pass 2: + 1 (two squares).
-    """
+def slab_ranges(N: int, form: str, x0: int, xc: int):
+    """The two-pass ranges of the shifts [x0, x0 + xc) as the library runs
+    them: (slab values per shift, pass-1 row bits, transformed values per
+    shift in pass 2, shifts).  Shifts below 2^L take the full slab of 2^N
+    values; above, the Hermitian-pair forms and (row pairs, on by default)
+    the plain FP32 / FP64 forms take half slabs of 2^(N-1) values; the row
+    pairs still transform 2^N values per shift in pass 2."""
     import paper_2512_24685_amd as sre2
 
-    base = "fp64" if form.startswith("fp64") else "fp32"
     herm = form.endswith("h")
-    ns = N - (1 if herm else 0)
-    vals = cs * (1 << ns)
-    eb = 8 if base == "fp32" else 16
-    L = sre2.row_bits(N, form)
-    if kind == "pass1":
-        return eb * vals, (4 + 2 * L) * vals
-    if kind == "pass2":
-        return eb * vals, (2 * (ns - L) + (6 if herm else 5)) * vals
-    raise ValueError(kind)
+    half = herm or (ROW_PAIRS and form in ("fp32", "fp64"))
+    Lf = sre2.row_bits(N, "fp64" if form.startswith("fp64") else "fp32")
+    if not half:
+        return [(1 << N, Lf, 1 << N, xc)]
+    Lh = sre2.row_bits(N, form)
+    lo = max(0, min(x0 + xc, 1 << Lh) - x0)
+    out = [(1 << N, Lf, 1 << N, lo)] if lo else []
+    if xc > lo:
+        out.append((1 << (N - 1), Lh, 1 << (N - 1) if herm else 1 << N, xc - lo))
+    return out
 
 
-def roofline(N, form, kind, ms, launches, cs, traffic, evals=1):
+def alg_totals(N: int, form: str, kind: str, x0: int, xc: int):
+    """Algorithmic bytes and VALU ops of one kernel class over the shifts
+    [x0, x0 + xc).
+
+    Bytes: every slab value is written once by pass 1 and read once by
+    pass 2: 8 B (FP32) / 16 B (FP64) per value (slab_ranges).
+    VALU ops per value: pass 1 = 4 (conj product) + 2 per butterfly stage
+    over the L row bits, per slab value; pass 2 = 2 per stage over the
+    remaining bits + 5 (|W|^2, square in FP64, FP64 add), per transformed
+    value; Hermitian pass 2: + 1 (two squares).
+    """
+    eb = 16 if form.startswith("fp64") else 8
+    herm = form.endswith("h")
+    by = ops = 0
+    for vals, L, tvals, n in slab_ranges(N, form, x0, xc):
+        by += eb * vals * n
+        if kind == "pass1":
+            ops += (4 + 2 * L) * vals * n
+        elif kind == "pass2":
+            nt = tvals.bit_length() - 1
+            ops += (2 * (nt - L) + (6 if herm and vals < 1 << N else 5)) * tvals * n
+        else:
+            raise ValueError(kind)
+    return by, ops
+
+
+def roofline(N, form, kind, ms, launches, traffic, evals=1, x0=0, xc=None):
+    """Roofline entry of one kernel class from its summed time `ms` over
+    `launches` launches covering `evals` times the shifts [x0, x0 + xc)
+    (default: whole evaluations).  achieved = algorithmic bytes per launch /
+    mean launch time (= total bytes / total time: the launches of an
+    evaluation differ in size, a full-slab chunk first, then half slabs)."""
     avg_s = ms / 1e3 / launches
     if kind in ("pass1", "pass2"):
-        by, ops = alg_units(N, form, kind, cs)
-        gbs = by / avg_s / 1e9
-        alu = ops / avg_s
+        by, ops = alg_totals(N, form, kind, x0, (1 << N) if xc is None else xc)
+        by, ops = by * evals, ops * evals
+        tot_s = ms / 1e3
+        gbs = by / tot_s / 1e9
+        alu = ops / tot_s
         ent = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                "kernel": "k_pass1" if kind == "pass1" else "k_pass2",
                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-               "alg_bytes_per_launch": by, "alu_tops": round(alu / 1e12, 3),
+               "alg_bytes_per_launch": round(by / launches), "alu_tops": round(alu / 1e12, 3),
                "alu_frac": round(alu / VALU_PEAK_OPS, 4)}
         return ent
     # fused kernel: every value stays on chip; VALU-bound.  The Hermitian
@@ -255,6 +285,7 @@ def stored_m2(g, name, psi):
 
 
 SCRATCH_LIMIT = 0  # bytes; 0 keeps the library default
+ROW_PAIRS = True  # row-pair half slabs of the plain forms (library default)
 LAST_STEPS = None  # per-step ms (min, median, max) of the last measure()
 
 
@@ -262,6 +293,8 @@ def new_context(sre2):
     ctx = sre2.Context(0)
     if SCRATCH_LIMIT:
         ctx.set_scratch_limit(SCRATCH_LIMIT)
+    if not ROW_PAIRS:
+        ctx.set_row_pairs(False)
     return ctx
 
 
@@ -459,7 +492,7 @@ def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"),
         for form in forms:
             ctx = new_context(sre2)
             cs, P = ctx.chunking(N, form)
-            chunks = max(1, work // (cs << N))
+            chunks = max(1, work // (cs * slab_ranges(N, form, 1 << (N - 1), 1)[0][0]))
             span = chunks * cs
             # the chunk-aligned range of `span` shifts holding the most stored shifts
             starts = sorted({(x // cs) * cs for x in ref if x >= 2 * cs})
@@ -484,7 +517,7 @@ def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"),
             if errs and max(errs) > 1e-4:
                 raise RuntimeError(f"N={N} {form}: partials off the stored oracle values "
                                    f"(max rel {max(errs):.3g})")
-            by, _ = alg_units(N, form, "pass1", cs)
+            by, _ = alg_totals(N, form, "pass1", x0, span)
             r = {"shifts_per_chunk": cs, "chunks_timed": chunks, "x_begin": x0,
                  "row_bits": sre2.row_bits(N, form),
                  "s_per_evaluation": dt / span * (1 << N),
@@ -492,7 +525,7 @@ def large_n_benchmark(sre2, torch, W, Ns=(22, 24), forms=("fp32", "split16"),
                  "max_rel_err_vs_oracle": max(errs) if errs else None}
             for k in ("pass1", "pass2"):
                 ms, n = kt[k]
-                gbs = by / (ms / 1e3 / n) / 1e9
+                gbs = by / (ms / 1e3) / 1e9
                 r[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_GBs": round(gbs, 1),
                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
             out[f"N{N}_{form}"] = r
@@ -664,6 +697,9 @@ def main():
     ap.add_argument("--large", type=int, default=1, help="large-slab measurement (0: skip)")
     ap.add_argument("--scratch-gib", type=float, default=0.0,
                     help="two-pass scratch limit per context in GiB (0: library default)")
+    ap.add_argument("--no-row-pairs", action="store_true",
+                    help="full slabs in the plain FP32 / FP64 forms (for comparison; results "
+                         "are bitwise the same)")
     ap.add_argument("--profile-chunks", type=int, default=0, metavar="C",
                     help="run only C two-pass chunks (the benchmark's launch shape) from "
                          "x = 2^(N-1), for counter collection")
@@ -681,8 +717,9 @@ def main():
         if not os.path.exists(exe):
             sys.exit("probe_mall is not built: run python -m paper_2512_24685_amd.build")
         sys.exit(subprocess.run([exe]).returncode)
-    global SCRATCH_LIMIT
+    global SCRATCH_LIMIT, ROW_PAIRS
     SCRATCH_LIMIT = int(args.scratch_gib * 2 ** 30)
+    ROW_PAIRS = not args.no_row_pairs
 
     import torch
 
@@ -717,7 +754,7 @@ def main():
     value = float(4 ** N) / (ms_per_step / 1e3)
     dom = max((k for k in kt if k != "aux" and kt[k][1] > 0), key=lambda k: kt[k][0])
     kname = {"pass1": "k_pass1", "pass2": "k_pass2", "shift": "k_fused"}[dom]
-    roof = roofline(N, args.form, dom, kt[dom][0], kt[dom][1], cs,
+    roof = roofline(N, args.form, dom, kt[dom][0], kt[dom][1],
                     stored_traffic(kname, N, args.form), evals=args.steps)
     roof["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
     if kname == "k_pass1" and args.form in ("fp32", "fp32h", "split16", "splitbf16"):
@@ -739,9 +776,8 @@ def main():
                     "M2": fm2,
                     "abs_dM2_vs_oracle": abs(fm2 - ref20) if ref20 is not None else None,
                     "abs_dM2_vs_headline": abs(fm2 - m2),
-                    "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1], fcs,
-                                         stored_traffic(fk, N, f),
-                                         evals=fsteps_n),
+                    "roofline": roofline(N, f, fdom, fkt[fdom][0], fkt[fdom][1],
+                                         stored_traffic(fk, N, f), evals=fsteps_n),
                     "kernels_ms_per_step": {k: round(v[0] / fsteps_n, 3)
                                             for k, v in fkt.items()}}
         log(f"[{f}] {forms[f]['ms_per_step']:.1f} ms per step")

@@ -128,6 +128,22 @@ int sre2_destroy(sre2_ctx* ctx);
  * depend on the chunk size. */
 int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes);
 
+/* Row pairs of the plain FP32 / FP64 forms (default on).  Pass 1 of the
+ * two-pass path (N >= 15 in FP32, N >= 14 in FP64) transforms the rows of a
+ * shift's 2^L x 2^(N-L) slab over their low L bits (Algorithm 1's transform
+ * split into rows and columns).  Because f_x(k XOR x) = conj f_x(k) (the
+ * summand of Eq. 3 at k and k XOR x), row r XOR (x >> L) of that slab is
+ * row r with its L-bit input XOR-permuted and conjugated; for x >= 2^L the
+ * library stores only the half of the rows whose bit j is clear (j a set bit
+ * of x >> L) and pass 2 rebuilds the other half by sign flips.  The stored
+ * values equal those of the full slab bit for bit, so every S_x, S and M2 is
+ * identical either way; the half slab halves the memory traffic and the
+ * pass-1 work of those shifts.  enable = 0 keeps the full slab (for
+ * comparison).  The general index and the spectrum (sre2_sre,
+ * sre2_pauli_spectrum) and the split forms always take the full slab.
+ * Errors: SRE2_EINVAL (ctx == NULL). */
+int sre2_set_row_pairs(sre2_ctx* ctx, int enable);
+
 /* Device workspace (bytes) a call with these arguments grows the context to,
  * with the current default scratch limit.  0 for invalid arguments. */
 size_t sre2_workspace_bytes(int N, int dtype, int form);
@@ -271,9 +287,11 @@ int sre2_set_timing(sre2_ctx* ctx, int enable);
  * Errors: SRE2_EINVAL, SRE2_EHIP. */
 int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches);
 
-/* Two-pass geometry of a full evaluation with this context's scratch limit:
- * shifts per chunk (0 when N uses the fused kernel) and column groups per
- * shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
+/* Two-pass geometry of a full evaluation with this context's scratch limit
+ * and row-pair setting: shifts per chunk of the shifts x >= 2^L (most of an
+ * evaluation; half slabs in the Hermitian-pair forms and, with row pairs, in
+ * the plain FP32 / FP64 forms; 0 when N uses the fused kernel) and column
+ * groups per shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups);
 
 /* Row bits L of pass 1 for (N, form): the slab of NS = N bits (N - 1 in the

@@ -63,6 +63,7 @@ def lib():
         "sre2_create": ([ctypes.POINTER(vp), c_int], c_int),
         "sre2_destroy": ([vp], c_int),
         "sre2_set_scratch_limit": ([vp, sz], c_int),
+        "sre2_set_row_pairs": ([vp, c_int], c_int),
         "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_m2_noalloc": ([c_int, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
@@ -144,6 +145,11 @@ class Context:
 
     def set_scratch_limit(self, nbytes: int):
         _check(lib().sre2_set_scratch_limit(self._p, int(nbytes)), "sre2_set_scratch_limit")
+
+    def set_row_pairs(self, enable: bool):
+        """Row-pair half slabs of the plain FP32 / FP64 forms (default on;
+        results are bitwise the same either way)."""
+        _check(lib().sre2_set_row_pairs(self._p, int(bool(enable))), "sre2_set_row_pairs")
 
     def set_timing(self, enable: bool):
         _check(lib().sre2_set_timing(self._p, int(bool(enable))), "sre2_set_timing")

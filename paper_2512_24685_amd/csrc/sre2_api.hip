@@ -105,23 +105,56 @@ struct Chunking {
     int P = 1;
 };
 
-Chunking chunking(int N, int form, bool herm, int64_t x_count, size_t limit) {
+// Slab bits of one shift and pass-1 row bits of a slab kind (kSlabFull,
+// kSlabHerm, kSlabPairs).
+int slab_bits(int N, int slab) { return N - (slab == kSlabFull ? 0 : 1); }
+int slab_rows(int form, int N, int slab) {
+    return row_bits(form, slab == kSlabHerm ? N - 1 : N);
+}
+
+Chunking chunking(int N, int form, int slab, int64_t x_count, size_t limit) {
     Chunking c;
     if (N <= fused_max(form)) return c;
-    const int L = row_bits(form, N - (herm ? 1 : 0));
-    const size_t slab = (size_t(1) << (N - (herm ? 1 : 0))) * (size_t)elem_bytes(work_dtype(form));
+    const int L = slab_rows(form, N, slab);
+    const size_t bytes = (size_t(1) << slab_bits(N, slab)) * (size_t)elem_bytes(work_dtype(form));
     int64_t cs = 1;
-    while ((size_t)(cs * 2) * slab <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << L))
+    while ((size_t)(cs * 2) * bytes <= limit && cs * 2 <= x_count && cs * 2 <= (int64_t(1) << L))
         cs *= 2;
     c.cs = cs;
     // Column groups per shift depend on (N, form) only - never on the chunk
     // size - so the order of the FP64 partial sums, and hence every result
-    // bit, is independent of the scratch limit.
-    const int64_t tiles = col_tiles(N, form, herm);
+    // bit, is independent of the scratch limit.  The row pairs keep the
+    // full slab's pass-2 tiles.
+    const int64_t tiles = col_tiles(N, form, slab == kSlabHerm);
     int P = 1;
     while (P < 64 && P * 2 <= tiles) P *= 2;
     c.P = P;
     return c;
+}
+
+// The shifts [x0, x0 + xc) of a two-pass evaluation split into at most two
+// ranges by slab kind: the full slab below 2^L, the half slab (Hermitian
+// pair; row pairs of the plain FP32 / FP64 M2 forms when `pairs`) above.
+struct SlabRange {
+    int slab;
+    int64_t x0, xc;
+};
+int slab_ranges(int N, int form, bool pairs, int64_t x0, int64_t xc, SlabRange* out) {
+    const int64_t x1 = x0 + xc;
+    int half = kSlabFull;
+    if (is_herm(form))
+        half = kSlabHerm;
+    else if (pairs && !is_split(form))
+        half = kSlabPairs;
+    int64_t split = x1;
+    if (half != kSlabFull) {
+        const int64_t lim = int64_t(1) << slab_rows(form, N, half);
+        split = x0 > lim ? x0 : (x1 < lim ? x1 : lim);
+    }
+    int k = 0;
+    if (split > x0) out[k++] = SlabRange{kSlabFull, x0, split - x0};
+    if (x1 > split) out[k++] = SlabRange{half, split, x1 - split};
+    return k;
 }
 
 // Reduction blocks of a state of n amplitudes / shifts: about 1024 values per
@@ -203,35 +236,43 @@ int stage_input(sre2_ctx* tctx, const Workspace& ws, const void* psi, int N, int
     return hip_status(launch_convert(psi, dtype, ws.psi_work, wd, int64_t(1) << N, st));
 }
 
-// Two-pass over [x0, x0 + xc) with one kernel family (plain or Hermitian),
-// chunks sized by ws.limit.
-int two_pass(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int form, bool herm,
+// Two-pass over [x0, x0 + xc) with one slab kind, chunks sized by ws.limit.
+int two_pass(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int form, int slab,
              int64_t x0, int64_t xc, double* Sx, const int* se, const Spec* spec,
              hipStream_t st) {
     const bool f64 = is_f64(form);
     const int split = split_kind(form);
-    const Chunking ch = chunking(N, form, herm, xc, ws.limit);
-    for (int64_t c0 = 0; c0 < xc; c0 += ch.cs) {
+    const Chunking ch = chunking(N, form, slab, xc, ws.limit);
+    // row pairs: a chunk stays inside one block of 2^L shifts (one row part
+    // x >> L per launch, so every workgroup takes the same specialisation)
+    const int64_t blk = slab == kSlabPairs ? int64_t(1) << slab_rows(form, N, slab) : 0;
+    for (int64_t c0 = 0, cs = 0; c0 < xc; c0 += cs) {
         // a short last chunk keeps the same column grouping
-        const int cs = (int)(xc - c0 < ch.cs ? xc - c0 : ch.cs);
+        cs = xc - c0 < ch.cs ? xc - c0 : ch.cs;
+        if (blk) {
+            const int64_t to_edge = blk - ((x0 + c0) & (blk - 1));
+            cs = cs < to_edge ? cs : to_edge;
+        }
         hipError_t e;
         {
             Timed tm(tctx, st, SRE2_KIND_PASS1);
-            e = f64 ? launch_pass1<double>(work, N, herm, split, x0 + c0, cs, ws.scratch, se, st)
-                    : launch_pass1<float>(work, N, herm, split, x0 + c0, cs, ws.scratch, se, st);
+            e = f64 ? launch_pass1<double>(work, N, slab, split, x0 + c0, (int)cs, ws.scratch, se,
+                                           st)
+                    : launch_pass1<float>(work, N, slab, split, x0 + c0, (int)cs, ws.scratch, se,
+                                          st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
             Timed tm(tctx, st, SRE2_KIND_PASS2);
-            e = f64 ? launch_pass2<double>(ws.scratch, N, herm, split, cs, ch.P, ws.part, se,
-                                           spec, st)
-                    : launch_pass2<float>(ws.scratch, N, herm, split, cs, ch.P, ws.part, se,
-                                          spec, st);
+            e = f64 ? launch_pass2<double>(ws.scratch, N, slab, split, x0 + c0, (int)cs, ch.P,
+                                           ws.part, se, spec, st)
+                    : launch_pass2<float>(ws.scratch, N, slab, split, x0 + c0, (int)cs, ch.P,
+                                          ws.part, se, spec, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
         {
             Timed tm(tctx, st, SRE2_KIND_AUX);
-            e = launch_group_sum(ws.part, cs, ch.P, Sx + c0, st);
+            e = launch_group_sum(ws.part, (int)cs, ch.P, Sx + c0, st);
         }
         if (e != hipSuccess) return SRE2_EHIP;
     }
@@ -239,29 +280,20 @@ int two_pass(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int f
 }
 
 // Two-pass workspace of the shifts [x0, x0 + xc) with this scratch limit:
-// *need = slab bytes and *need_part = column-group partials (doubles) for the
-// larger of the plain and Hermitian-pair chunk shapes, *split = the first
-// shift of the Hermitian-pair range (x1 for the plain forms).  Returns the
-// largest chunk (shifts).
-int64_t slab_need(int N, int form, int64_t x0, int64_t xc, size_t limit, size_t* need,
-                  size_t* need_part, int64_t* split) {
-    const int64_t x1 = x0 + xc;
-    // Hermitian-pair two-pass needs x >= 2^L of its own (N - 1)-bit slab
-    const int64_t lim = int64_t(1) << row_bits(form, N - 1);
-    *split = is_herm(form) ? (x0 > lim ? x0 : (x1 < lim ? x1 : lim)) : x1;
+// *need = slab bytes and *need_part = column-group partials (doubles) for
+// the largest chunk shape of its slab ranges.  Returns the largest chunk
+// (shifts).
+int64_t slab_need(int N, int form, bool pairs, int64_t x0, int64_t xc, size_t limit,
+                  size_t* need, size_t* need_part) {
     const int elem = elem_bytes(work_dtype(form));
     *need = 0;
     *need_part = 0;
     int64_t cs_max = 0;
-    if (*split > x0) {
-        const Chunking c = chunking(N, form, false, *split - x0, limit);
-        *need = (size_t)c.cs * (size_t(1) << N) * elem;
-        *need_part = (size_t)c.cs * c.P;
-        cs_max = c.cs;
-    }
-    if (x1 > *split) {
-        const Chunking c = chunking(N, form, true, x1 - *split, limit);
-        const size_t b = (size_t)c.cs * (size_t(1) << (N - 1)) * elem;
+    SlabRange rg[2];
+    const int nr = slab_ranges(N, form, pairs, x0, xc, rg);
+    for (int i = 0; i < nr; ++i) {
+        const Chunking c = chunking(N, form, rg[i].slab, rg[i].xc, limit);
+        const size_t b = (size_t)c.cs * (size_t(1) << slab_bits(N, rg[i].slab)) * elem;
         *need = *need > b ? *need : b;
         *need_part = *need_part > (size_t)c.cs * c.P ? *need_part : (size_t)c.cs * c.P;
         cs_max = cs_max > c.cs ? cs_max : c.cs;
@@ -273,13 +305,16 @@ int64_t slab_need(int N, int form, int64_t x0, int64_t xc, size_t limit, size_t*
 // and set ws.scratch, ws.part and ws.limit.  When the device cannot hold the
 // slab, the chunks shrink (halving the limit for this call) down to one
 // shift per chunk.  Chunking never changes a result bit.
-int ctx_two_pass_ws(sre2_ctx* ctx, int N, int form, int64_t x0, int64_t xc, Workspace* ws) {
+// `pairs`: the call may take the row-pair slabs (the context allows them
+// and the call reduces to M2).
+int ctx_two_pass_ws(sre2_ctx* ctx, int N, int form, int64_t x0, int64_t xc, bool pairs,
+                    Workspace* ws) {
+    ws->pairs = pairs && ctx->row_pairs;
     if (N <= fused_max(form)) return SRE2_OK;
     size_t limit = ctx->scratch_limit, need = 0, need_part = 0;
-    int64_t split = 0;
     int rc;
     for (;;) {
-        const int64_t cs_max = slab_need(N, form, x0, xc, limit, &need, &need_part, &split);
+        const int64_t cs_max = slab_need(N, form, ws->pairs, x0, xc, limit, &need, &need_part);
         rc = ensure(&ctx->scratch, &ctx->scratch_bytes, need);
         if (rc != SRE2_ENOMEM || cs_max <= 1) break;
         limit = need / 2;
@@ -326,18 +361,14 @@ int shift_sums(sre2_ctx* tctx, const Workspace& ws, const void* work, int N, int
         }
         return SRE2_OK;
     }
-    size_t need = 0, need_part = 0;
-    int64_t split = x1;
-    slab_need(N, form, x0, xc, ws.limit, &need, &need_part, &split);
-    int rc = SRE2_OK;
-    if (split > x0) {
-        rc = two_pass(tctx, ws, work, N, form, false, x0, split - x0, Sx, se, spec, st);
+    SlabRange rg[2];
+    const int nr = slab_ranges(N, form, ws.pairs && spec == nullptr, x0, xc, rg);
+    for (int i = 0; i < nr; ++i) {
+        const int rc = two_pass(tctx, ws, work, N, form, rg[i].slab, rg[i].x0, rg[i].xc,
+                                Sx + (rg[i].x0 - x0), se, spec, st);
         if (rc) return rc;
     }
-    if (x1 > split)
-        rc = two_pass(tctx, ws, work, N, form, true, split, x1 - split, Sx + (split - x0), se,
-                      spec, st);
-    return rc;
+    return SRE2_OK;
 }
 
 // Norm partials (and, for the split form, its scale exponent).
@@ -420,7 +451,7 @@ int m2_one(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, hipStream
            double* partials, const Spec* spec = nullptr) {
     Workspace ws;
     int rc = ctx_common_ws(ctx, N, dtype, form, partials == nullptr, &ws);
-    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, 0, int64_t(1) << N, &ws);
+    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, 0, int64_t(1) << N, spec == nullptr, &ws);
     if (rc) return rc;
     return m2_launch(ctx, ws, psi, N, dtype, form, st, out, partials, spec, false);
 }
@@ -512,9 +543,8 @@ int ws_layout(int N, int dtype, int form, bool need_sx, size_t bytes, size_t* ps
     if (N <= fused_max(form)) return SRE2_OK;
     // the largest chunks whose slab and partials fit what is left
     size_t lim = bytes - off, need = 0, need_part = 0;
-    int64_t split = 0;
     for (;;) {
-        const int64_t cs = slab_need(N, form, 0, (int64_t)n, lim, &need, &need_part, &split);
+        const int64_t cs = slab_need(N, form, true, 0, (int64_t)n, lim, &need, &need_part);
         const size_t pb = up(need_part * sizeof(double));
         if (off + pb + need <= bytes) {
             *part_off = off;
@@ -623,8 +653,7 @@ size_t sre2_workspace_bytes(int N, int dtype, int form) {
     if (work_dtype(form) != dtype) b += n * (size_t)elem_bytes(work_dtype(form));
     if (N > fused_max(form)) {
         size_t slab = 0, part = 0;
-        int64_t split = 0;
-        slab_need(N, form, 0, (int64_t)n, kDefaultScratchLimit, &slab, &part, &split);
+        slab_need(N, form, true, 0, (int64_t)n, kDefaultScratchLimit, &slab, &part);
         b += slab + part * sizeof(double);
     }
     return b;
@@ -695,7 +724,7 @@ int sre2_partials(sre2_ctx* ctx, const void* psi, int N, int dtype, int form, in
     const hipStream_t st = (hipStream_t)stream;
     Workspace ws;
     rc = ctx_common_ws(ctx, N, dtype, form, false, &ws);
-    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, x_begin, x_count, &ws);
+    if (!rc) rc = ctx_two_pass_ws(ctx, N, form, x_begin, x_count, true, &ws);
     if (rc) return rc;
     const void* work = nullptr;
     rc = stage_input(ctx, ws, psi, N, dtype, form, st, &work);
@@ -791,9 +820,19 @@ int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches) {
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups) {
     if (!ctx || !shifts_per_chunk || !groups || N < 1 || N > SRE2_MAX_N || !form_ok(form))
         return SRE2_EINVAL;
-    const Chunking ch = chunking(N, form, is_herm(form), int64_t(1) << N, ctx->scratch_limit);
+    // the chunks of the high shifts x >= 2^L, most of an evaluation
+    SlabRange rg[2];
+    const int64_t n = int64_t(1) << N;
+    const int nr = slab_ranges(N, form, ctx->row_pairs, 0, n, rg);
+    const Chunking ch = chunking(N, form, rg[nr - 1].slab, n, ctx->scratch_limit);
     *shifts_per_chunk = ch.cs;
     *groups = ch.P;
+    return SRE2_OK;
+}
+
+int sre2_set_row_pairs(sre2_ctx* ctx, int enable) {
+    if (!ctx) return SRE2_EINVAL;
+    ctx->row_pairs = enable != 0;
     return SRE2_OK;
 }
 

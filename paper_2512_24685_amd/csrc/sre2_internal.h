@@ -88,15 +88,25 @@ template <typename Real>
 hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int64_t x0,
                                int64_t xc, double* S, const int* se, const Pack& pk,
                                const Spec* sp, hipStream_t st);
+// Two-pass slab kinds: the full slab of 2^N values per shift; the Hermitian
+// pair's half slab (2^(N-1) values, rows of pass1_row_bits(N - 1) bits); the
+// row pairs of the plain FP32 / FP64 M2 forms (half the rows of the full
+// slab, rows of pass1_row_bits(N) bits; pass 2 rebuilds the other half
+// exactly, so S_x is bit for bit that of the full slab).  The half slabs
+// need x >= 2^L.
+constexpr int kSlabFull = 0;
+constexpr int kSlabHerm = 1;
+constexpr int kSlabPairs = 2;
 // Two-pass, one chunk of cs shifts starting at x0: pass 1 writes the
-// row-transformed slabs (cs * 2^(N - herm) complex values) to `scratch`;
-// pass 2 writes part[s*P + p], the p-th column-group partial of shift x0+s.
+// row-transformed slabs (cs * 2^N or cs * 2^(N-1) complex values) to
+// `scratch`; pass 2 writes part[s*P + p], the p-th column-group partial of
+// shift x0+s.
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, int split, int64_t x0, int cs,
+hipError_t launch_pass1(const void* psi, int N, int slab, int split, int64_t x0, int cs,
                         void* scratch, const int* se, hipStream_t st);
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, int split, int cs, int P,
-                        double* part, const int* se, const Spec* sp, hipStream_t st);
+hipError_t launch_pass2(const void* scratch, int N, int slab, int split, int64_t x0, int cs,
+                        int P, double* part, const int* se, const Spec* sp, hipStream_t st);
 // out[0..2] = (sum |psi|^2, sum |psi|^4, non-finite count) of the input as
 // given, in FP64; m holds 3 kMaxRed doubles of block partials.
 hipError_t launch_moments(const void* psi, int dtype, int64_t n, int nblocks, double* m,

@@ -15,9 +15,11 @@
 //              Workgroups loop over tiles; FP32 one-shift tiles keep psi[k]
 //              in registers across them.
 //  k_pass1     N > TB: row transform over the low TB bits of k, f_x built on
-//              the fly from psi, written to a scratch slab.
+//              the fly from psi, written to a scratch slab (for shifts
+//              x >= 2^TB only half its rows: Hermitian pair, row pairs).
 //  k_pass2     N > TB: column transform over the high N-TB bits, |W|^4 and a
-//              per-workgroup FP64 partial sum; nothing is written back.
+//              per-workgroup FP64 partial sum; nothing is written back.  The
+//              row-pair form rebuilds the rows pass 1 left out, exactly.
 //  k_convert / k_norm_part / k_sum_part / k_final: input staging, FP64 norm,
 //              fixed-order FP64 reductions and the logarithm.
 //  k_moment_part / k_moment_final: sum |psi|^2, sum |psi|^4 and non-finite
@@ -34,6 +36,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sre2_plan.h"
 #include "sre2_geometry.h"
 #include "sre2_internal.h"
@@ -44,11 +48,18 @@ template <typename Real> struct CT;
 template <> struct CT<float> { using T = float2; };
 template <> struct CT<double> { using T = double2; };
 
+// conj(a) * b.  The imaginary part rounds both products before the
+// difference (no fused multiply-add), so that cmul_conj_a(b, a) is exactly
+// conj(cmul_conj_a(a, b)): f_x(k ^ x) = conj f_x(k) then holds bit for bit,
+// which the row-pair slabs of the two-pass path rely on.
 template <typename C>
-__device__ __forceinline__ C cmul_conj_a(C a, C b) {  // conj(a) * b
+__device__ __forceinline__ C cmul_conj_a(C a, C b) {
     C r;
     r.x = a.x * b.x + a.y * b.y;
-    r.y = a.x * b.y - a.y * b.x;
+    {
+#pragma clang fp contract(off)
+        r.y = a.x * b.y - a.y * b.x;
+    }
     return r;
 }
 
@@ -222,6 +233,36 @@ __device__ __forceinline__ C load_at(__amdgpu_buffer_rsrc_t rs, uint32_t vidx, u
 // Insert a zero bit at position `hb` of `v`.
 __device__ __forceinline__ uint32_t insert0(uint32_t v, uint32_t hb) {
     return ((v >> hb) << (hb + 1)) | (v & ((1u << hb) - 1u));
+}
+
+// Remove bit `b` of `v` (the bits above it move down by one): the inverse
+// of insert0 on values with that bit clear.  Like insert0 it maps disjoint
+// bit sets to disjoint bit sets, so it adds over them.
+__host__ __device__ constexpr uint32_t remove_bit(uint32_t v, int b) {
+    return ((v >> (b + 1)) << b) | (v & ((1u << b) - 1u));
+}
+
+// Row bit left out of a half slab (Hermitian pair, row pairs), for the row
+// part xh = x >> L (nonzero) of a shift x: a set bit of xh, the lowest one
+// inside `pref` when there is one, else the top one.  Pass 1 then builds
+// only the slab rows with that bit clear.
+__device__ __forceinline__ int half_row_bit(uint32_t xh, uint32_t pref) {
+    const uint32_t p = xh & pref;
+    return p ? __builtin_ctz(p) : 31 - __builtin_clz(xh);
+}
+
+// Flip the sign bits of a complex value's parts by the masks mx, my (each
+// 0 or the sign bit of a float, applied to the high word of a double).
+constexpr uint32_t kSign = 0x80000000u;
+__device__ __forceinline__ float2 xor_signs(float2 v, uint32_t mx, uint32_t my) {
+    v.x = __uint_as_float(__float_as_uint(v.x) ^ mx);
+    v.y = __uint_as_float(__float_as_uint(v.y) ^ my);
+    return v;
+}
+__device__ __forceinline__ double2 xor_signs(double2 v, uint32_t mx, uint32_t my) {
+    v.x = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v.x) ^ ((uint64_t)mx << 32));
+    v.y = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v.y) ^ ((uint64_t)my << 32));
+    return v;
 }
 
 // Butterflies over the register bits of `bfly` (a subset of `reg`), one tile
@@ -745,18 +786,21 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 
 // ---------------------------------------------------------------------------
 // Two-pass, pass 1: row transform over k_lo (TB = L bits) of f_x for a chunk
-// of shifts; the slab of one shift holds 2^NS values (NS = N, or N - 1 in the
-// Hermitian-pair form, which needs x >= 2^L so that the dropped bit hb is a
-// row bit and only rows with that bit clear are built).  Grid (cs, rows):
-// block (s, r) takes shift slot s of slab row r; blocks are dispatched with
-// x fastest, so neighbouring blocks read the same psi rows.
+// of shifts; the slab of one shift holds 2^NS values.  NS = N, or with HERM
+// a half slab of NS = N - 1: only the rows whose bit j = half_row_bit(x >> L,
+// pref) is clear (x >= 2^L, so that j is a row bit), for the Hermitian pair
+// (pref = 0: j is the top set bit of x) and for the row pairs of the plain
+// forms (pref = pass 2's register row bits, L that of the full slab).  Grid
+// (cs, rows): block (s, r) takes shift slot s of slab row r; blocks are
+// dispatched with x fastest, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
 template <typename Real, int TB, int RB, bool HERM, int SPLIT>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? half_waves(TB, RB)
                                    : (SPLIT && TB <= 12 ? SRE2_P1S_WAVES : SRE2_P1_WAVES))))
 void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, int cs,
-             typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp) {
+             typename CT<Real>::T* __restrict__ scratch, const int* __restrict__ scale_exp,
+             uint32_t pref) {
     using C = typename CT<Real>::T;
     constexpr int PK = 2000 + 10000 * SPLIT;
     constexpr Plan P = plan_of<Real, TB, RB, PK>();
@@ -769,7 +813,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
     const int64_t s = blockIdx.x;      // shift slot in the chunk
     const uint64_t x = (uint64_t)(x0 + s);
     uint32_t row = srow;
-    if constexpr (HERM) row = insert0(srow, (63u - (uint32_t)__clzll(x)) - TB);
+    if constexpr (HERM) row = insert0(srow, half_row_bit((uint32_t)(x >> TB), pref));
     const uint32_t rowbase = row << TB;
     const uint32_t prow = rowbase ^ (uint32_t)(x & ~(uint64_t)((1u << TB) - 1u));  // partner row
     const uint32_t xlo = (uint32_t)(x & ((1u << TB) - 1u));
@@ -805,17 +849,97 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 }
 
 // ---------------------------------------------------------------------------
-// Two-pass, pass 2: column transform over the HT slab-row bits of one shift's
-// slab (2^NS values = 2^HT rows of 2^L).  A tile is 2^HT rows x 2^(TB-HT)
-// columns.  Block b -> shift slot b / P, column group b % P; the group loops
-// over its column tiles and writes one FP64 partial of S_x.
+// Row pairs (plain forms, shifts x >= 2^L).  With xh = x >> L and
+// xl = x mod 2^L, f_x(k ^ x) = conj f_x(k) makes slab row r ^ xh of pass 1
+// the row r transformed with its input XOR-permuted by xl and conjugated, so
+//   row(r ^ xh)[z] = (-1)^popcount(z & xl) conj(row(r)[z]).
+// That holds bit for bit: the products are exactly conjugate (cmul_conj_a),
+// and a butterfly network fed an XOR-permuted input computes the same sums
+// and differences, some of them negated (u + v = v + u, v - u = -(u - v)).
+// So pass 1 stores only the rows with bit j = half_row_bit(xh, register row
+// bits of the pass-2 tile) clear, and pass 2 rebuilds a row with bit j set
+// from its partner: conjugate and sign are sign-bit flips, and the column
+// transform then runs on exactly the values of the full slab.  A launch
+// covers shifts of one row part xh (its chunk stays inside one block of 2^L
+// shifts), so j is one value per launch and the kernel runs a tile loop
+// specialised on it: j is taken among the register row bits when xh has one,
+// so that which elements are rebuilt is fixed per register index
+// (pair_load_reg); otherwise xh has only thread row bits and whole threads
+// hold rebuilt rows (pair_load_thr).  Stored values are read twice (as
+// themselves and as a partner) inside one tile, the second time from the
+// caches.
 // ---------------------------------------------------------------------------
-template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN>
+template <typename C, int RB, uint32_t REG, int CB, int J>
+__device__ __forceinline__ void pair_load_reg(C (&v)[1 << RB], __amdgpu_buffer_rsrc_t rs, int L,
+                                              uint32_t vb0, uint32_t vb1, uint32_t xh,
+                                              uint32_t xl, uint32_t cto, uint32_t mT) {
+    constexpr uint32_t CMASK = (1u << CB) - 1u;
+    const uint32_t xhr = xh & (REG >> CB);  // xh on the register row bits
+    // conjugate: the imaginary part flips; the empty asm keeps the compiler
+    // from splitting y ^ mTy back into two XORs per element
+    uint32_t mTy = mT ^ kSign;
+    asm volatile("" : "+v"(mTy));
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        const uint32_t r = pdep((uint32_t)i, REG);
+        const uint32_t R = r >> CB, cr = r & CMASK;
+        if ((R >> J) & 1u) {  // a rebuilt row: partner row ^ xh, stored
+            const uint32_t sr = cr ? ((__builtin_popcount(cr & xl) & 1u) ? kSign : 0u) : 0u;
+            const C t = load_at<C>(rs, vb1, (remove_bit(R ^ xhr, J) << L) + cto + cr);
+            v[i] = xor_signs(t, mT ^ sr, mTy ^ sr);
+        } else {
+            v[i] = load_at<C>(rs, vb0, (remove_bit(R, J) << L) + cto + cr);
+        }
+    }
+}
+
+// Calls f(std::integral_constant<int, j>) for the register row bit j.
+template <uint32_t RROW, int JJ = 0, typename F>
+__device__ __forceinline__ void with_reg_row_bit(int j, F&& f) {
+    if constexpr (JJ < 32) {
+        if constexpr ((RROW >> JJ) & 1u) {
+            if (j == JJ) {
+                f(std::integral_constant<int, JJ>{});
+                return;
+            }
+        }
+        with_reg_row_bit<RROW, JJ + 1>(j, f);
+    }
+}
+
+// j a thread row bit (xh has no register row bit): a thread's rows are all
+// stored (fm = 0) or all rebuilt (fm = ~0); vb already points at the stored rows.
+template <typename C, int RB, uint32_t REG, int CB>
+__device__ __forceinline__ void pair_load_thr(int j, C (&v)[1 << RB], __amdgpu_buffer_rsrc_t rs,
+                                              int L, uint32_t vb, uint32_t fm, uint32_t xl,
+                                              uint32_t cto, uint32_t mT) {
+    constexpr uint32_t CMASK = (1u << CB) - 1u;
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+        const uint32_t r = pdep((uint32_t)i, REG);
+        const uint32_t R = r >> CB, cr = r & CMASK;
+        const uint32_t m = fm & (mT ^ ((__builtin_popcount(cr & xl) & 1u) ? kSign : 0u));
+        const C t = load_at<C>(rs, vb, (remove_bit(R, j) << L) + cto + cr);
+        v[i] = xor_signs(t, m, m ^ (fm & kSign));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass, pass 2: column transform over the HT slab-row bits of one shift's
+// slab (2^NS values = 2^HT rows of 2^L; with PAIR the slab holds the 2^(HT-1)
+// stored rows of the row pairs, and x0 is the chunk's first shift).  A tile
+// is 2^HT rows x 2^(TB-HT) columns.  Block b -> shift slot b / P, column
+// group b % P; the group loops over its column tiles and writes one FP64
+// partial of S_x.
+// ---------------------------------------------------------------------------
+template <typename Real, int HT, int TB, int RB, bool HERM, int SPLIT, bool GEN, bool PAIR>
 __global__ __launch_bounds__(1 << (TB - RB))
 __attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? half_waves(TB, RB)
                                    : (SPLIT ? SRE2_P2S_WAVES : SRE2_P2_WAVES))))
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
-             double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp) {
+             double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp,
+             int64_t x0) {
+    static_assert(!PAIR || (!HERM && !SPLIT && !GEN), "row pairs: plain M2 forms only");
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 3000 + HT + 10000 * SPLIT;
@@ -840,21 +964,33 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     const int L = NS - HT;  // row bits of pass 1
     const int ntile = 1 << (L - CB);  // column tiles per shift
     const int per = ntile / P;
-    const auto rs = buf_rsrc(scratch + ((uint64_t)s << NS), (uint32_t)sizeof(C) << NS);
+    const int SH = PAIR ? NS - 1 : NS;  // slab bits of one shift
+    const auto rs = buf_rsrc(scratch + ((uint64_t)s << SH), (uint32_t)sizeof(C) << SH);
     // tile element e -> slab offset (e >> CB) * 2^L + (e & CMASK), which adds
     // over disjoint bits: the thread's part once, the register element's part
     // (and the column tile's) as a uniform offset
     const uint32_t base = thread_base<r0.lperm, r0.wave>();
     const uint32_t vb = ((base >> CB) << L) + (base & CMASK);
+    // row pairs: the shift's row and column parts, the left-out row bit j,
+    // the thread's stored-row (vb0) and partner-row (vb1) address parts and
+    // the sign (-1)^popcount(z & xl) of its column bits
+    constexpr uint32_t RROW = r0.reg >> CB;
+    uint32_t xh = 0, xl = 0, vb0 = 0, vb1 = 0, sT = 0, fm = 0;
+    int j = 0;
+    if constexpr (PAIR) {
+        const uint64_t x = (uint64_t)(x0 + s);
+        xh = (uint32_t)(x >> L);
+        xl = (uint32_t)x & ((1u << L) - 1u);
+        j = half_row_bit(xh, RROW);
+        const uint32_t rowT = base >> CB, colT = base & CMASK;
+        vb0 = (remove_bit(rowT, j) << L) + colT;
+        vb1 = (remove_bit(rowT ^ (xh & ~RROW), j) << L) + colT;
+        sT = __builtin_popcount(colT & xl) & 1u;
+        fm = 0u - ((rowT >> j) & 1u);
+    }
     double acc = 0.0;
-    for (int ct = g * per; ct < (g + 1) * per; ++ct) {
-        const uint32_t cto = (uint32_t)ct << CB;
-        C v[1 << RB];
-#pragma unroll
-        for (int i = 0; i < (1 << RB); ++i) {
-            const uint32_t r = pdep((uint32_t)i, r0.reg);
-            v[i] = load_at<C, NT ? 2 : 0>(rs, vb, cto + ((r >> CB) << L) + (r & CMASK));
-        }
+    // column transform of one tile and its terms, tiles in ascending order
+    auto consume = [&](C (&v)[1 << RB]) {
         run_transform<Real, TB, RB, PK>(lds, v);
         if constexpr (GEN) {
 #pragma unroll
@@ -863,6 +999,61 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
 #pragma unroll
             for (int i = 0; i < (1 << RB); ++i) acc += HERM ? abs4h(v[i]) : abs4(v[i]);
         }
+    };
+    const int c0 = g * per, c1 = (g + 1) * per;
+    // Plain and Hermitian tiles that fit the LDS whole load the next tile
+    // while transforming this one (two register sets; these kernels are held
+    // to two waves per SIMD by their LDS tiles, which leaves the registers);
+    // barriers wait on LDS only, so the loads stay in flight across the
+    // transform.  load_tile(v, ct) fills v with column tile ct.
+    constexpr bool PREFETCH = !half_lds<Real>(TB) && !SPLIT && !GEN;
+    auto tiles = [&](auto&& load_tile) {
+        if constexpr (PREFETCH) {
+            C va[1 << RB], vn[1 << RB];
+            load_tile(va, c0);
+            for (int ct = c0; ct < c1; ct += 2) {
+                if (ct + 1 < c1) load_tile(vn, ct + 1);
+                consume(va);
+                if (ct + 1 < c1) {
+                    if (ct + 2 < c1) load_tile(va, ct + 2);
+                    consume(vn);
+                }
+            }
+        } else {
+            for (int ct = c0; ct < c1; ++ct) {
+                C v[1 << RB];
+                load_tile(v, ct);
+                consume(v);
+            }
+        }
+    };
+    if constexpr (PAIR) {
+        if ((RROW >> j) & 1u) {
+            with_reg_row_bit<RROW>(j, [&](auto J) {
+                tiles([&](C (&v)[1 << RB], int ct) {
+                    const uint32_t cto = (uint32_t)ct << CB;
+                    const uint32_t mT = ((sT ^ __builtin_popcount(cto & xl)) & 1u) ? kSign : 0u;
+                    pair_load_reg<C, RB, r0.reg, CB, decltype(J)::value>(v, rs, L, vb0, vb1, xh,
+                                                                         xl, cto, mT);
+                });
+            });
+        } else {
+            const uint32_t vbt = fm ? vb1 : vb0;
+            tiles([&](C (&v)[1 << RB], int ct) {
+                const uint32_t cto = (uint32_t)ct << CB;
+                const uint32_t mT = ((sT ^ __builtin_popcount(cto & xl)) & 1u) ? kSign : 0u;
+                pair_load_thr<C, RB, r0.reg, CB>(j, v, rs, L, vbt, fm, xl, cto, mT);
+            });
+        }
+    } else {
+        tiles([&](C (&v)[1 << RB], int ct) {
+            const uint32_t cto = (uint32_t)ct << CB;
+#pragma unroll
+            for (int i = 0; i < (1 << RB); ++i) {
+                const uint32_t r = pdep((uint32_t)i, r0.reg);
+                v[i] = load_at<C, NT ? 2 : 0>(rs, vb, cto + ((r >> CB) << L) + (r & CMASK));
+            }
+        });
     }
     if constexpr (!GEN) {
         if constexpr (HERM) acc *= 16.0;
@@ -1085,14 +1276,29 @@ hipError_t launch_fused_nt(const void* psi, int64_t x0, int64_t xc, double* S, c
     return hipGetLastError();
 }
 
-template <typename Real, int HT, bool HERM, int SPLIT, bool GEN>
+template <typename Real, int HT, bool HERM, int SPLIT, bool GEN, bool PAIR>
 hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* part, const int* se,
-                           const Spec& sp, hipStream_t st) {
+                           const Spec& sp, int64_t x0, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
-    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM, SPLIT, GEN>), dim3((unsigned)((int64_t)cs * P)),
-                       dim3(1 << (TB - RB)), 0, st, (const C*)scratch, NS, P, part, se, sp);
+    hipLaunchKernelGGL((k_pass2<Real, HT, TB, RB, HERM, SPLIT, GEN, PAIR>),
+                       dim3((unsigned)((int64_t)cs * P)), dim3(1 << (TB - RB)), 0, st,
+                       (const C*)scratch, NS, P, part, se, sp, x0);
     return hipGetLastError();
+}
+
+// Register row bits of the first round of the plain pass-2 tile of HT rows:
+// the preferred left-out row bits of the row pairs.
+template <typename Real, int HT>
+constexpr uint32_t pass2_reg_rows() {
+    constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
+    return plan_of<Real, TB, RB, 3000 + HT>().r[0].reg >> (TB - HT);
+}
+template <typename Real, int... Hs>
+uint32_t pair_pref_of(int HT, std::integer_sequence<int, Hs...>) {
+    uint32_t m = 0;
+    ((HT == Hs + 1 ? (m = pass2_reg_rows<Real, Hs + 1>(), 0) : 0), ...);
+    return m;
 }
 
 template <typename Real, bool GEN, int... Ns>
@@ -1119,14 +1325,14 @@ hipError_t dispatch_fused(int NT, const void* psi, int64_t x0, int64_t xc, doubl
     return e;
 }
 
-template <typename Real, bool HERM, int SPLIT, bool GEN, int... Hs>
+template <typename Real, bool HERM, int SPLIT, bool GEN, bool PAIR = false, int... Hs>
 hipError_t dispatch_pass2(int HT, const void* scratch, int NS, int cs, int P, double* part,
-                          const int* se, const Spec& sp, hipStream_t st,
+                          const int* se, const Spec& sp, int64_t x0, hipStream_t st,
                           std::integer_sequence<int, Hs...>) {
     hipError_t e = hipErrorInvalidValue;
     ((HT == Hs + 1
-          ? (e = launch_pass2_ht<Real, Hs + 1, HERM, SPLIT, GEN>(scratch, NS, cs, P, part, se, sp,
-                                                                 st),
+          ? (e = launch_pass2_ht<Real, Hs + 1, HERM, SPLIT, GEN, PAIR>(scratch, NS, cs, P, part,
+                                                                       se, sp, x0, st),
              0)
           : 0),
      ...);
@@ -1180,98 +1386,114 @@ hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int
 }
 
 template <typename Real, int TB>
-hipError_t launch_pass1_tb(const void* psi, int NS, bool herm, int split, int64_t x0, int cs,
-                           void* scratch, const int* se, hipStream_t st) {
+hipError_t launch_pass1_tb(const void* psi, int NS, bool half, int split, int64_t x0, int cs,
+                           void* scratch, const int* se, uint32_t pref, hipStream_t st) {
     using C = typename CT<Real>::T;
     constexpr int RB = pass1_rb<Real>(TB, false), RBS = pass1_rb<Real>(TB, true);
     const int64_t rows = (int64_t)1 << (NS - TB);
     if (cs < 1 || rows > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)cs, (unsigned)rows), block(1 << (TB - RB)), blocks(1 << (TB - RBS));
-    if (herm)
+    if (half)
         hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
-                           NS, x0, cs, (C*)scratch, se);
+                           NS, x0, cs, (C*)scratch, se, pref);
     else if (split) {
         if constexpr (sizeof(Real) == 4) {
             if (split == 1)
                 hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 1>), grid, blocks, 0, st,
-                                   (const C*)psi, NS, x0, cs, (C*)scratch, se);
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
             else
                 hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 2>), grid, blocks, 0, st,
-                                   (const C*)psi, NS, x0, cs, (C*)scratch, se);
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
         }
     } else
         hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 0>), grid, block, 0, st,
-                           (const C*)psi, NS, x0, cs, (C*)scratch, se);
+                           (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
     return hipGetLastError();
 }
 
 template <typename Real, int... Ls>
-hipError_t dispatch_pass1(int L, const void* psi, int NS, bool herm, int split, int64_t x0,
-                          int cs, void* scratch, const int* se, hipStream_t st,
+hipError_t dispatch_pass1(int L, const void* psi, int NS, bool half, int split, int64_t x0,
+                          int cs, void* scratch, const int* se, uint32_t pref, hipStream_t st,
                           std::integer_sequence<int, Ls...>) {
     hipError_t e = hipErrorInvalidValue;
     ((L == Tune<Real>::ROW + Ls
-          ? (e = launch_pass1_tb<Real, Tune<Real>::ROW + Ls>(psi, NS, herm, split, x0, cs, scratch,
-                                                             se, st),
+          ? (e = launch_pass1_tb<Real, Tune<Real>::ROW + Ls>(psi, NS, half, split, x0, cs,
+                                                             scratch, se, pref, st),
              0)
           : 0),
      ...);
     return e;
 }
 
+// Slab geometry of a two-pass slab kind: slab bits NS of one shift and
+// pass-1 row bits L (the row pairs keep the rows and columns of the full
+// slab and store half its rows).
 template <typename Real>
-hipError_t launch_pass1(const void* psi, int N, bool herm, int split, int64_t x0, int cs,
+void slab_geometry(int N, int slab, int* NS, int* L) {
+    *NS = N - (slab == kSlabFull ? 0 : 1);
+    *L = row_bits_of<Real>(slab == kSlabHerm ? N - 1 : N);
+}
+
+template <typename Real>
+hipError_t launch_pass1(const void* psi, int N, int slab, int split, int64_t x0, int cs,
                         void* scratch, const int* se, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    if (split < 0 || split > 2 || (split && (herm || sizeof(Real) != 4)))
+    if (slab < kSlabFull || slab > kSlabPairs || split < 0 || split > 2 ||
+        (split && (slab != kSlabFull || sizeof(Real) != 4)))
         return hipErrorInvalidValue;
-    const int NS = N - (herm ? 1 : 0);
-    const int L = row_bits_of<Real>(NS);
-    if (herm && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
+    int NS, L;
+    slab_geometry<Real>(N, slab, &NS, &L);
+    if (slab != kSlabFull && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
+    constexpr int HMAX = pass2_max_rows<Real>();
+    const uint32_t pref =
+        slab == kSlabPairs ? pair_pref_of<Real>(N - L, std::make_integer_sequence<int, HMAX>{}) : 0u;
     return dispatch_pass1<Real>(
-        L, psi, NS, herm, split, x0, cs, scratch, se, st,
+        L, psi, NS, slab != kSlabFull, split, x0, cs, scratch, se, pref, st,
         std::make_integer_sequence<int, Prec<Real>::MAXTB - Tune<Real>::ROW + 1>{});
 }
 
 template <typename Real>
-hipError_t launch_pass2(const void* scratch, int N, bool herm, int split, int cs, int P,
-                        double* part, const int* se, const Spec* sp, hipStream_t st) {
+hipError_t launch_pass2(const void* scratch, int N, int slab, int split, int64_t x0, int cs,
+                        int P, double* part, const int* se, const Spec* sp, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
-    if (split < 0 || split > 2 || (split && (herm || sizeof(Real) != 4)))
+    if (slab < kSlabFull || slab > kSlabPairs || split < 0 || split > 2 ||
+        (split && (slab != kSlabFull || sizeof(Real) != 4)) || (sp && slab == kSlabPairs))
         return hipErrorInvalidValue;
-    const int NS = N - (herm ? 1 : 0);
-    const int ROW = row_bits_of<Real>(NS);  // this slab's pass-1 row bits
+    int NS, L;
+    slab_geometry<Real>(N, slab, &NS, &L);
+    const bool herm = slab == kSlabHerm;
+    if (slab == kSlabPairs) NS = N;  // the kernel takes the full slab's bits
+    const int HT = NS - L;
     constexpr int HMAX = pass2_max_rows<Real>();
+    constexpr auto hs = std::make_integer_sequence<int, HMAX>{};
     if (sp) {
         if (split || sp->kind < kRedPow || sp->kind > kRedHist ||
             (sp->kind == kRedHist && (!sp->hist || !sp->nrm || sp->nbins < 2 ||
                                       sp->nbins > kMaxBins)))
             return hipErrorInvalidValue;
         if (herm)
-            return dispatch_pass2<Real, true, 0, true>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                           *sp, st,
-                                                           std::make_integer_sequence<int, HMAX>{});
-        return dispatch_pass2<Real, false, 0, true>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                        *sp, st,
-                                                        std::make_integer_sequence<int, HMAX>{});
+            return dispatch_pass2<Real, true, 0, true>(HT, scratch, NS, cs, P, part, se, *sp, x0,
+                                                       st, hs);
+        return dispatch_pass2<Real, false, 0, true>(HT, scratch, NS, cs, P, part, se, *sp, x0,
+                                                    st, hs);
     }
     const Spec none{};
     if (herm)
-        return dispatch_pass2<Real, true, 0, false>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                        none, st,
-                                                        std::make_integer_sequence<int, HMAX>{});
+        return dispatch_pass2<Real, true, 0, false>(HT, scratch, NS, cs, P, part, se, none, x0,
+                                                    st, hs);
+    if (slab == kSlabPairs)
+        return dispatch_pass2<Real, false, 0, false, true>(HT, scratch, NS, cs, P, part, se, none,
+                                                           x0, st, hs);
     if constexpr (sizeof(Real) == 4) {
         if (split == 1)
-            return dispatch_pass2<Real, false, 1, false>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                         none, st,
-                                                         std::make_integer_sequence<int, HMAX>{});
+            return dispatch_pass2<Real, false, 1, false>(HT, scratch, NS, cs, P, part, se, none,
+                                                         x0, st, hs);
         if (split == 2)
-            return dispatch_pass2<Real, false, 2, false>(NS - ROW, scratch, NS, cs, P, part, se,
-                                                         none, st,
-                                                         std::make_integer_sequence<int, HMAX>{});
+            return dispatch_pass2<Real, false, 2, false>(HT, scratch, NS, cs, P, part, se, none,
+                                                         x0, st, hs);
     }
-    return dispatch_pass2<Real, false, 0, false>(NS - ROW, scratch, NS, cs, P, part, se, none,
-                                                     st, std::make_integer_sequence<int, HMAX>{});
+    return dispatch_pass2<Real, false, 0, false>(HT, scratch, NS, cs, P, part, se, none, x0, st,
+                                                 hs);
 }
 
 template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int64_t, int64_t,
@@ -1280,13 +1502,13 @@ template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int6
 template hipError_t launch_shift_kernel<double>(const void*, int, bool, int, int64_t, int64_t,
                                                 double*, const int*, const Pack&, const Spec*,
                                                 hipStream_t);
-template hipError_t launch_pass1<float>(const void*, int, bool, int, int64_t, int, void*,
+template hipError_t launch_pass1<float>(const void*, int, int, int, int64_t, int, void*,
                                         const int*, hipStream_t);
-template hipError_t launch_pass1<double>(const void*, int, bool, int, int64_t, int, void*,
+template hipError_t launch_pass1<double>(const void*, int, int, int, int64_t, int, void*,
                                          const int*, hipStream_t);
-template hipError_t launch_pass2<float>(const void*, int, bool, int, int, int, double*,
+template hipError_t launch_pass2<float>(const void*, int, int, int, int64_t, int, int, double*,
                                         const int*, const Spec*, hipStream_t);
-template hipError_t launch_pass2<double>(const void*, int, bool, int, int, int, double*,
+template hipError_t launch_pass2<double>(const void*, int, int, int, int64_t, int, int, double*,
                                          const int*, const Spec*, hipStream_t);
 
 // s = 14 - ceil(log2 n) from the norm partials (0 when n is not positive and

@@ -29,6 +29,9 @@ int main() {
     EXPECT(sre2_create(&ctx, 0), SRE2_OK);
     EXPECT(sre2_set_scratch_limit(ctx, size_t(1) << 20), SRE2_OK);
     EXPECT(sre2_set_scratch_limit(ctx, size_t(32) << 30), SRE2_OK);
+    EXPECT(sre2_set_row_pairs(ctx, 0), SRE2_OK);
+    EXPECT(sre2_set_row_pairs(ctx, 1), SRE2_OK);
+    EXPECT(sre2_set_row_pairs(nullptr, 1), SRE2_EINVAL);
     EXPECT(sre2_set_timing(ctx, 1), SRE2_OK);
     double ms[SRE2_KIND_COUNT];
     int64_t launches[SRE2_KIND_COUNT];

@@ -15,13 +15,13 @@ hipError_t launch_shift_kernel(const void*, int, bool, int, int64_t, int64_t, do
     return hipErrorNoDevice;
 }
 template <typename Real>
-hipError_t launch_pass1(const void*, int, bool, int, int64_t, int, void*, const int*,
+hipError_t launch_pass1(const void*, int, int, int, int64_t, int, void*, const int*,
                         hipStream_t) {
     return hipErrorNoDevice;
 }
 template <typename Real>
-hipError_t launch_pass2(const void*, int, bool, int, int, int, double*, const int*, const Spec*,
-                        hipStream_t) {
+hipError_t launch_pass2(const void*, int, int, int, int64_t, int, int, double*, const int*,
+                        const Spec*, hipStream_t) {
     return hipErrorNoDevice;
 }
 template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int64_t, int64_t,
@@ -30,13 +30,13 @@ template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int6
 template hipError_t launch_shift_kernel<double>(const void*, int, bool, int, int64_t, int64_t,
                                                 double*, const int*, const Pack&, const Spec*,
                                                 hipStream_t);
-template hipError_t launch_pass1<float>(const void*, int, bool, int, int64_t, int, void*,
+template hipError_t launch_pass1<float>(const void*, int, int, int, int64_t, int, void*,
                                         const int*, hipStream_t);
-template hipError_t launch_pass1<double>(const void*, int, bool, int, int64_t, int, void*,
+template hipError_t launch_pass1<double>(const void*, int, int, int, int64_t, int, void*,
                                          const int*, hipStream_t);
-template hipError_t launch_pass2<float>(const void*, int, bool, int, int, int, double*,
+template hipError_t launch_pass2<float>(const void*, int, int, int, int64_t, int, int, double*,
                                         const int*, const Spec*, hipStream_t);
-template hipError_t launch_pass2<double>(const void*, int, bool, int, int, int, double*,
+template hipError_t launch_pass2<double>(const void*, int, int, int, int64_t, int, int, double*,
                                          const int*, const Spec*, hipStream_t);
 hipError_t launch_moments(const void*, int, int64_t, int, double*, double*, hipStream_t) {
     return hipErrorNoDevice;

@@ -171,11 +171,12 @@ def test_row_bits_query(L):
 def test_workspace_bytes_covers_default_chunks(L):
     """sre2_workspace_bytes sizes the slab with the default scratch limit of a
     fresh context: at least the slab of one default chunk (shifts per chunk
-    from sre2_chunking) for the plain and the Hermitian-pair forms."""
+    from sre2_chunking: half slabs for the Hermitian-pair forms and the row
+    pairs of the plain FP32 / FP64 forms) for every form."""
     ctx = sre2.Context(0)
     try:
-        for form, herm in (("fp32", False), ("fp32h", True), ("split16", False),
-                           ("fp64", False), ("fp64h", True)):
+        for form, herm in (("fp32", True), ("fp32h", True), ("split16", False),
+                           ("fp64", True), ("fp64h", True)):
             elem = 16 if form.startswith("fp64") else 8
             for N in (15, 18, 20, 22, 24):
                 if N > 24 and form.startswith("fp64"):
@@ -214,3 +215,24 @@ def test_noalloc_argument_validation(L):
     assert L.sre2_m2_noalloc(0, FAKE, 20, sre2.C64, f["fp64"], None, FAKE, None) == sre2.ESCRATCH
     assert L.sre2_m2_noalloc(0, FAKE, 26, sre2.C64, f["fp32h"], None, FAKE, None) == sre2.ESCRATCH
     assert L.sre2_strerror(sre2.ESCRATCH) != b"unknown status code"
+
+
+def test_row_pairs_setting_sets_the_chunk_shape():
+    """sre2_set_row_pairs: host-only; with row pairs the plain FP32 / FP64
+    forms chunk the shifts above 2^L in half slabs (twice the shifts per
+    chunk at the same scratch limit), without them in full slabs."""
+    L = sre2.lib()
+    assert L.sre2_set_row_pairs(None, 1) == sre2.EINVAL
+    ctx = sre2.Context(0)
+    try:
+        for form in ("fp32", "fp64"):
+            cs_on, P_on = ctx.chunking(22, form)
+            ctx.set_row_pairs(False)
+            cs_off, P_off = ctx.chunking(22, form)
+            ctx.set_row_pairs(True)
+            assert cs_on == 2 * cs_off and P_on == P_off
+        cs_s, _ = ctx.chunking(22, "split16")
+        ctx.set_row_pairs(False)
+        assert ctx.chunking(22, "split16")[0] == cs_s  # split forms: full slabs always
+    finally:
+        ctx.close()

@@ -26,7 +26,9 @@ def test_stored_counters_match_the_kernel_code():
     sha = bench.kernel_source_sha()
     assert rec["entries"] and all(e["source_sha"] == sha for e in rec["entries"])
     t = bench.stored_traffic("k_pass1", 20, "fp32")
-    assert t is not None and abs(t / 2 ** 35 - 1) < 0.05  # the 32 GiB slab of a chunk
+    assert t is not None and abs(t / 2 ** 34 - 1) < 0.05  # the 16 GiB half slab of a row-pair chunk
+    t = bench.stored_traffic("k_pass1", 20, "split16")
+    assert t is not None and abs(t / 2 ** 35 - 1) < 0.05  # the 32 GiB full slab of a split chunk
 
 
 def test_more_than_one_gpu_is_refused():
@@ -35,9 +37,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
-@pytest.mark.parametrize("form,eb,ns", [("fp32", 8, 20), ("fp32h", 8, 19), ("fp64", 16, 20)])
-def test_algorithmic_bytes_per_launch(form, eb, ns):
+@pytest.mark.parametrize("form,eb,L,half", [("fp32", 8, 12, True), ("fp32h", 8, 12, True),
+                                             ("fp64", 16, 11, True), ("fp64h", 16, 11, True),
+                                             ("split16", 8, 12, False)])
+def test_algorithmic_bytes_per_evaluation(form, eb, L, half):
+    """Slab bytes of a whole N = 20 evaluation: shifts below 2^L take the
+    full slab of 2^20 values, the others (Hermitian pair, row pairs) half
+    slabs; the split forms take full slabs throughout."""
     pytest.importorskip("torch")
-    by, ops = bench.alg_units(20, form, "pass1", 4096)
-    assert by == eb * 4096 * (1 << ns)
+    by, ops = bench.alg_totals(20, form, "pass1", 0, 1 << 20)
+    vals = (1 << L) * (1 << 20) + ((1 << 20) - (1 << L)) * (1 << 19) if half else 1 << 40
+    assert by == eb * vals
     assert ops > 0
+    # a range inside the half-slab shifts: 2^(N-1) values per shift
+    by, _ = bench.alg_totals(20, form, "pass1", 1 << 19, 4096)
+    assert by == eb * 4096 * (1 << (19 if half else 20))

@@ -201,7 +201,52 @@ def test_scratch_fallback_when_allocation_fails(monkeypatch):
     launches = ctx.timing_read()["pass1"][1]
     ctx.close()
     assert a.m2 == b.m2 and a.S == b.S
-    assert launches == (1 << 18) // 2048  # 4 GiB chunks of 2048 shifts
+    # 4 GiB chunks: 2048 full slabs of 2 MiB below 2^12, then row-pair half
+    # slabs of 1 MiB, 4096 shifts per chunk (at most 2^12)
+    assert launches == 4096 // 2048 + ((1 << 18) - 4096) // 4096
+
+
+@pytest.mark.parametrize("form,N", [("fp32", 15), ("fp32", 17), ("fp32", 20), ("fp64", 14),
+                                    ("fp64", 16), ("fp64", 19)])
+def test_row_pairs_bitwise_equal_full_slab(form, N):
+    """The row-pair half slabs (default) against the full slab (row pairs
+    off): every S_x, S and M2 bit for bit, over whole evaluations that span
+    the full-slab shifts below 2^L and the half-slab shifts above."""
+    c128 = is64(form)
+    psi = dev(W.haar(N, 300 + N, np.complex128 if c128 else np.complex64))
+    case_id("row-pairs", form, N)
+    on, off = sre2.Context(0), sre2.Context(0)
+    off.set_row_pairs(False)
+    try:
+        a = sre2.shift_partials(psi, form=form, ctx=on).cpu().numpy()
+        b = sre2.shift_partials(psi, form=form, ctx=off).cpu().numpy()
+        assert np.array_equal(a, b)
+        ra, rb = sre2.m2(psi, form=form, ctx=on), sre2.m2(psi, form=form, ctx=off)
+        assert ra.m2 == rb.m2 and ra.S == rb.S
+    finally:
+        on.close()
+        off.close()
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("N", [22, 24])
+def test_row_pairs_bitwise_large_chunk(form, N):
+    """N = 22 / 24: one whole default row-pair chunk (the 2^14-value
+    half-LDS rows at N = 24 in FP32) against the full slab, bit for bit."""
+    c128 = is64(form)
+    psi = dev(W.haar(N, 400 + N, np.complex128 if c128 else np.complex64))
+    on, off = sre2.Context(0), sre2.Context(0)
+    off.set_row_pairs(False)
+    try:
+        cs, _ = on.chunking(N, form)
+        x0 = 3 << (N - 2)
+        case_id("row-pairs-large", form, N, cs)
+        a = sre2.shift_partials(psi, x0, cs, form=form, ctx=on).cpu().numpy()
+        b = sre2.shift_partials(psi, x0, cs, form=form, ctx=off).cpu().numpy()
+        assert np.array_equal(a, b)
+    finally:
+        on.close()
+        off.close()
 
 
 @pytest.mark.parametrize("N", [12, 16])
@@ -337,7 +382,8 @@ def test_large_n_full_default_chunk(oracle_mod, N, form):
     ctx = sre2.Context(0)
     try:
         cs, _ = ctx.chunking(N, form)
-        assert cs == (1024 if N == 22 else 256) // (2 if c128 else 1) * (2 if form.endswith("h") else 1)
+        half = form.endswith("h") or form in ("fp32", "fp64")  # Hermitian pair, row pairs
+        assert cs == (1024 if N == 22 else 256) // (2 if c128 else 1) * (2 if half else 1)
         x0 = 1 << (N - 1)
         xs = x0 + np.arange(cs, dtype=np.int64)
         case_id("large-chunk-t", N, form, cs)

@@ -597,3 +597,144 @@ def test_two_pass_long_rows_match_oracle(probe, oracle_mod, prec, L, herm, split
     xs = [1 << L, (1 << N) - 1] if herm else [0, (1 << N) - 1 - 0x155, 1 << (N - 1)]
     S = emulate_two_pass_partials(probe, psi, prec, xs, herm, split, L=L)
     assert np.allclose(S, oracle_mod.partials(psi, xs), rtol=1e-11, atol=0)
+
+
+def remove_bit(v, b):
+    return ((v >> (b + 1)) << b) | (v & ((1 << b) - 1))
+
+
+def popc_np(v):
+    v = np.asarray(v, dtype=np.int64)
+    c = np.zeros_like(v)
+    while np.any(v):
+        c += v & 1
+        v = v >> 1
+    return c
+
+
+def half_row_bit(xh, pref):
+    p = xh & pref
+    return (p & -p).bit_length() - 1 if p else xh.bit_length() - 1
+
+
+def pair_sources(rd, tb, rb, cb, L, x, ct):
+    """Row-pair pass-2 loads exactly as k_pass2<PAIR> forms them, per thread
+    and register element: offset in the shift's half slab and the sign flips
+    of the real and imaginary parts (1 = flip)."""
+    reg = rd[0] & ((1 << tb) - 1)
+    M = mapping(rd, tb, rb)
+    base = M[:, :1]
+    r = pdep(np.arange(1 << rb, dtype=np.int64), reg)[None, :]
+    cmask = (1 << cb) - 1
+    rrow = reg >> cb
+    xh, xl = x >> L, x & ((1 << L) - 1)
+    j = half_row_bit(xh, rrow)
+    rowT, colT = base >> cb, base & cmask
+    vb0 = (remove_bit(rowT, j) << L) + colT
+    vb1 = (remove_bit(rowT ^ (xh & ~rrow), j) << L) + colT
+    cto = ct << cb
+    mT = (popc_np(colT & xl) ^ popc_np(np.array(cto & xl))) & 1
+    R, cr = r >> cb, r & cmask
+    sc = popc_np(cr & xl) & 1
+    if (rrow >> j) & 1:
+        flag = (R >> j) & 1
+        off = np.where(flag, vb1 + (remove_bit(R ^ (xh & rrow), j) << L) + cto + cr,
+                       vb0 + (remove_bit(R, j) << L) + cto + cr)
+        m = np.where(flag, mT ^ sc, 0)
+        return M, j, off, m, np.where(flag, m ^ 1, 0)
+    ft = (rowT >> j) & 1
+    off = np.where(ft, vb1, vb0) + (remove_bit(R, j) << L) + cto + cr
+    m = ft & (mT ^ sc)
+    return M, j, off, m, m ^ ft
+
+
+def pair_shifts(rd, tb, cb, N, L, rng):
+    """Shifts x >= 2^L of N bits: random ones, each single row bit, and row
+    parts on thread row bits only (the pair_load_thr case)."""
+    HT = N - L
+    rrow = (rd[0] & ((1 << tb) - 1)) >> cb
+    trow = ((1 << HT) - 1) & ~rrow
+    xs = [int(v) for v in rng.integers(1 << L, 1 << N, size=6)]
+    xs += [(1 << (L + b)) | int(rng.integers(0, 1 << L)) for b in range(HT)]
+    if trow:
+        xs += [((int(rng.integers(1, 1 << HT)) & trow or (trow & -trow)) << L)
+               | int(rng.integers(0, 1 << L)) for _ in range(4)]
+    return xs
+
+
+def test_row_pair_sources(probe):
+    """Every pass-2 plan (both precisions, every row count H): the row-pair
+    loads fetch, for tile element e = (row r, column c) of column tile ct, the
+    stored row remove_bit(r, j) when bit j of r is clear, else the partner
+    remove_bit(r ^ xh, j) with the real part negated iff
+    popcount(z & xl) is odd and the imaginary part iff it is even
+    (z = ct 2^cb + c): row(r ^ xh)[z] = (-1)^popcount(z & xl) conj row(r)[z]."""
+    rng = np.random.default_rng(11)
+    for prec in (0, 1):
+        fmax, _, nmax = geo(probe, prec, LIMITS)
+        for N in range(fmax + 1, nmax + 1):
+            L = geo(probe, prec, PASS1, N)[0]
+            HT = N - L
+            tb, rb, sb = geo(probe, prec, PASS2, HT)
+            cb = tb - HT
+            rd = plan(probe, tb, rb, sb, cb, tb, 0, "pass2")[0]
+            for x in pair_shifts(rd, tb, cb, N, L, rng):
+                for ct in (0, (1 << (L - cb)) - 1):
+                    M, j, off, fx, fy = pair_sources(rd, tb, rb, cb, L, x, ct)
+                    xh, xl = x >> L, x & ((1 << L) - 1)
+                    assert (xh >> j) & 1
+                    row, c = M >> cb, M & ((1 << cb) - 1)
+                    z = (ct << cb) + c
+                    part = (row >> j) & 1
+                    want = np.where(part, remove_bit(row ^ xh, j), remove_bit(row, j)) << L
+                    assert np.array_equal(off, want + z), (prec, N, x, ct)
+                    sig = popc_np(z & xl) & 1
+                    assert np.array_equal(fx, np.where(part, sig, 0)), (prec, N, x)
+                    assert np.array_equal(fy, np.where(part, sig ^ 1, 0)), (prec, N, x)
+                    assert off.min() >= 0 and off.max() < 1 << (N - 1)
+
+
+def emulate_row_pairs(probe, psi, prec, xs):
+    """Per-shift sums with row-pair slabs: pass 1 builds only the rows with
+    bit j clear, pass 2 loads through pair_sources."""
+    N = psi.size.bit_length() - 1
+    L, _, sb = geo(probe, prec, PASS1, N)
+    rb1 = p1rb(probe, prec, L)
+    HT = N - L
+    tb2, rb2, _ = geo(probe, prec, PASS2, HT)
+    cb = tb2 - HT
+    p1 = plan(probe, L, rb1, sb, 0, L, 0, "pass1")
+    p2 = plan(probe, tb2, rb2, sb, cb, tb2, 0, "pass2")
+    rrow = (p2[0][0] & ((1 << tb2) - 1)) >> cb
+    e1 = np.arange(1 << L)
+    out = []
+    for x in xs:
+        assert x >= 1 << L
+        j = half_row_bit(x >> L, rrow)
+        rows = insert0(np.arange(1 << (HT - 1)), j)
+        rowbase = (rows << L)[:, None]
+        prow = rowbase ^ (x & ~((1 << L) - 1))
+        X = np.conj(psi[prow + (e1 ^ (x & ((1 << L) - 1)))[None, :]]) * psi[rowbase + e1[None, :]]
+        half = run_tile(X, p1, L, rb1, sb).reshape(-1)
+        acc = 0.0
+        for ct in range(1 << (L - cb)):
+            M, _, off, fx, fy = pair_sources(p2[0], tb2, rb2, cb, L, x, ct)
+            v = half[off]
+            v = np.where(fx, -1.0, 1.0) * v.real + 1j * np.where(fy, -1.0, 1.0) * v.imag
+            tile = np.zeros(1 << tb2, dtype=np.complex128)
+            tile[M] = v
+            acc += reduce4(run_tile(tile, p2, tb2, rb2, sb), False)
+        out.append(acc)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec,extra", [(0, 1), (0, 3), (1, 1), (1, 3)])
+def test_row_pairs_match_oracle(probe, oracle_mod, prec, extra):
+    fmax, L, _ = geo(probe, prec, LIMITS)
+    N = fmax + extra
+    psi = W.haar(N, 17)
+    L = geo(probe, prec, PASS1, N)[0]
+    xs = [1 << L, (1 << N) - 1, 0x2A5A % (1 << N) | (1 << L), 1 << (N - 1), 3 << (N - 2),
+          (1 << L) | 5]
+    S = emulate_row_pairs(probe, psi, prec, xs)
+    assert np.allclose(S, oracle_mod.partials(psi, xs), rtol=1e-11, atol=0)
