@@ -142,6 +142,13 @@ def roofline(N, form, kind, ms, launches, traffic, evals=1, x0=0, xc=None):
                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                "alg_bytes_per_launch": round(by / launches), "alu_tops": round(alu / 1e12, 3),
                "alu_frac": round(alu / VALU_PEAK_OPS, 4)}
+        if alu / VALU_PEAK_OPS > gbs / HBM_PEAK_GBS:
+            # closer to its arithmetic roof than to HBM (the row-pair pass 2):
+            # report it against the VALU issue rate, HBM figures beside
+            ent.update(bound="alu", achieved=round(alu / 1e12, 3),
+                       peak=round(VALU_PEAK_OPS / 1e12, 2), unit="Tops/s",
+                       frac=round(alu / VALU_PEAK_OPS, 4), alg_ops_per_launch=round(ops / launches),
+                       hbm_GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
         return ent
     # fused kernel: every value stays on chip; VALU-bound.  The Hermitian
     # forms run x = 0 as a separate short plain launch, so the work and the
@@ -757,12 +764,27 @@ def main():
     roof = roofline(N, args.form, dom, kt[dom][0], kt[dom][1],
                     stored_traffic(kname, N, args.form), evals=args.steps)
     roof["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
-    if kname == "k_pass1" and args.form in ("fp32", "fp32h", "split16", "splitbf16"):
+    if args.form in ("fp32", "fp64"):
+        # the whole evaluation in algorithmic VALU operations of the plain
+        # transform: (2N + 7) per Pauli string (4 for the conjugate product,
+        # 2 per butterfly stage, 3 for |W|^2 and its square; the FP64
+        # accumulation not counted) against the non-packed issue rate
+        roof["evaluation_alu_frac"] = round((2 * N + 7) * 4.0 ** N / (ms_per_step / 1e3)
+                                            / VALU_PEAK_OPS, 4)
+    if dom == "pass2" and kt["pass1"][1] > 0:
+        # the other pass beside the dominant one
+        p1 = roofline(N, args.form, "pass1", kt["pass1"][0], kt["pass1"][1],
+                      stored_traffic("k_pass1", N, args.form), evals=args.steps)
+        roof["pass1"] = {k: p1[k] for k in ("bound", "achieved", "unit", "frac", "avg_launch_us",
+                                            "alu_frac", "traffic")}
+    p1_gbs = roof["achieved"] if kname == "k_pass1" else roof.get("pass1", {}).get("achieved")
+    if p1_gbs and args.form in ("fp32", "fp32h", "split16", "splitbf16"):
         ceil = store_ceiling()
         if ceil:
             roof["store_ceiling"] = {"what": "store-only kernel with pass 1's row layout "
-                                             "(probe_store pattern A, this GPU, now)",
-                                     "GBs": ceil, "frac": round(roof["achieved"] / ceil, 4)}
+                                             "(probe_store pattern A, this GPU, now); frac = "
+                                             "k_pass1's algorithmic rate over it",
+                                     "GBs": ceil, "frac": round(p1_gbs / ceil, 4)}
 
     forms = {}
     all_forms = [args.form] + [x for x in args.also.split(",") if x and x != args.form]
