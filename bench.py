@@ -80,12 +80,12 @@ def slab_ranges(N: int, form: str, x0: int, xc: int):
     them: (slab values per shift, pass-1 row bits, transformed values per
     shift in pass 2, shifts).  Shifts below 2^L take the full slab of 2^N
     values; above, the Hermitian-pair forms and (row pairs, on by default)
-    the plain FP32 / FP64 forms take half slabs of 2^(N-1) values; the row
+    the plain and split forms take half slabs of 2^(N-1) values; the row
     pairs still transform 2^N values per shift in pass 2."""
     import paper_2512_24685_amd as sre2
 
     herm = form.endswith("h")
-    half = herm or (ROW_PAIRS and form in ("fp32", "fp64"))
+    half = herm or ROW_PAIRS
     Lf = sre2.row_bits(N, "fp64" if form.startswith("fp64") else "fp32")
     if not half:
         return [(1 << N, Lf, 1 << N, xc)]

@@ -128,20 +128,23 @@ int sre2_destroy(sre2_ctx* ctx);
  * depend on the chunk size. */
 int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes);
 
-/* Row pairs of the plain FP32 / FP64 forms (default on).  Pass 1 of the
+/* Row pairs of the plain and split forms (default on).  Pass 1 of the
  * two-pass path (N >= 15 in FP32, N >= 14 in FP64) transforms the rows of a
  * shift's 2^L x 2^(N-L) slab over their low L bits (Algorithm 1's transform
  * split into rows and columns).  Because f_x(k XOR x) = conj f_x(k) (the
  * summand of Eq. 3 at k and k XOR x), row r XOR (x >> L) of that slab is
  * row r with its L-bit input XOR-permuted and conjugated; for x >= 2^L the
  * library stores only the half of the rows whose bit j is clear (j a set bit
- * of x >> L) and pass 2 rebuilds the other half by sign flips.  The stored
- * values equal those of the full slab bit for bit, so every S_x, S and M2 is
- * identical either way; the half slab halves the memory traffic and the
- * pass-1 work of those shifts.  enable = 0 keeps the full slab (for
- * comparison).  The general index and the spectrum (sre2_sre,
- * sre2_pauli_spectrum) and the split forms always take the full slab.
- * Errors: SRE2_EINVAL (ctx == NULL). */
+ * of x >> L) and pass 2 rebuilds the other half by sign flips, which halves
+ * the memory traffic and the pass-1 work of those shifts.  In the plain
+ * FP32 / FP64 forms the rebuilt rows equal those of the full slab bit for
+ * bit, so every S_x, S and M2 is identical either way; in the split forms
+ * (whose H_16 products on the matrix cores sum in an order the permutation
+ * does not preserve) they are the exact images of the computed stored rows,
+ * so results differ from the full slab's by rounding only, within the same
+ * error bound.  enable = 0 keeps the full slab (for comparison).  The general
+ * index and the spectrum (sre2_sre, sre2_pauli_spectrum) always take the
+ * full slab.  Errors: SRE2_EINVAL (ctx == NULL). */
 int sre2_set_row_pairs(sre2_ctx* ctx, int enable);
 
 /* Device workspace (bytes) a call with these arguments grows the context to,
@@ -290,7 +293,7 @@ int sre2_timing_read(sre2_ctx* ctx, double* ms, int64_t* launches);
 /* Two-pass geometry of a full evaluation with this context's scratch limit
  * and row-pair setting: shifts per chunk of the shifts x >= 2^L (most of an
  * evaluation; half slabs in the Hermitian-pair forms and, with row pairs, in
- * the plain FP32 / FP64 forms; 0 when N uses the fused kernel) and column
+ * the plain and split forms; 0 when N uses the fused kernel) and column
  * groups per shift in pass 2.  Host-only.  Errors: SRE2_EINVAL. */
 int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int* groups);
 

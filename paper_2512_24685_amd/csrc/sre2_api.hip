@@ -134,7 +134,7 @@ Chunking chunking(int N, int form, int slab, int64_t x_count, size_t limit) {
 
 // The shifts [x0, x0 + xc) of a two-pass evaluation split into at most two
 // ranges by slab kind: the full slab below 2^L, the half slab (Hermitian
-// pair; row pairs of the plain FP32 / FP64 M2 forms when `pairs`) above.
+// pair; row pairs of the plain and split M2 forms when `pairs`) above.
 struct SlabRange {
     int slab;
     int64_t x0, xc;
@@ -144,7 +144,7 @@ int slab_ranges(int N, int form, bool pairs, int64_t x0, int64_t xc, SlabRange* 
     int half = kSlabFull;
     if (is_herm(form))
         half = kSlabHerm;
-    else if (pairs && !is_split(form))
+    else if (pairs)
         half = kSlabPairs;
     int64_t split = x1;
     if (half != kSlabFull) {

@@ -17,7 +17,7 @@ constexpr size_t kDefaultScratchLimit = size_t(32) << 30;
 struct sre2_ctx {
     int device = 0;
     size_t scratch_limit = sre2::kDefaultScratchLimit;  // halved on allocation failure, per call
-    bool row_pairs = true;  // row-pair half slabs for the plain M2 forms (sre2_set_row_pairs)
+    bool row_pairs = true;  // row-pair half slabs for the M2 forms (sre2_set_row_pairs)
     void* psi_work = nullptr;
     size_t psi_work_bytes = 0;
     double* sx = nullptr;  // S_x when the caller passes no partials buffer
@@ -50,7 +50,7 @@ struct Workspace {
     void* scratch = nullptr;   // two-pass slab
     double* part = nullptr;    // two-pass column-group partials of one chunk
     size_t limit = 0;          // slab bytes available: sets the chunk size
-    bool pairs = true;         // the plain M2 forms take row-pair slabs above 2^L
+    bool pairs = true;         // the plain and split M2 forms take row-pair slabs above 2^L
 };
 constexpr size_t red_doubles() { return 3 * (size_t)kMaxRed + 2; }
 

@@ -90,10 +90,11 @@ hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int
                                const Spec* sp, hipStream_t st);
 // Two-pass slab kinds: the full slab of 2^N values per shift; the Hermitian
 // pair's half slab (2^(N-1) values, rows of pass1_row_bits(N - 1) bits); the
-// row pairs of the plain FP32 / FP64 M2 forms (half the rows of the full
-// slab, rows of pass1_row_bits(N) bits; pass 2 rebuilds the other half
-// exactly, so S_x is bit for bit that of the full slab).  The half slabs
-// need x >= 2^L.
+// row pairs of the plain and split M2 forms (half the rows of the full slab,
+// rows of pass1_row_bits(N) bits; pass 2 rebuilds the other half from them
+// by sign flips: in the plain FP32 / FP64 forms S_x is then bit for bit that
+// of the full slab, in the split forms it differs by rounding only).  The
+// half slabs need x >= 2^L.
 constexpr int kSlabFull = 0;
 constexpr int kSlabHerm = 1;
 constexpr int kSlabPairs = 2;

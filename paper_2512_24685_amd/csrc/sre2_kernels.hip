@@ -939,7 +939,7 @@ __attribute__((amdgpu_waves_per_eu(half_lds<Real>(TB) ? half_waves(TB, RB)
 void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
              double* __restrict__ part, const int* __restrict__ scale_exp, const Spec sp,
              int64_t x0) {
-    static_assert(!PAIR || (!HERM && !SPLIT && !GEN), "row pairs: plain M2 forms only");
+    static_assert(!PAIR || (!HERM && !GEN), "row pairs: plain and split M2 forms only");
     using C = typename CT<Real>::T;
     constexpr int T = 1 << (TB - RB);
     constexpr int PK = 3000 + HT + 10000 * SPLIT;
@@ -1001,12 +1001,14 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
         }
     };
     const int c0 = g * per, c1 = (g + 1) * per;
-    // Plain and Hermitian tiles that fit the LDS whole load the next tile
-    // while transforming this one (two register sets; these kernels are held
-    // to two waves per SIMD by their LDS tiles, which leaves the registers);
+    // Plain, Hermitian and row-pair tiles that fit the LDS whole load the
+    // next tile while transforming this one (two register sets; these
+    // kernels are held to two waves per SIMD by their LDS tiles, which leaves
+    // the registers; the full-slab split kernel and split tiles above 2^12
+    // values have none to spare);
     // barriers wait on LDS only, so the loads stay in flight across the
     // transform.  load_tile(v, ct) fills v with column tile ct.
-    constexpr bool PREFETCH = !half_lds<Real>(TB) && !SPLIT && !GEN;
+    constexpr bool PREFETCH = !half_lds<Real>(TB) && (!SPLIT || (PAIR && TB <= 12)) && !GEN;
     auto tiles = [&](auto&& load_tile) {
         if constexpr (PREFETCH) {
             C va[1 << RB], vn[1 << RB];
@@ -1287,17 +1289,23 @@ hipError_t launch_pass2_ht(const void* scratch, int NS, int cs, int P, double* p
     return hipGetLastError();
 }
 
-// Register row bits of the first round of the plain pass-2 tile of HT rows:
-// the preferred left-out row bits of the row pairs.
-template <typename Real, int HT>
+// Register row bits of the first round of the pass-2 tile of HT rows (split
+// form s: its matrix-core plan): the preferred left-out row bits of the row
+// pairs, so that pass 1 leaves out the rows pass 2 rebuilds.
+template <typename Real, int HT, int SPLIT>
 constexpr uint32_t pass2_reg_rows() {
     constexpr int TB = pass2_tb<Real>(HT), RB = Tune<Real>::RB2;
-    return plan_of<Real, TB, RB, 3000 + HT>().r[0].reg >> (TB - HT);
+    return plan_of<Real, TB, RB, 3000 + HT + 10000 * SPLIT>().r[0].reg >> (TB - HT);
 }
 template <typename Real, int... Hs>
-uint32_t pair_pref_of(int HT, std::integer_sequence<int, Hs...>) {
+uint32_t pair_pref_of(int HT, int split, std::integer_sequence<int, Hs...>) {
     uint32_t m = 0;
-    ((HT == Hs + 1 ? (m = pass2_reg_rows<Real, Hs + 1>(), 0) : 0), ...);
+    ((HT == Hs + 1 ? (m = split == 0 ? pass2_reg_rows<Real, Hs + 1, 0>()
+                        : split == 1 ? pass2_reg_rows<Real, Hs + 1, 1>()
+                                     : pass2_reg_rows<Real, Hs + 1, 2>(),
+                      0)
+                   : 0),
+     ...);
     return m;
 }
 
@@ -1393,19 +1401,25 @@ hipError_t launch_pass1_tb(const void* psi, int NS, bool half, int split, int64_
     const int64_t rows = (int64_t)1 << (NS - TB);
     if (cs < 1 || rows > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)cs, (unsigned)rows), block(1 << (TB - RB)), blocks(1 << (TB - RBS));
-    if (half)
-        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
-                           NS, x0, cs, (C*)scratch, se, pref);
-    else if (split) {
+    if (split) {
         if constexpr (sizeof(Real) == 4) {
-            if (split == 1)
+            if (split == 1 && half)
+                hipLaunchKernelGGL((k_pass1<Real, TB, RBS, true, 1>), grid, blocks, 0, st,
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
+            else if (split == 1)
                 hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 1>), grid, blocks, 0, st,
+                                   (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
+            else if (half)
+                hipLaunchKernelGGL((k_pass1<Real, TB, RBS, true, 2>), grid, blocks, 0, st,
                                    (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
             else
                 hipLaunchKernelGGL((k_pass1<Real, TB, RBS, false, 2>), grid, blocks, 0, st,
                                    (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
         }
-    } else
+    } else if (half)
+        hipLaunchKernelGGL((k_pass1<Real, TB, RB, true, 0>), grid, block, 0, st, (const C*)psi,
+                           NS, x0, cs, (C*)scratch, se, pref);
+    else
         hipLaunchKernelGGL((k_pass1<Real, TB, RB, false, 0>), grid, block, 0, st,
                            (const C*)psi, NS, x0, cs, (C*)scratch, se, pref);
     return hipGetLastError();
@@ -1439,14 +1453,16 @@ hipError_t launch_pass1(const void* psi, int N, int slab, int split, int64_t x0,
                         void* scratch, const int* se, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
     if (slab < kSlabFull || slab > kSlabPairs || split < 0 || split > 2 ||
-        (split && (slab != kSlabFull || sizeof(Real) != 4)))
+        (split && (slab == kSlabHerm || sizeof(Real) != 4)))
         return hipErrorInvalidValue;
     int NS, L;
     slab_geometry<Real>(N, slab, &NS, &L);
     if (slab != kSlabFull && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
     constexpr int HMAX = pass2_max_rows<Real>();
     const uint32_t pref =
-        slab == kSlabPairs ? pair_pref_of<Real>(N - L, std::make_integer_sequence<int, HMAX>{}) : 0u;
+        slab == kSlabPairs
+            ? pair_pref_of<Real>(N - L, split, std::make_integer_sequence<int, HMAX>{})
+            : 0u;
     return dispatch_pass1<Real>(
         L, psi, NS, slab != kSlabFull, split, x0, cs, scratch, se, pref, st,
         std::make_integer_sequence<int, Prec<Real>::MAXTB - Tune<Real>::ROW + 1>{});
@@ -1457,7 +1473,7 @@ hipError_t launch_pass2(const void* scratch, int N, int slab, int split, int64_t
                         int P, double* part, const int* se, const Spec* sp, hipStream_t st) {
     if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return hipErrorInvalidValue;
     if (slab < kSlabFull || slab > kSlabPairs || split < 0 || split > 2 ||
-        (split && (slab != kSlabFull || sizeof(Real) != 4)) || (sp && slab == kSlabPairs))
+        (split && (slab == kSlabHerm || sizeof(Real) != 4)) || (sp && slab == kSlabPairs))
         return hipErrorInvalidValue;
     int NS, L;
     slab_geometry<Real>(N, slab, &NS, &L);
@@ -1481,9 +1497,18 @@ hipError_t launch_pass2(const void* scratch, int N, int slab, int split, int64_t
     if (herm)
         return dispatch_pass2<Real, true, 0, false>(HT, scratch, NS, cs, P, part, se, none, x0,
                                                     st, hs);
-    if (slab == kSlabPairs)
+    if (slab == kSlabPairs) {
+        if constexpr (sizeof(Real) == 4) {
+            if (split == 1)
+                return dispatch_pass2<Real, false, 1, false, true>(HT, scratch, NS, cs, P, part,
+                                                                   se, none, x0, st, hs);
+            if (split == 2)
+                return dispatch_pass2<Real, false, 2, false, true>(HT, scratch, NS, cs, P, part,
+                                                                   se, none, x0, st, hs);
+        }
         return dispatch_pass2<Real, false, 0, false, true>(HT, scratch, NS, cs, P, part, se, none,
                                                            x0, st, hs);
+    }
     if constexpr (sizeof(Real) == 4) {
         if (split == 1)
             return dispatch_pass2<Real, false, 1, false>(HT, scratch, NS, cs, P, part, se, none,

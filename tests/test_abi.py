@@ -175,7 +175,7 @@ def test_workspace_bytes_covers_default_chunks(L):
     pairs of the plain FP32 / FP64 forms) for every form."""
     ctx = sre2.Context(0)
     try:
-        for form, herm in (("fp32", True), ("fp32h", True), ("split16", False),
+        for form, herm in (("fp32", True), ("fp32h", True), ("split16", True),
                            ("fp64", True), ("fp64h", True)):
             elem = 16 if form.startswith("fp64") else 8
             for N in (15, 18, 20, 22, 24):
@@ -218,21 +218,22 @@ def test_noalloc_argument_validation(L):
 
 
 def test_row_pairs_setting_sets_the_chunk_shape():
-    """sre2_set_row_pairs: host-only; with row pairs the plain FP32 / FP64
+    """sre2_set_row_pairs: host-only; with row pairs the plain and split
     forms chunk the shifts above 2^L in half slabs (twice the shifts per
-    chunk at the same scratch limit), without them in full slabs."""
+    chunk at the same scratch limit), without them in full slabs; the
+    Hermitian-pair forms keep their own half slabs either way."""
     L = sre2.lib()
     assert L.sre2_set_row_pairs(None, 1) == sre2.EINVAL
     ctx = sre2.Context(0)
     try:
-        for form in ("fp32", "fp64"):
+        for form in ("fp32", "fp64", "split16", "splitbf16"):
             cs_on, P_on = ctx.chunking(22, form)
             ctx.set_row_pairs(False)
             cs_off, P_off = ctx.chunking(22, form)
             ctx.set_row_pairs(True)
             assert cs_on == 2 * cs_off and P_on == P_off
-        cs_s, _ = ctx.chunking(22, "split16")
+        cs_h, _ = ctx.chunking(22, "fp32h")
         ctx.set_row_pairs(False)
-        assert ctx.chunking(22, "split16")[0] == cs_s  # split forms: full slabs always
+        assert ctx.chunking(22, "fp32h")[0] == cs_h
     finally:
         ctx.close()

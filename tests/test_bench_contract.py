@@ -28,7 +28,7 @@ def test_stored_counters_match_the_kernel_code():
     t = bench.stored_traffic("k_pass1", 20, "fp32")
     assert t is not None and abs(t / 2 ** 34 - 1) < 0.05  # the 16 GiB half slab of a row-pair chunk
     t = bench.stored_traffic("k_pass1", 20, "split16")
-    assert t is not None and abs(t / 2 ** 35 - 1) < 0.05  # the 32 GiB full slab of a split chunk
+    assert t is not None and abs(t / 2 ** 34 - 1) < 0.05  # the split form's row pairs too
 
 
 def test_more_than_one_gpu_is_refused():
@@ -39,11 +39,11 @@ def test_more_than_one_gpu_is_refused():
 
 @pytest.mark.parametrize("form,eb,L,half", [("fp32", 8, 12, True), ("fp32h", 8, 12, True),
                                              ("fp64", 16, 11, True), ("fp64h", 16, 11, True),
-                                             ("split16", 8, 12, False)])
+                                             ("split16", 8, 12, True)])
 def test_algorithmic_bytes_per_evaluation(form, eb, L, half):
     """Slab bytes of a whole N = 20 evaluation: shifts below 2^L take the
     full slab of 2^20 values, the others (Hermitian pair, row pairs) half
-    slabs; the split forms take full slabs throughout."""
+    slabs (also the split forms, with row pairs on by default)."""
     pytest.importorskip("torch")
     by, ops = bench.alg_totals(20, form, "pass1", 0, 1 << 20)
     vals = (1 << L) * (1 << 20) + ((1 << 20) - (1 << L)) * (1 << 19) if half else 1 << 40

@@ -228,6 +228,33 @@ def test_row_pairs_bitwise_equal_full_slab(form, N):
         off.close()
 
 
+@pytest.mark.parametrize("form,N", [("split16", 15), ("split16", 18), ("splitbf16", 17),
+                                    ("split16", 20)])
+def test_row_pairs_split_forms_within_rounding(oracle_mod, form, N):
+    """Split forms with row pairs: the rebuilt rows are the exact images of
+    the computed stored rows, so S_x differs from the full slab's by rounding
+    only (the matrix cores sum the H_16 products in their own order): both
+    within the FP32 per-shift bar of each other and of the oracle."""
+    psi_np = W.haar(N, 500 + N, np.complex64)
+    psi = dev(psi_np)
+    case_id("row-pairs-split", form, N)
+    on, off = sre2.Context(0), sre2.Context(0)
+    off.set_row_pairs(False)
+    try:
+        a = sre2.shift_partials(psi, form=form, ctx=on).cpu().numpy()
+        b = sre2.shift_partials(psi, form=form, ctx=off).cpu().numpy()
+        assert np.max(np.abs(a - b) / b) <= TOL_SX[form]
+        xs = [0, 1, (1 << 12) + 5, (1 << N) - 1, 3 << (N - 2)]
+        ref = oracle_mod.partials(psi_np.astype(np.complex128), xs)
+        assert np.max(np.abs(a[xs] - ref) / ref) <= TOL_SX[form]
+        ra = sre2.m2(psi, form=form, ctx=on)
+        rb = sre2.m2(psi, form=form, ctx=off)
+        assert abs(ra.m2 - rb.m2) <= TOL_M2[form]
+    finally:
+        on.close()
+        off.close()
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp64"])
 @pytest.mark.parametrize("N", [22, 24])
 def test_row_pairs_bitwise_large_chunk(form, N):
@@ -382,8 +409,8 @@ def test_large_n_full_default_chunk(oracle_mod, N, form):
     ctx = sre2.Context(0)
     try:
         cs, _ = ctx.chunking(N, form)
-        half = form.endswith("h") or form in ("fp32", "fp64")  # Hermitian pair, row pairs
-        assert cs == (1024 if N == 22 else 256) // (2 if c128 else 1) * (2 if half else 1)
+        # half slabs in every form: Hermitian pair, row pairs
+        assert cs == (1024 if N == 22 else 256) // (2 if c128 else 1) * 2
         x0 = 1 << (N - 1)
         xs = x0 + np.arange(cs, dtype=np.int64)
         case_id("large-chunk-t", N, form, cs)

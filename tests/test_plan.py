@@ -663,21 +663,22 @@ def pair_shifts(rd, tb, cb, N, L, rng):
 
 
 def test_row_pair_sources(probe):
-    """Every pass-2 plan (both precisions, every row count H): the row-pair
+    """Every pass-2 plan (both precisions and the split form, every row
+    count H): the row-pair
     loads fetch, for tile element e = (row r, column c) of column tile ct, the
     stored row remove_bit(r, j) when bit j of r is clear, else the partner
     remove_bit(r ^ xh, j) with the real part negated iff
     popcount(z & xl) is odd and the imaginary part iff it is even
     (z = ct 2^cb + c): row(r ^ xh)[z] = (-1)^popcount(z & xl) conj row(r)[z]."""
     rng = np.random.default_rng(11)
-    for prec in (0, 1):
+    for prec, split in ((0, 0), (1, 0), (0, 1)):
         fmax, _, nmax = geo(probe, prec, LIMITS)
         for N in range(fmax + 1, nmax + 1):
             L = geo(probe, prec, PASS1, N)[0]
             HT = N - L
             tb, rb, sb = geo(probe, prec, PASS2, HT)
             cb = tb - HT
-            rd = plan(probe, tb, rb, sb, cb, tb, 0, "pass2")[0]
+            rd = plan(probe, tb, rb, sb, cb, tb, split, "pass2")[0]
             for x in pair_shifts(rd, tb, cb, N, L, rng):
                 for ct in (0, (1 << (L - cb)) - 1):
                     M, j, off, fx, fy = pair_sources(rd, tb, rb, cb, L, x, ct)
@@ -694,17 +695,19 @@ def test_row_pair_sources(probe):
                     assert off.min() >= 0 and off.max() < 1 << (N - 1)
 
 
-def emulate_row_pairs(probe, psi, prec, xs):
+def emulate_row_pairs(probe, psi, prec, xs, split=0):
     """Per-shift sums with row-pair slabs: pass 1 builds only the rows with
-    bit j clear, pass 2 loads through pair_sources."""
+    bit j clear (j preferred among the register row bits of pass 2's plan,
+    the split form's own plan in the split form), pass 2 loads through
+    pair_sources."""
     N = psi.size.bit_length() - 1
     L, _, sb = geo(probe, prec, PASS1, N)
-    rb1 = p1rb(probe, prec, L)
+    rb1 = p1rb(probe, prec, L, split)
     HT = N - L
     tb2, rb2, _ = geo(probe, prec, PASS2, HT)
     cb = tb2 - HT
-    p1 = plan(probe, L, rb1, sb, 0, L, 0, "pass1")
-    p2 = plan(probe, tb2, rb2, sb, cb, tb2, 0, "pass2")
+    p1 = plan(probe, L, rb1, sb, 0, L, 2 * split, "pass1")
+    p2 = plan(probe, tb2, rb2, sb, cb, tb2, split, "pass2")
     rrow = (p2[0][0] & ((1 << tb2) - 1)) >> cb
     e1 = np.arange(1 << L)
     out = []
@@ -728,13 +731,14 @@ def emulate_row_pairs(probe, psi, prec, xs):
     return np.array(out)
 
 
-@pytest.mark.parametrize("prec,extra", [(0, 1), (0, 3), (1, 1), (1, 3)])
-def test_row_pairs_match_oracle(probe, oracle_mod, prec, extra):
+@pytest.mark.parametrize("prec,extra,split", [(0, 1, 0), (0, 3, 0), (1, 1, 0), (1, 3, 0),
+                                               (0, 1, 1), (0, 3, 1)])
+def test_row_pairs_match_oracle(probe, oracle_mod, prec, extra, split):
     fmax, L, _ = geo(probe, prec, LIMITS)
     N = fmax + extra
     psi = W.haar(N, 17)
     L = geo(probe, prec, PASS1, N)[0]
     xs = [1 << L, (1 << N) - 1, 0x2A5A % (1 << N) | (1 << L), 1 << (N - 1), 3 << (N - 2),
           (1 << L) | 5]
-    S = emulate_row_pairs(probe, psi, prec, xs)
+    S = emulate_row_pairs(probe, psi, prec, xs, split)
     assert np.allclose(S, oracle_mod.partials(psi, xs), rtol=1e-11, atol=0)
