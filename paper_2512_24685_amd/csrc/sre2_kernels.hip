@@ -790,7 +790,8 @@ void k_fused(const typename CT<Real>::T* __restrict__ psi, int64_t x_begin, int6
 // a half slab of NS = N - 1: only the rows whose bit j = half_row_bit(x >> L,
 // pref) is clear (x >= 2^L, so that j is a row bit), for the Hermitian pair
 // (pref = 0: j is the top set bit of x) and for the row pairs of the plain
-// forms (pref = pass 2's register row bits, L that of the full slab).  Grid
+// and split forms (pref = the register row bits of the pass-2 plan, L that
+// of the full slab).  Grid
 // (cs, rows): block (s, r) takes shift slot s of slab row r; blocks are
 // dispatched with x fastest, so neighbouring blocks read the same psi rows.
 // ---------------------------------------------------------------------------
@@ -849,7 +850,7 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 }
 
 // ---------------------------------------------------------------------------
-// Row pairs (plain forms, shifts x >= 2^L).  With xh = x >> L and
+// Row pairs (plain and split forms, shifts x >= 2^L).  With xh = x >> L and
 // xl = x mod 2^L, f_x(k ^ x) = conj f_x(k) makes slab row r ^ xh of pass 1
 // the row r transformed with its input XOR-permuted by xl and conjugated, so
 //   row(r ^ xh)[z] = (-1)^popcount(z & xl) conj(row(r)[z]).
@@ -859,7 +860,10 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // So pass 1 stores only the rows with bit j = half_row_bit(xh, register row
 // bits of the pass-2 tile) clear, and pass 2 rebuilds a row with bit j set
 // from its partner: conjugate and sign are sign-bit flips, and the column
-// transform then runs on exactly the values of the full slab.  A launch
+// transform then runs on exactly the values of the full slab.  (The split
+// forms' H_16 products on the matrix cores sum in an order the permutation
+// does not preserve: there the rebuilt rows are the exact images of the
+// computed stored rows, equal to the full slab's up to rounding.)  A launch
 // covers shifts of one row part xh (its chunk stays inside one block of 2^L
 // shifts), so j is one value per launch and the kernel runs a tile loop
 // specialised on it: j is taken among the register row bits when xh has one,
