@@ -228,6 +228,34 @@ def test_row_pairs_bitwise_equal_full_slab(form, N):
         off.close()
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_row_pairs_ragged_ranges_and_small_chunks(oracle_mod, form):
+    """Shift ranges that start inside a block of 2^L shifts and cross
+    several of them, with a scratch limit that leaves chunks of a few
+    shifts: the row-pair chunks split at every block edge, bit for bit the
+    full slab's S_x and within the bar of the oracle."""
+    N = 16
+    c128 = is64(form)
+    psi_np = W.haar(N, 611, np.complex128 if c128 else np.complex64)
+    psi = dev(psi_np)
+    L = sre2.row_bits(N, form)
+    x0, xc = (1 << L) - 6, 2 * (1 << L) + 613
+    case_id("row-pairs-ragged", form, x0, xc)
+    on, off = sre2.Context(0), sre2.Context(0)
+    off.set_row_pairs(False)
+    on.set_scratch_limit(5 << 20)
+    try:
+        a = sre2.shift_partials(psi, x0, xc, form=form, ctx=on).cpu().numpy()
+        b = sre2.shift_partials(psi, x0, xc, form=form, ctx=off).cpu().numpy()
+        assert np.array_equal(a, b)
+        pick = np.array([0, 5, 6, 7, (1 << L) + 5, (1 << L) + 6, xc - 1])
+        ref = oracle_mod.partials(psi_np, x0 + pick)
+        assert np.max(np.abs(a[pick] - ref) / ref) <= TOL_SX[form]
+    finally:
+        on.close()
+        off.close()
+
+
 @pytest.mark.parametrize("form,N", [("split16", 15), ("split16", 18), ("splitbf16", 17),
                                     ("split16", 20)])
 def test_row_pairs_split_forms_within_rounding(oracle_mod, form, N):
