@@ -7,7 +7,7 @@ that stops - a killed job, a lost node - resumes at the first range not yet
 stored.  The end is `sre2_m2_from_partials`: the norm, the fixed-order sum
 over x and the logarithm of `sre2_m2`, so the result is bitwise that of one
 uninterrupted call (S_x of a shift do not depend on the range it was computed
-in).  A whole N = 24 FP32 evaluation took 894 s on one MI355X.
+in).  A whole N = 24 FP32 evaluation takes about 13 minutes on one MI355X.
 
 Files: `<path>.sx.npy` (float64, 2^N S_x, written in place as ranges finish)
 and `<path>.json` (N, form, input dtype, SHA-256 of the state's bytes and the
