@@ -742,3 +742,49 @@ def test_row_pairs_match_oracle(probe, oracle_mod, prec, extra, split):
           (1 << L) | 5]
     S = emulate_row_pairs(probe, psi, prec, xs, split)
     assert np.allclose(S, oracle_mod.partials(psi, xs), rtol=1e-11, atol=0)
+
+
+def _fwht_rows_f32(re, im):
+    """Unnormalised FWHT along the last axis in float32, one stage per bit
+    ((u, v) -> (u + v, u - v)), every operation rounded to float32."""
+    re, im = re.copy(), im.copy()
+    n = re.shape[-1]
+    h = 1
+    while h < n:
+        a = re.reshape(re.shape[:-1] + (n // (2 * h), 2, h))
+        b = im.reshape(im.shape[:-1] + (n // (2 * h), 2, h))
+        ua, va = a[..., 0, :].copy(), a[..., 1, :].copy()
+        ub, vb = b[..., 0, :].copy(), b[..., 1, :].copy()
+        a[..., 0, :], a[..., 1, :] = ua + va, ua - va
+        b[..., 0, :], b[..., 1, :] = ub + vb, ub - vb
+        h *= 2
+    return re, im
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_row_pair_identity_is_exact_in_float32(seed):
+    """The identity the row pairs rely on, in IEEE float32 with every
+    operation rounded: the row transform of slab row r ^ xh equals
+    (-1)^popcount(z & xl) conj of that of row r bit for bit, when the
+    products conj(a) b round their imaginary part as two products and a
+    difference (the real part is symmetric in a and b either way)."""
+    rng = np.random.default_rng(seed)
+    N, L = 10, 6
+    psi = (rng.standard_normal(1 << N) + 1j * rng.standard_normal(1 << N)).astype(np.complex64)
+    pr, pi = psi.real.astype(np.float32), psi.imag.astype(np.float32)
+    k = np.arange(1 << N)
+    for x in rng.integers(1 << L, 1 << N, size=8):
+        x = int(x)
+        a_r, a_i = pr[k ^ x], pi[k ^ x]
+        # conj(a) * b with a = psi[k ^ x], b = psi[k]
+        fr = (a_r * pr + a_i * pi).astype(np.float32)
+        fi = ((a_r * pi).astype(np.float32) - (a_i * pr).astype(np.float32)).astype(np.float32)
+        rows_r, rows_i = _fwht_rows_f32(fr.reshape(-1, 1 << L), fi.reshape(-1, 1 << L))
+        xh, xl = x >> L, x & ((1 << L) - 1)
+        z = np.arange(1 << L)
+        neg = (popc_np(z & xl) & 1).astype(bool)
+        for r in range(1 << (N - L)):
+            want_r = np.where(neg, -rows_r[r], rows_r[r])
+            want_i = np.where(neg, rows_i[r], -rows_i[r])
+            assert np.array_equal(rows_r[r ^ xh].view(np.uint32), want_r.view(np.uint32))
+            assert np.array_equal(rows_i[r ^ xh].view(np.uint32), want_i.view(np.uint32))
