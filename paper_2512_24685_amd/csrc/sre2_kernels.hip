@@ -51,7 +51,10 @@ template <> struct CT<double> { using T = double2; };
 // conj(a) * b.  The imaginary part rounds both products before the
 // difference (no fused multiply-add), so that cmul_conj_a(b, a) is exactly
 // conj(cmul_conj_a(a, b)): f_x(k ^ x) = conj f_x(k) then holds bit for bit,
-// which the row-pair slabs of the two-pass path rely on.
+// which the row-pair slabs of the two-pass path rely on.  The real part may
+// fuse one product: a.x b.x + a.y b.y with either product fused is the same
+// for (a, b) and (b, a), as the same expression fuses the same position
+// (the GPU tests compare row-pair and full-slab results bit for bit).
 template <typename C>
 __device__ __forceinline__ C cmul_conj_a(C a, C b) {
     C r;
