@@ -79,9 +79,10 @@ def slab_ranges(N: int, form: str, x0: int, xc: int):
     """The two-pass ranges of the shifts [x0, x0 + xc) as the library runs
     them: (slab values per shift, pass-1 row bits, transformed values per
     shift in pass 2, shifts).  Shifts below 2^L take the full slab of 2^N
-    values; above, the Hermitian-pair forms and (row pairs, on by default)
-    the plain and split forms take half slabs of 2^(N-1) values; the row
-    pairs still transform 2^N values per shift in pass 2."""
+    values; above (from `sre2_half_slab_first_shift`), the Hermitian-pair
+    forms and (row pairs, on by default) the plain and split forms take half
+    slabs of 2^(N-1) values; the row pairs still transform 2^N values per
+    shift in pass 2."""
     import paper_2512_24685_amd as sre2
 
     herm = form.endswith("h")
@@ -90,7 +91,8 @@ def slab_ranges(N: int, form: str, x0: int, xc: int):
     if not half:
         return [(1 << N, Lf, 1 << N, xc)]
     Lh = sre2.row_bits(N, form)
-    lo = max(0, min(x0 + xc, 1 << Lh) - x0)
+    first = sre2.half_slab_first_shift(N, form)
+    lo = max(0, min(x0 + xc, first) - x0)
     out = [(1 << N, Lf, 1 << N, lo)] if lo else []
     if xc > lo:
         out.append((1 << (N - 1), Lh, 1 << (N - 1) if herm else 1 << N, xc - lo))

@@ -147,6 +147,15 @@ int sre2_set_scratch_limit(sre2_ctx* ctx, size_t bytes);
  * full slab.  Errors: SRE2_EINVAL (ctx == NULL). */
 int sre2_set_row_pairs(sre2_ctx* ctx, int enable);
 
+/* First shift x of an N-qubit evaluation that takes a half slab in the
+ * two-pass path with the default settings (Hermitian pair; row pairs, which
+ * start at 2^L, or in the plain forms where x >> L has a register row bit
+ * of the pass-2 tile when that tile is a half-LDS one: 2^(L + 5) at N = 22
+ * and 24 in FP32);
+ * shifts below it take the full slab.  2^N when N uses the fused kernel.
+ * Host-only.  Returns -1 for invalid arguments. */
+int64_t sre2_half_slab_first_shift(int N, int form);
+
 /* Device workspace (bytes) a call with these arguments grows the context to,
  * with the current default scratch limit.  0 for invalid arguments. */
 size_t sre2_workspace_bytes(int N, int dtype, int form);

@@ -64,6 +64,7 @@ def lib():
         "sre2_destroy": ([vp], c_int),
         "sre2_set_scratch_limit": ([vp, sz], c_int),
         "sre2_set_row_pairs": ([vp, c_int], c_int),
+        "sre2_half_slab_first_shift": ([c_int, c_int], i64),
         "sre2_workspace_bytes": ([c_int, c_int, c_int], sz),
         "sre2_m2": ([vp, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
         "sre2_m2_noalloc": ([c_int, vp, c_int, c_int, c_int, vp, vp, vp], c_int),
@@ -112,6 +113,15 @@ def header_functions() -> list[str]:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sre2_[a-z0-9_]+)\s*\(", text)))
+
+
+def half_slab_first_shift(N: int, form: str = "fp32") -> int:
+    """First shift that takes a half slab (Hermitian pair, row pairs) in a
+    default evaluation; 2^N when there is none."""
+    v = lib().sre2_half_slab_first_shift(N, FORMS[form])
+    if v < 0:
+        raise ValueError(f"no two-pass geometry for N={N} form={form}")
+    return int(v)
 
 
 def row_bits(N: int, form: str = "fp32") -> int:

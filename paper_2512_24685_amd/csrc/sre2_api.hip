@@ -150,7 +150,10 @@ int slab_ranges(int N, int form, bool pairs, int64_t x0, int64_t xc, SlabRange* 
         half = kSlabPairs;
     int64_t split = x1;
     if (half != kSlabFull) {
-        const int64_t lim = int64_t(1) << slab_rows(form, N, half);
+        const int64_t lim =
+            half == kSlabHerm ? int64_t(1) << slab_rows(form, N, half)
+            : is_f64(form)    ? pair_first_shift<double>(N, 0)
+                              : pair_first_shift<float>(N, split_kind(form));
         split = x0 > lim ? x0 : (x1 < lim ? x1 : lim);
     }
     int k = 0;
@@ -830,6 +833,16 @@ int sre2_chunking(sre2_ctx* ctx, int N, int form, int64_t* shifts_per_chunk, int
     *shifts_per_chunk = ch.cs;
     *groups = ch.P;
     return SRE2_OK;
+}
+
+int64_t sre2_half_slab_first_shift(int N, int form) {
+    if (N < 1 || N > SRE2_MAX_N || !form_ok(form)) return -1;
+    if (N > (is_f64(form) ? max_n<double>() : max_n<float>())) return -1;
+    const int64_t n = int64_t(1) << N;
+    if (N <= fused_max(form)) return n;
+    SlabRange rg[2];
+    const int nr = slab_ranges(N, form, true, 0, n, rg);
+    return rg[nr - 1].slab == kSlabFull ? n : rg[nr - 1].x0;
 }
 
 int sre2_set_row_pairs(sre2_ctx* ctx, int enable) {

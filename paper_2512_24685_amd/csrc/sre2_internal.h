@@ -102,6 +102,11 @@ constexpr int kSlabPairs = 2;
 // row-transformed slabs (cs * 2^N or cs * 2^(N-1) complex values) to
 // `scratch`; pass 2 writes part[s*P + p], the p-th column-group partial of
 // shift x0+s.
+// First shift of the row-pair range (shifts below it take the full slab):
+// 2^L, or 2^(L + r) when the plain pass-2 tile is a half-LDS tile (r: the
+// lowest register row bit of its plan); 2^N when N is fused.
+template <typename Real>
+int64_t pair_first_shift(int N, int split);
 template <typename Real>
 hipError_t launch_pass1(const void* psi, int N, int slab, int split, int64_t x0, int cs,
                         void* scratch, const int* se, hipStream_t st);

@@ -872,7 +872,10 @@ void k_pass1(const typename CT<Real>::T* __restrict__ psi, int NS, int64_t x0, i
 // specialised on it: j is taken among the register row bits when xh has one,
 // so that which elements are rebuilt is fixed per register index
 // (pair_load_reg); otherwise xh has only thread row bits and whole threads
-// hold rebuilt rows (pair_load_thr).  Stored values are read twice (as
+// hold rebuilt rows (pair_load_thr; not in the plain half-LDS tiles, whose
+// row pairs start where xh has a register row bit, pair_first_shift, and
+// which form the thread's address parts per tile to stay within their
+// registers).  Stored values are read twice (as
 // themselves and as a partner) inside one tile, the second time from the
 // caches.
 // ---------------------------------------------------------------------------
@@ -982,6 +985,13 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
     // the thread's stored-row (vb0) and partner-row (vb1) address parts and
     // the sign (-1)^popcount(z & xl) of its column bits
     constexpr uint32_t RROW = r0.reg >> CB;
+    // the thread-row variant is left out of the plain half-LDS tiles (their
+    // registers are full); their row pairs start where x >> L has a register
+    // row bit, which for their plans (the top row bits in registers) is
+    // x >= 2^(L + lowest register row bit), pair_first_shift
+    constexpr bool THR = !half_lds<Real>(TB) || SPLIT;
+    static_assert(!PAIR || THR || RROW + (RROW & (0u - RROW)) == (1u << HT),
+                  "half-LDS row pairs need the top row bits in registers");
     uint32_t xh = 0, xl = 0, vb0 = 0, vb1 = 0, sT = 0, fm = 0;
     int j = 0;
     if constexpr (PAIR) {
@@ -990,10 +1000,12 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
         xl = (uint32_t)x & ((1u << L) - 1u);
         j = half_row_bit(xh, RROW);
         const uint32_t rowT = base >> CB, colT = base & CMASK;
-        vb0 = (remove_bit(rowT, j) << L) + colT;
-        vb1 = (remove_bit(rowT ^ (xh & ~RROW), j) << L) + colT;
-        sT = __builtin_popcount(colT & xl) & 1u;
-        fm = 0u - ((rowT >> j) & 1u);
+        if constexpr (THR) {
+            vb0 = (remove_bit(rowT, j) << L) + colT;
+            vb1 = (remove_bit(rowT ^ (xh & ~RROW), j) << L) + colT;
+            sT = __builtin_popcount(colT & xl) & 1u;
+            fm = 0u - ((rowT >> j) & 1u);
+        }
     }
     double acc = 0.0;
     // column transform of one tile and its terms, tiles in ascending order
@@ -1040,19 +1052,38 @@ void k_pass2(const typename CT<Real>::T* __restrict__ scratch, int NS, int P,
         if ((RROW >> j) & 1u) {
             with_reg_row_bit<RROW>(j, [&](auto J) {
                 tiles([&](C (&v)[1 << RB], int ct) {
+                    constexpr int JJ = decltype(J)::value;
                     const uint32_t cto = (uint32_t)ct << CB;
-                    const uint32_t mT = ((sT ^ __builtin_popcount(cto & xl)) & 1u) ? kSign : 0u;
-                    pair_load_reg<C, RB, r0.reg, CB, decltype(J)::value>(v, rs, L, vb0, vb1, xh,
-                                                                         xl, cto, mT);
+                    uint32_t v0 = vb0, v1 = vb1, st = sT;
+                    if constexpr (!THR) {
+                        // large tiles: the thread's parts formed per tile from
+                        // its id (the empty asm statements keep them there),
+                        // so that no register holds them across the
+                        // transform; remove_bit is linear over XOR, so the
+                        // partner part is the stored part XOR a uniform term
+                        uint32_t tb = thread_base<r0.lperm, r0.wave>();
+                        uint32_t xt = remove_bit(xh & ~RROW, JJ) << L;
+                        asm volatile("" : "+v"(tb), "+s"(xt));
+                        v0 = (remove_bit(tb >> CB, JJ) << L) + (tb & CMASK);
+                        v1 = v0 ^ xt;
+                        st = __builtin_popcount(tb & CMASK & xl) & 1u;
+                    }
+                    const uint32_t mT = ((st ^ __builtin_popcount(cto & xl)) & 1u) ? kSign : 0u;
+                    pair_load_reg<C, RB, r0.reg, CB, JJ>(v, rs, L, v0, v1, xh, xl, cto, mT);
                 });
             });
-        } else {
+        } else if constexpr (THR) {
             const uint32_t vbt = fm ? vb1 : vb0;
             tiles([&](C (&v)[1 << RB], int ct) {
                 const uint32_t cto = (uint32_t)ct << CB;
                 const uint32_t mT = ((sT ^ __builtin_popcount(cto & xl)) & 1u) ? kSign : 0u;
                 pair_load_thr<C, RB, r0.reg, CB>(j, v, rs, L, vbt, fm, xl, cto, mT);
             });
+        } else {
+            // half-LDS tiles take row pairs only for shifts whose row part
+            // has a register row bit (pair_first_shift); a launch outside
+            // that range reports NaN rather than a wrong sum
+            acc = __builtin_nan("");
         }
     } else {
         tiles([&](C (&v)[1 << RB], int ct) {
@@ -1400,6 +1431,29 @@ hipError_t launch_shift_kernel(const void* psi, int N, bool herm, int split, int
     return shift_kernel_gen<Real, false>(psi, N, herm, split, x0, xc, S, se, pk, Spec{}, st);
 }
 
+template <typename Real, int... Hs>
+int64_t pair_first_shift_of(int N, int split, std::integer_sequence<int, Hs...> hs) {
+    const int L = row_bits_of<Real>(N), HT = N - L;
+    int64_t first = (int64_t)1 << L;
+    if (split == 0 && half_lds<Real>(pass2_tb<Real>(HT))) {
+        const uint32_t rrow = pair_pref_of<Real>(HT, split, hs);
+        first = (int64_t)1 << (L + __builtin_ctz(rrow));
+    }
+    return first;
+}
+
+// First shift of the row-pair range of an N-qubit evaluation (split form
+// `split`): 2^L, or for the plain half-LDS pass-2 tiles 2^(L + r) with r the
+// lowest register row bit of the pass-2 plan, so that x >> L has one.
+template <typename Real>
+int64_t pair_first_shift(int N, int split) {
+    if (N <= Tune<Real>::FMAX || N > max_n_of<Real>()) return (int64_t)1 << N;
+    constexpr int HMAX = pass2_max_rows<Real>();
+    return pair_first_shift_of<Real>(N, split, std::make_integer_sequence<int, HMAX>{});
+}
+template int64_t pair_first_shift<float>(int, int);
+template int64_t pair_first_shift<double>(int, int);
+
 template <typename Real, int TB>
 hipError_t launch_pass1_tb(const void* psi, int NS, bool half, int split, int64_t x0, int cs,
                            void* scratch, const int* se, uint32_t pref, hipStream_t st) {
@@ -1465,6 +1519,7 @@ hipError_t launch_pass1(const void* psi, int N, int slab, int split, int64_t x0,
     int NS, L;
     slab_geometry<Real>(N, slab, &NS, &L);
     if (slab != kSlabFull && x0 < ((int64_t)1 << L)) return hipErrorInvalidValue;
+    if (slab == kSlabPairs && x0 < pair_first_shift<Real>(N, split)) return hipErrorInvalidValue;
     constexpr int HMAX = pass2_max_rows<Real>();
     const uint32_t pref =
         slab == kSlabPairs
@@ -1484,6 +1539,7 @@ hipError_t launch_pass2(const void* scratch, int N, int slab, int split, int64_t
         return hipErrorInvalidValue;
     int NS, L;
     slab_geometry<Real>(N, slab, &NS, &L);
+    if (slab == kSlabPairs && x0 < pair_first_shift<Real>(N, split)) return hipErrorInvalidValue;
     const bool herm = slab == kSlabHerm;
     if (slab == kSlabPairs) NS = N;  // the kernel takes the full slab's bits
     const int HT = NS - L;

@@ -30,6 +30,13 @@ template hipError_t launch_shift_kernel<float>(const void*, int, bool, int, int6
 template hipError_t launch_shift_kernel<double>(const void*, int, bool, int, int64_t, int64_t,
                                                 double*, const int*, const Pack&, const Spec*,
                                                 hipStream_t);
+// the host rule without the plans: row pairs from 2^L
+template <typename Real>
+int64_t pair_first_shift(int N, int) {
+    return (int64_t)1 << pass1_row_bits<Real>(N);
+}
+template int64_t pair_first_shift<float>(int, int);
+template int64_t pair_first_shift<double>(int, int);
 template hipError_t launch_pass1<float>(const void*, int, int, int, int64_t, int, void*,
                                         const int*, hipStream_t);
 template hipError_t launch_pass1<double>(const void*, int, int, int, int64_t, int, void*,

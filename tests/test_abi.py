@@ -237,3 +237,22 @@ def test_row_pairs_setting_sets_the_chunk_shape():
         assert ctx.chunking(22, "fp32h")[0] == cs_h
     finally:
         ctx.close()
+
+
+def test_half_slab_first_shift():
+    """Where the half slabs start (host-only): 2^L for the row pairs and the
+    Hermitian pair at N = 20, 2^(L + 5) for the FP32 row pairs at N = 22 and
+    24 (half-LDS pass-2 tiles whose lowest register row bit is row bit 5),
+    2^N for fused sizes and -1 for bad arguments."""
+    L = sre2.lib()
+    assert sre2.half_slab_first_shift(20, "fp32") == 1 << 12
+    assert sre2.half_slab_first_shift(20, "fp32h") == 1 << 12
+    assert sre2.half_slab_first_shift(20, "fp64") == 1 << 11
+    assert sre2.half_slab_first_shift(22, "fp32") == 1 << 17
+    assert sre2.half_slab_first_shift(24, "fp32") == 1 << 19
+    assert sre2.half_slab_first_shift(14, "fp32") == 1 << 14
+    assert L.sre2_half_slab_first_shift(0, sre2.FORMS["fp32"]) == -1
+    for N in range(15, 25):
+        for form in ("fp32", "split16", "fp32h"):
+            f = sre2.half_slab_first_shift(N, form)
+            assert (1 << sre2.row_bits(N, form)) <= f < (1 << N) and f & (f - 1) == 0
