@@ -283,6 +283,31 @@ def test_row_pairs_split_forms_within_rounding(oracle_mod, form, N):
         off.close()
 
 
+@pytest.mark.parametrize("form,N", [("fp32", 22), ("fp32", 23), ("fp64", 21), ("fp64", 22)])
+def test_row_pairs_start_of_large_tiles(oracle_mod, form, N):
+    """Where the half-LDS pass-2 tiles take row pairs only from
+    2^(L + 5) on (sre2_half_slab_first_shift): shifts on both sides of that
+    boundary, bit for bit the full slab's S_x and within the oracle's bar."""
+    c128 = is64(form)
+    psi_np = W.haar(N, 700 + N, np.complex128 if c128 else np.complex64)
+    psi = dev(psi_np)
+    first = sre2.half_slab_first_shift(N, form)
+    assert first > 1 << sre2.row_bits(N, form)
+    x0, xc = first - 3, 7
+    case_id("row-pairs-start", form, N, first)
+    on, off = sre2.Context(0), sre2.Context(0)
+    off.set_row_pairs(False)
+    try:
+        a = sre2.shift_partials(psi, x0, xc, form=form, ctx=on).cpu().numpy()
+        b = sre2.shift_partials(psi, x0, xc, form=form, ctx=off).cpu().numpy()
+        assert np.array_equal(a, b)
+        ref = oracle_mod.partials(psi_np, np.arange(x0, x0 + xc)[[0, 3, 6]])
+        assert np.max(np.abs(a[[0, 3, 6]] - ref) / ref) <= TOL_SX[form]
+    finally:
+        on.close()
+        off.close()
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp64"])
 @pytest.mark.parametrize("N", [22, 24])
 def test_row_pairs_bitwise_large_chunk(form, N):
